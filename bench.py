@@ -1,0 +1,135 @@
+#!/usr/bin/env python3
+"""Benchmark: trajectory-steps/s and Krotov iterations/s on one MI355X.
+
+One benchmark step is one Krotov iteration of the whole hot path: the costate
+(backward) pass with the current pulses, the sequential forward pass with the
+per-step cross-trajectory reduction and pulse update, and the functional.
+A Krotov iteration advances 2 M nt trajectory-steps.  Inputs are synthetic
+(seeded cascade-network workloads) and resident on the GPU before timing.
+
+Default workload: chain of 2 nodes, cavity at 3 Fock levels (d = 81),
+M = 1024 trajectories, nt = 2000 steps on T = 50, complex128.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3}  # published MI355X vector peaks, TFLOP/s
+
+
+def cpu_baseline(name: str, M_sub: int, nt: int) -> dict:
+    """The FP64 oracle timed on this host for one Krotov iteration (bounded sample)."""
+    import numpy as np
+    from oracle import krotov as ok
+    from oracle.mcwf import System
+    from workloads import config_workload
+    from threadpoolctl import threadpool_limits
+    # one BLAS thread: on these small dense matrices more threads only slow it down
+    limiter = threadpool_limits(limits=1)
+    blas_threads = 1
+    w = config_workload(name, M=M_sub, nt=nt)
+    sysd = System.from_sparse(w.H0, w.H_ctrl, w.L_jump)
+    fw = ok.plain_forward(sysd, w.psi0, w.psi_tgt, w.u0, w.T, M_sub, w.seed, 0)
+    t0 = time.perf_counter()
+    chi, _ = ok.costates(sysd, w.psi_tgt, fw.tau, w.u0, w.T, M_sub, w.seed, 1)
+    ok.sequential_forward(sysd, w.psi0, w.psi_tgt, w.u0, chi, w.S, w.lam, w.T, M_sub,
+                          w.seed, 1)
+    el = time.perf_counter() - t0
+    limiter.restore_original_limits()
+    cores = len(os.sched_getaffinity(0))
+    return {"value": 2.0 * M_sub * nt / el, "unit": "trajectory-steps/s",
+            "cores": blas_threads,
+            "kind": "oracle",
+            "sample": f"one Krotov iteration (backward + sequential forward) of {name} with "
+                      f"M={M_sub} of the workload's trajectories, full nt={nt}; "
+                      f"{el:.1f} s; host cores {cores}, BLAS threads {blas_threads}"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="chain2_fock3")
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32"])
+    ap.add_argument("--M", type=int, default=None)
+    ap.add_argument("--nt", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=8)
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the method "
+              "shards across GPUs by trajectories, which this build does not run.",
+              file=sys.stderr)
+        return 2
+
+    from paper_1801_04382_amd import trajkrotov as tk
+    from workloads import CONFIGS, config_workload
+
+    w = config_workload(args.workload, M=args.M, nt=args.nt)
+    prec = args.precision or CONFIGS[args.workload]["precision"]
+    ctx = tk.Context(precision=prec)
+    ctx.load(w)
+    # warm-up: the guess forward pass (iteration 0) and W Krotov iterations
+    J0, _, _ = ctx.krotov_iterate(w.M, w.seed, args.warmup, rec_cap=0)
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    J, _, _ = ctx.krotov_iterate(w.M, w.seed, args.steps, first_iteration=args.warmup + 1,
+                                 rec_cap=0)
+    elapsed = time.perf_counter() - t0
+    ctx.set_timing(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    traj_steps = 2.0 * w.M * w.nt
+    kernels = {}
+    for kind, name in [(tk.TK_KERNEL_BACKWARD, "backward"), (tk.TK_KERNEL_KROTOV, "krotov"),
+                       (tk.TK_KERNEL_FORWARD, "forward")]:
+        t = ctx.timing(kind)
+        if t["launches"]:
+            avg_ms = t["ms_total"] / t["launches"]
+            kernels[name] = {"avg_ms": avg_ms, "launches": t["launches"],
+                             "tflops": t["flops"] / t["launches"] / (avg_ms * 1e-3) / 1e12,
+                             "gbs": t["bytes"] / t["launches"] / (avg_ms * 1e-3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    kd = kernels[dom]
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(kd["tflops"], 4),
+                "peak": PEAK[prec], "unit": "TFLOP/s",
+                "frac": round(kd["tflops"] / PEAK[prec], 5), "traffic": None,
+                "hbm_gbs": round(kd["gbs"], 2)}
+    info = ctx.launch_info()
+    out = {
+        "metric": "trajectory-steps/s + Krotov iters/s (FP32 batched vs FP64 plain) at "
+                  "|dJ_T|<=1e-4",
+        "value": traj_steps / (ms_per_step * 1e-3),
+        "unit": "trajectory-steps/s",
+        "krotov_iters_per_s": 1e3 / ms_per_step,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "d": w.dim, "M": w.M, "nt": w.nt, "T": w.T,
+                   "precision": prec, "variant": info["variant"],
+                   "krotov_blocks": info["blocks"], "traj_per_wave": info["traj_per_wave"]},
+        "J_T_last": float(J[-1]),
+        "kernels": {k: {kk: round(vv, 5) if isinstance(vv, float) else vv
+                        for kk, vv in v.items()} for k, v in kernels.items()},
+        "roofline": roofline,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, w.nt)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,245 @@
+/*
+ * trajkrotov -- trajectory-parallel Krotov optimisation on one AMD MI355X.
+ *
+ * C ABI of the library.  It implements, on the GPU, the hot path of
+ * Goerz & Jacobs, "Efficient optimization of state preparation in quantum
+ * networks using quantum trajectories":
+ *
+ *   - Monte-Carlo wave-function (quantum jump) trajectories under the
+ *     non-Hermitian effective Hamiltonian, with jump times located inside a
+ *     time step (Sec. 2.1, the MCWF algorithm and the paragraph after it);
+ *   - costates propagated backward from the trajectory functional's boundary
+ *     condition (Sec. 2.3);
+ *   - the per-time-step cross-trajectory reduction
+ *     s_ij = sum_k Im <chi_k(t_j)| H_i |Psi_k(t_j)>  and the sequential,
+ *     independent-trajectory Krotov pulse update (Sec. 2.2 "sequential" and
+ *     Sec. 2.3, the independent-trajectory update);
+ *   - the trajectory functional J_T = 1 - (1/M) sum_k |tau_k|^2 (Sec. 2.3).
+ *
+ * Problem statement (Sec. 2.1): H(t) = H0 + sum_i u_i(t) H_i with real,
+ * piecewise-constant controls u_ij on the intervals (t_j, t_{j+1}] of a grid
+ * t_j = j T / nt, and Lindblad operators {L_l}.  The library forms
+ *     H_eff = H0 + sum_i u_i H_i - (i/2) sum_l L_l^+ L_l
+ * itself (MCWF step 1, with the anti-Hermitian factor -i/2).
+ *
+ * Conventions (all entry points):
+ *   - Every function returns an int status (TK_OK = 0, negative = error) and
+ *     never throws across the ABI; tk_last_error() describes the last error.
+ *   - All pointer arguments are HOST pointers.  Inputs are copied during the
+ *     call (the caller may free them on return); outputs are caller-allocated
+ *     and written before the call returns.  Calls are synchronous.
+ *   - Complex numbers are interleaved (re, im) doubles: a complex vector of
+ *     length n is a double array of length 2n.
+ *   - Time steps are 0-based: step j is the interval (j dt, (j+1) dt], dt = T/nt.
+ *   - One context per host thread; a context owns all of its device memory.
+ *   - Random numbers: Philox4x64-10 (Salmon et al., SC'11).  Block n of
+ *     trajectory k uses counter [n, iteration, direction, 0] and key
+ *     [seed, (instance << 32) | k]; word 0 is the norm threshold of waiting
+ *     period n, word 1 picks the operator of the jump that ends it; a word w
+ *     maps to (w >> 11) * 2^-53.  A trajectory's record therefore does not
+ *     depend on M, on the launch configuration or on other trajectories.
+ */
+#ifndef TRAJKROTOV_H
+#define TRAJKROTOV_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define TK_API __attribute__((visibility("default")))
+#else
+#define TK_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum tk_status {
+  TK_OK = 0,
+  TK_EINVAL = -1,       /* invalid argument (shape, NULL, NaN, not normalised) */
+  TK_EDIM = -2,         /* dimension mismatch between arguments               */
+  TK_ENOMEM = -3,       /* device or host allocation failed                   */
+  TK_EHIP = -4,         /* HIP runtime error, or a kernel reported a fault     */
+  TK_ENOTHERM = -5,     /* H0 or a control Hamiltonian is not Hermitian        */
+  TK_ERECCAP = -6,      /* jump-record buffer too small; *n_rec = count needed */
+  TK_ENUMERIC = -7,     /* numerical failure (jump with all ||L_l psi|| = 0,
+                           step too long for the polynomial propagator)        */
+  TK_ESTATE = -8,       /* call order violated (e.g. no system set)           */
+  TK_ENODEV = -9,       /* no usable gfx950 device                            */
+  TK_EUNSUPPORTED = -10 /* problem shape outside the compiled kernel variants */
+};
+
+/* ---- precision of the bulk propagation -------------------------------- */
+enum tk_precision {
+  TK_FP64 = 0, /* complex128 states and operators                         */
+  TK_FP32 = 1  /* complex64 states and operators; norms, jump tests,
+                  overlaps and the Krotov reduction stay in FP64           */
+};
+
+/* ---- data types --------------------------------------------------------- */
+
+/* Square sparse matrix in CSR form, complex128 values (host memory). */
+typedef struct tk_csr {
+  int64_t n_rows;          /* = number of columns = Hilbert dimension d     */
+  int64_t nnz;
+  const int64_t *indptr;   /* [n_rows + 1], indptr[0] = 0, non-decreasing   */
+  const int32_t *indices;  /* [nnz] column indices in [0, n_rows)           */
+  const double *values;    /* [2 * nnz] interleaved (re, im)                 */
+} tk_csr;
+
+/* One quantum jump (MCWF step 4) as recorded by a propagation pass. */
+typedef struct tk_jump {
+  int32_t instance;   /* optimisation instance (0 for single-system calls) */
+  int32_t traj;       /* trajectory index k                                 */
+  int32_t step;       /* 0-based time step containing the jump              */
+  int32_t op;         /* index l of the jump operator applied               */
+  int32_t ordinal;    /* n: jumps of this trajectory earlier in this pass   */
+  int32_t direction;  /* 0 forward, 1 backward (costate)                    */
+  int32_t iteration;  /* Krotov iteration of the pass                       */
+  int32_t reserved;
+  double t;           /* jump time                                          */
+} tk_jump;
+
+/* Per-kernel timing accumulated since the last tk_reset_timing(). */
+typedef struct tk_kernel_timing {
+  double ms_total;    /* sum of HIP-event durations of the launches          */
+  int64_t launches;
+  double flops;       /* algorithmic flops of those launches (see below)    */
+  double bytes;       /* algorithmic HBM bytes of those launches            */
+  int64_t traj_steps; /* trajectory-steps advanced by those launches        */
+} tk_kernel_timing;
+
+enum tk_kernel_kind {
+  TK_KERNEL_FORWARD = 0,   /* plain forward pass (iteration 0, functional) */
+  TK_KERNEL_BACKWARD = 1,  /* costate pass                                  */
+  TK_KERNEL_KROTOV = 2,    /* sequential forward pass with pulse update     */
+  TK_KERNEL_COUNT = 3
+};
+
+typedef struct tk_ctx tk_ctx; /* opaque */
+
+/* ---- lifecycle ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` computing in `precision`.
+ * Errors: TK_EINVAL (bad precision), TK_ENODEV (no such device / not gfx950),
+ * TK_ENOMEM.  On error *out is NULL. */
+TK_API int tk_create(tk_ctx **out, int device, int precision);
+
+/* Free the context and all device memory it owns (NULL is accepted). */
+TK_API void tk_destroy(tk_ctx *ctx);
+
+/* Text of the last error on this context (owned by ctx; valid until the next
+ * call on it).  Returns a static string for a NULL ctx. */
+TK_API const char *tk_last_error(const tk_ctx *ctx);
+
+/* Version string of the library (static storage). */
+TK_API const char *tk_version(void);
+
+/* ---- problem definition -------------------------------------------------- */
+
+/* Define H0, the n_ctrl control Hamiltonians H_ctrl[i] and the n_jump
+ * Lindblad operators L_jump[l] (Sec. 2.1), all d x d.  H0 and each H_ctrl[i]
+ * must be Hermitian (max |H - H^+| <= 1e-12 max |H|), else TK_ENOTHERM.
+ * Limits: 1 <= d; 0 <= n_ctrl <= 8; 0 <= n_jump <= 8.  Invalidates pulses,
+ * states and stored costates.  Errors: TK_EINVAL, TK_EDIM, TK_ENOTHERM,
+ * TK_EUNSUPPORTED (no compiled kernel variant fits the sparsity), TK_ENOMEM. */
+TK_API int tk_set_system(tk_ctx *ctx, int64_t d, const tk_csr *H0, int32_t n_ctrl,
+                  const tk_csr *H_ctrl, int32_t n_jump, const tk_csr *L_jump);
+
+/* Initial state Psi(0) and target Psi_tgt (Sec. 2.1), each [2d].  psi0 must be
+ * normalised to 1e-10; the target is normalised by the library (it must be
+ * non-zero).  Errors: TK_ESTATE (no system), TK_EINVAL. */
+TK_API int tk_set_states(tk_ctx *ctx, const double *psi0, const double *psi_tgt);
+
+/* Pulses: nt steps on [0, T]; u [n_ctrl * nt] row-major (control i, step j at
+ * u[i * nt + j]); S [n_ctrl * nt] update shape in [0, 1] (NULL means 1);
+ * lambda [n_ctrl] Krotov weights > 0 (NULL means 1) (Sec. 2.2, the extended
+ * functional).  Invalidates stored costates and functional values.
+ * Errors: TK_ESTATE, TK_EINVAL (nt < 1, T <= 0, non-finite, lambda <= 0). */
+TK_API int tk_set_pulses(tk_ctx *ctx, int32_t nt, double T, const double *u,
+                  const double *S, const double *lambda);
+
+/* Current pulses (after tk_krotov_iterate they are the optimised ones),
+ * u_out [n_ctrl * nt].  Errors: TK_ESTATE. */
+TK_API int tk_get_pulses(const tk_ctx *ctx, double *u_out);
+
+/* ---- propagation --------------------------------------------------------- */
+
+/* Forward pass of M trajectories from psi0 with the current pulses
+ * (MCWF, Sec. 2.1), random streams (seed, iteration, direction 0).
+ * Outputs (each may be NULL): psiT_out [M * 2d] normalised final states;
+ * tau_out [2M] overlaps tau_k = <Psi_tgt|Psi_k(T)>; rec [cap] jump records
+ * in unspecified order, *n_rec = number of jumps (if larger than cap,
+ * returns TK_ERECCAP after writing cap records).  The overlaps are kept in
+ * the context as the boundary condition of the next backward pass.
+ * Errors: TK_ESTATE, TK_EINVAL (M < 1), TK_ENOMEM, TK_ENUMERIC, TK_EHIP,
+ * TK_ERECCAP. */
+TK_API int tk_propagate_forward(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t iteration,
+                         double *psiT_out, double *tau_out, tk_jump *rec,
+                         int64_t cap, int64_t *n_rec);
+
+/* Backward (costate) pass: each trajectory starts from the normalised target
+ * and runs the MCWF rules in reverse time with exp(+i H_eff^+ tau) and an
+ * independent stream (seed, iteration, direction 1).  The costate stored for
+ * time t_j is chi_k(t_j) = tau_k chi_hat_k(t_j) (Sec. 2.3: boundary condition
+ * chi_k(T) = tau_k Psi_tgt), j = 0 .. nt-1, kept in device memory
+ * ([nt][M][d], bulk precision) for tk_get_costate and the next Krotov pass.
+ * tau [2M]: overlaps from the previous forward pass; NULL uses the ones kept
+ * by the last forward pass (same M).  Records as in tk_propagate_forward.
+ * Errors: TK_ESTATE, TK_EINVAL, TK_ENOMEM, TK_ENUMERIC, TK_EHIP, TK_ERECCAP. */
+TK_API int tk_propagate_backward(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t iteration,
+                          const double *tau, tk_jump *rec, int64_t cap,
+                          int64_t *n_rec);
+
+/* Copy the stored costates at time t_j, chi_out [M * 2d] (complex128).
+ * Errors: TK_ESTATE (no costates stored), TK_EINVAL (j out of range). */
+TK_API int tk_get_costate(const tk_ctx *ctx, int32_t j, double *chi_out);
+
+/* Trajectory functional J_T = 1 - (1/M) sum_k |tau_k|^2 (Sec. 2.3) of the
+ * current pulses: one forward pass (seed, iteration).  tau_out [2M] may be
+ * NULL.  Errors: as tk_propagate_forward. */
+TK_API int tk_functional(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t iteration,
+                  double *J_T, double *tau_out);
+
+/* ---- optimisation -------------------------------------------------------- */
+
+/* Krotov iterations (Sec. 2.2 and 2.3).  With first_iteration = 0, runs the
+ * guess forward pass (iteration 0) and writes J_T_out[0], then iterations
+ * 1..n_iter into J_T_out[1..n_iter] (n_iter + 1 values).  With
+ * first_iteration = n0 >= 1, continues from the overlaps kept by the forward
+ * pass of iteration n0-1 (same M and seed, else TK_ESTATE) and writes n_iter
+ * values for iterations n0 .. n0+n_iter-1.  Iteration n = backward pass with
+ * u^(n-1) (stream iteration n, direction 1), then the sequential forward pass
+ * (iteration n, direction 0) which, at every step j, reduces
+ *   s_ij = sum_k Im <chi_k(t_j)| H_i |Psi_hat_k(t_j)>   (FP64, fixed order)
+ * and sets u_ij = u_ij + S_ij s_ij / (lambda_i M) before propagating step j.
+ * The context's pulses are updated in place.  Records of all passes go to
+ * rec (may be NULL).  Errors: as the propagation calls. */
+TK_API int tk_krotov_iterate(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t first_iteration,
+                      int32_t n_iter, double *J_T_out, tk_jump *rec, int64_t cap,
+                      int64_t *n_rec);
+
+/* ---- instrumentation ------------------------------------------------------ */
+
+/* Enable (1) or disable (0) HIP-event timing of every kernel launch. */
+TK_API int tk_set_timing(tk_ctx *ctx, int enable);
+
+/* Accumulated timing of kernel kind `kind` (tk_kernel_kind).  flops and bytes
+ * are algorithmic: per trajectory-step 8 K nnz + 8 K d + 4 d real flops
+ * (K Taylor terms of the step, nnz stored non-zeros of H_eff) and the costate
+ * bytes the method must move (written once backward, read once forward). */
+TK_API int tk_get_timing(const tk_ctx *ctx, int kind, tk_kernel_timing *out);
+TK_API int tk_reset_timing(tk_ctx *ctx);
+
+/* Description of the kernel variant selected for the current system (static
+ * string per variant, e.g. "fp64 R=2 WS=4 NC=2"), and the launch shape of the
+ * last Krotov pass: waves per block, trajectories per wave, blocks. */
+TK_API int tk_get_launch_info(const tk_ctx *ctx, const char **variant, int32_t *waves_per_block,
+                       int32_t *traj_per_wave, int32_t *blocks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRAJKROTOV_H */

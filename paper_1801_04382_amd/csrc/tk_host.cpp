@@ -1,0 +1,1026 @@
+// Host side of libtrajkrotov: validation, operator packing, device memory,
+// kernel launches and the Krotov iteration driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "tk_internal.h"
+
+namespace {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// host sparse matrices
+// ---------------------------------------------------------------------------
+struct Csr {
+  int64_t n = 0;
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> idx;
+  std::vector<cd> val;
+  int64_t nnz() const { return static_cast<int64_t>(idx.size()); }
+  int max_row() const {
+    int64_t w = 0;
+    for (int64_t r = 0; r < n; ++r) w = std::max(w, ptr[r + 1] - ptr[r]);
+    return static_cast<int>(w);
+  }
+};
+
+// dense-row accumulation helper (d is small enough for per-row scatter)
+struct RowAcc {
+  std::vector<cd> acc;
+  std::vector<int32_t> cols;
+  std::vector<char> used;
+  explicit RowAcc(int64_t n) : acc(n), used(n, 0) {}
+  void add(int32_t c, cd v) {
+    if (!used[c]) {
+      used[c] = 1;
+      cols.push_back(c);
+      acc[c] = 0;
+    }
+    acc[c] += v;
+  }
+  void flush(Csr &out) {
+    std::sort(cols.begin(), cols.end());
+    for (int32_t c : cols) {
+      if (acc[c] != cd(0.0, 0.0)) {
+        out.idx.push_back(c);
+        out.val.push_back(acc[c]);
+      }
+      used[c] = 0;
+    }
+    cols.clear();
+    out.ptr.push_back(out.nnz());
+  }
+};
+
+Csr adjoint(const Csr &a) {
+  Csr t;
+  t.n = a.n;
+  std::vector<int64_t> cnt(a.n + 1, 0);
+  for (int32_t c : a.idx) cnt[c + 1]++;
+  for (int64_t r = 0; r < a.n; ++r) cnt[r + 1] += cnt[r];
+  t.ptr = cnt;
+  t.idx.resize(a.nnz());
+  t.val.resize(a.nnz());
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t r = 0; r < a.n; ++r)
+    for (int64_t p = a.ptr[r]; p < a.ptr[r + 1]; ++p) {
+      const int32_t c = a.idx[p];
+      t.idx[pos[c]] = static_cast<int32_t>(r);
+      t.val[pos[c]] = std::conj(a.val[p]);
+      pos[c]++;
+    }
+  return t;
+}
+
+// c = a + alpha * b
+Csr axpy(const Csr &a, cd alpha, const Csr &b) {
+  Csr c;
+  c.n = a.n;
+  c.ptr.push_back(0);
+  RowAcc row(a.n);
+  for (int64_t r = 0; r < a.n; ++r) {
+    for (int64_t p = a.ptr[r]; p < a.ptr[r + 1]; ++p) row.add(a.idx[p], a.val[p]);
+    for (int64_t p = b.ptr[r]; p < b.ptr[r + 1]; ++p) row.add(b.idx[p], alpha * b.val[p]);
+    row.flush(c);
+  }
+  return c;
+}
+
+// c = a * b
+Csr multiply(const Csr &a, const Csr &b) {
+  Csr c;
+  c.n = a.n;
+  c.ptr.push_back(0);
+  RowAcc row(a.n);
+  for (int64_t r = 0; r < a.n; ++r) {
+    for (int64_t p = a.ptr[r]; p < a.ptr[r + 1]; ++p) {
+      const int32_t k = a.idx[p];
+      for (int64_t q = b.ptr[k]; q < b.ptr[k + 1]; ++q) row.add(b.idx[q], a.val[p] * b.val[q]);
+    }
+    row.flush(c);
+  }
+  return c;
+}
+
+
+// ||A||_2 <= sqrt(||A||_1 ||A||_inf)
+double norm2_bound(const Csr &a) {
+  std::vector<double> col(a.n, 0.0);
+  double rmax = 0.0;
+  for (int64_t r = 0; r < a.n; ++r) {
+    double rs = 0.0;
+    for (int64_t p = a.ptr[r]; p < a.ptr[r + 1]; ++p) {
+      rs += std::abs(a.val[p]);
+      col[a.idx[p]] += std::abs(a.val[p]);
+    }
+    rmax = std::max(rmax, rs);
+  }
+  double cmax = 0.0;
+  for (double v : col) cmax = std::max(cmax, v);
+  return std::sqrt(rmax * cmax);
+}
+
+// y = A x (dense vector)
+void spmv(const Csr &a, const std::vector<cd> &x, std::vector<cd> &y) {
+  y.assign(a.n, cd(0.0, 0.0));
+  for (int64_t r = 0; r < a.n; ++r) {
+    cd s(0.0, 0.0);
+    for (int64_t p = a.ptr[r]; p < a.ptr[r + 1]; ++p) s += a.val[p] * x[a.idx[p]];
+    y[r] = s;
+  }
+}
+
+// Estimate of ||A||_2 by power iteration on A^+ A (from below), inflated by 5%
+// and never above the rigorous bound sqrt(||A||_1 ||A||_inf).
+double norm2_estimate(const Csr &a) {
+  const double rigorous = norm2_bound(a);
+  if (a.nnz() == 0) return 0.0;
+  const Csr ad = adjoint(a);
+  std::vector<cd> x(a.n), y, z;
+  for (int64_t i = 0; i < a.n; ++i) x[i] = cd(1.0 + 0.001 * (i % 7), 0.01 * (i % 3));
+  double lam = 0.0;
+  for (int it = 0; it < 300; ++it) {
+    double nx = 0.0;
+    for (const cd &v : x) nx += std::norm(v);
+    nx = std::sqrt(nx);
+    if (!(nx > 0.0)) break;
+    for (cd &v : x) v /= nx;
+    spmv(a, x, y);
+    spmv(ad, y, z);
+    double rq = 0.0;
+    for (int64_t i = 0; i < a.n; ++i) rq += std::real(std::conj(x[i]) * z[i]);
+    lam = std::sqrt(std::max(rq, 0.0));
+    x.swap(z);
+  }
+  return std::min(1.05 * lam, rigorous);
+}
+
+double max_abs(const Csr &a) {
+  double m = 0.0;
+  for (const cd &v : a.val) m = std::max(m, std::abs(v));
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    if (n == 0) n = 8;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = n;
+    return hipSuccess;
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+struct Ell {  // packed per-lane slices of one operator group
+  std::vector<int32_t> col;
+  std::vector<double> val;  // interleaved complex, FP64 (converted on upload)
+};
+
+}  // namespace
+
+struct tk_ctx {
+  int device = 0;
+  int precision = TK_FP64;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int n_cu = 0;
+
+  bool has_system = false, has_states = false, has_pulses = false;
+  int64_t d = 0;
+  int n_ctrl = 0, n_jump = 0;
+  const tk::Variant *var = nullptr;
+  int wc = 1, wl = 1;
+  double b0 = 0.0;
+  double bc[tk::kMaxCtrl] = {};
+  int64_t nnz_heff = 0;
+  std::vector<Csr> H_ctrl_host;
+
+  DevBuf f_scol, f_sval, f_ccol, f_cval, b_scol, b_sval, b_ccol, b_cval, lcol, lval;
+  DevBuf psi0_bulk, tgt_bulk, tgt64;
+
+  int nt = 0;
+  double T = 0.0;
+  std::vector<double> u, S, lam;
+  DevBuf u_dev, u_new_dev, S_dev, lam_dev;
+
+  DevBuf chi, tau, psiT, slots, rec, rec_count, err_dev, jt_dev;
+  int chi_M = -1;
+  int tau_M = -1;
+  uint64_t tau_seed = 0;
+  int64_t tau_iter = -1;
+
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  tk_kernel_timing tstat[TK_KERNEL_COUNT] = {};
+  int last_wpb = 0, last_tw = 0, last_blocks = 0;
+
+  size_t bulk_cplx() const { return precision == TK_FP64 ? 16 : 8; }
+};
+
+namespace {
+
+int fail(tk_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(tk_ctx *c, hipError_t e, const char *what) {
+  return fail(c, e == hipErrorOutOfMemory ? TK_ENOMEM : TK_EHIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define TK_HIP(ctx, call)                               \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+int read_csr(tk_ctx *c, const tk_csr *m, int64_t d, const char *name, Csr &out) {
+  if (!m) return fail(c, TK_EINVAL, std::string(name) + " is NULL");
+  if (m->n_rows != d) return fail(c, TK_EDIM, std::string(name) + " has the wrong dimension");
+  if (m->nnz < 0 || (m->nnz > 0 && (!m->indices || !m->values)) || !m->indptr)
+    return fail(c, TK_EINVAL, std::string(name) + ": missing arrays");
+  if (m->indptr[0] != 0 || m->indptr[d] != m->nnz)
+    return fail(c, TK_EINVAL, std::string(name) + ": indptr does not span nnz");
+  out.n = d;
+  out.ptr.assign(m->indptr, m->indptr + d + 1);
+  for (int64_t r = 0; r < d; ++r)
+    if (out.ptr[r + 1] < out.ptr[r])
+      return fail(c, TK_EINVAL, std::string(name) + ": indptr decreases");
+  // merge duplicates / drop zeros through a row accumulator
+  Csr clean;
+  clean.n = d;
+  clean.ptr.push_back(0);
+  RowAcc row(d);
+  for (int64_t r = 0; r < d; ++r) {
+    for (int64_t p = out.ptr[r]; p < out.ptr[r + 1]; ++p) {
+      const int32_t col = m->indices[p];
+      const double re = m->values[2 * p], im = m->values[2 * p + 1];
+      if (col < 0 || col >= d) return fail(c, TK_EINVAL, std::string(name) + ": column out of range");
+      if (!std::isfinite(re) || !std::isfinite(im))
+        return fail(c, TK_EINVAL, std::string(name) + ": non-finite value");
+      row.add(col, cd(re, im));
+    }
+    row.flush(clean);
+  }
+  out = std::move(clean);
+  return TK_OK;
+}
+
+bool hermitian(const Csr &h) {
+  const Csr diff = axpy(h, cd(-1.0, 0.0), adjoint(h));
+  return max_abs(diff) <= 1e-12 * std::max(max_abs(h), 1e-300);
+}
+
+// Per-lane slot layout of one operator `a` (may be null = all padding) in W
+// slots starting at slot index `first` of an array laid out [slot][m][lane]
+// (row r = lane + 64 m).  Each row's non-zeros are dealt to the slots; a slot
+// a row does not use points at `dummy`, a zero element every lane may read at
+// once (a broadcast).  Which non-zero goes to which slot is free, so for every
+// slot and every 16-lane group the entries are chosen greedily to spread the
+// gathered elements over the LDS bank groups (element c lies in group
+// c mod n_bank_groups), which keeps the gathers of one instruction from
+// colliding in the same banks.
+void pack_group(const Csr *a, int W, int first, int R, int n_bank_groups, int32_t dummy,
+                std::vector<int32_t> &col, std::vector<double> &val) {
+  const int lanes = tk::kWave;
+  std::vector<std::vector<std::pair<int32_t, cd>>> left(static_cast<size_t>(R) * lanes);
+  for (int m = 0; m < R; ++m)
+    for (int lane = 0; lane < lanes; ++lane) {
+      const int64_t row = lane + static_cast<int64_t>(lanes) * m;
+      auto &l = left[static_cast<size_t>(m) * lanes + lane];
+      if (a && row < a->n)
+        for (int64_t p = a->ptr[row]; p < a->ptr[row + 1]; ++p) l.push_back({a->idx[p], a->val[p]});
+    }
+  std::vector<int> load(n_bank_groups);
+  for (int w = 0; w < W; ++w)
+    for (int m = 0; m < R; ++m)
+      for (int g0 = 0; g0 < lanes; g0 += 16) {
+        std::fill(load.begin(), load.end(), 0);
+        bool dummy_used = false;
+        for (int lane = g0; lane < g0 + 16; ++lane) {
+          auto &l = left[static_cast<size_t>(m) * lanes + lane];
+          const size_t slot = (static_cast<size_t>(first + w) * R + m) * lanes + lane;
+          if (l.empty()) {
+            col[slot] = dummy;
+            val[2 * slot] = val[2 * slot + 1] = 0.0;
+            if (!dummy_used) load[dummy % n_bank_groups]++;
+            dummy_used = true;
+            continue;
+          }
+          size_t best = 0;
+          for (size_t q = 1; q < l.size(); ++q) {
+            const int lb = load[l[best].first % n_bank_groups], lq = load[l[q].first % n_bank_groups];
+            if (lq < lb || (lq == lb && l[q].first < l[best].first)) best = q;
+          }
+          col[slot] = l[best].first;
+          val[2 * slot] = l[best].second.real();
+          val[2 * slot + 1] = l[best].second.imag();
+          load[l[best].first % n_bank_groups]++;
+          l.erase(l.begin() + static_cast<long>(best));
+        }
+      }
+}
+
+// Operators ops[g], each in W slots: layout [g][w][m][lane].
+void pack(const std::vector<const Csr *> &ops, int W, int R, int n_bank_groups, Ell &out) {
+  const size_t n = ops.size() * static_cast<size_t>(W) * R * tk::kWave;
+  out.col.assign(n, 0);
+  out.val.assign(2 * n, 0.0);
+  const int32_t dummy = R * tk::kWave;
+  for (size_t g = 0; g < ops.size(); ++g)
+    pack_group(ops[g], W, static_cast<int>(g) * W, R, n_bank_groups, dummy, out.col, out.val);
+}
+
+// Control operators: slots c = i * wc .. i * wc + wc - 1 hold H_i; slots past
+// n_ctrl * wc are padding.
+void pack_ctrl(const std::vector<Csr> &H, int wc, int NC, int R, int n_bank_groups, Ell &out) {
+  const size_t n = static_cast<size_t>(NC) * R * tk::kWave;
+  out.col.assign(n, 0);
+  out.val.assign(2 * n, 0.0);
+  const int32_t dummy = R * tk::kWave;
+  for (int i = 0; i * wc < NC; ++i) {
+    const Csr *a = i < static_cast<int>(H.size()) ? &H[i] : nullptr;
+    pack_group(a, std::min(wc, NC - i * wc), i * wc, R, n_bank_groups, dummy, out.col, out.val);
+  }
+}
+
+int upload(tk_ctx *c, DevBuf &buf, const void *src, size_t bytes) {
+  TK_HIP(c, buf.ensure(bytes));
+  if (bytes) TK_HIP(c, hipMemcpy(buf.p, src, bytes, hipMemcpyHostToDevice));
+  return TK_OK;
+}
+
+int upload_ell(tk_ctx *c, const Ell &e, DevBuf &col, DevBuf &val) {
+  int rc = upload(c, col, e.col.data(), e.col.size() * sizeof(int32_t));
+  if (rc) return rc;
+  if (c->precision == TK_FP64) return upload(c, val, e.val.data(), e.val.size() * sizeof(double));
+  std::vector<float> f(e.val.begin(), e.val.end());
+  return upload(c, val, f.data(), f.size() * sizeof(float));
+}
+
+int upload_vec(tk_ctx *c, DevBuf &buf, const std::vector<double> &v) {
+  if (c->precision == TK_FP64) return upload(c, buf, v.data(), v.size() * sizeof(double));
+  std::vector<float> f(v.begin(), v.end());
+  return upload(c, buf, f.data(), f.size() * sizeof(float));
+}
+
+// Taylor order of one step (same rule as the kernels).
+int taylor_order_host(double x, double tol, int kmax) {
+  const double ex = std::exp(x);
+  double t = x;
+  for (int K = 1; K <= kmax; ++K) {
+    t *= x / static_cast<double>(K + 1);
+    if (t * ex <= tol) return K;
+  }
+  return kmax;
+}
+
+double pass_flops(const tk_ctx *c, const std::vector<double> &u, int M) {
+  double f = 0.0;
+  const double tol = c->precision == TK_FP64 ? 1e-16 : 6e-8;
+  for (int j = 0; j < c->nt; ++j) {
+    double b = c->b0;
+    for (int i = 0; i < c->n_ctrl; ++i) b += std::fabs(u[static_cast<size_t>(i) * c->nt + j]) * c->bc[i];
+    const double x = b * (c->T / c->nt);
+    const int n_sub = x > tk::kMaxStepNorm ? static_cast<int>(std::ceil(x / tk::kMaxStepNorm)) : 1;
+    const int K = taylor_order_host(x / n_sub, tol, tk::kMaxTaylor);
+    f += n_sub * (8.0 * K * c->nnz_heff + 8.0 * K * c->d + 4.0 * c->d);
+  }
+  return f * M;
+}
+
+tk::PassArgs base_args(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, bool backward) {
+  tk::PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.d = static_cast<int>(c->d);
+  a.nt = c->nt;
+  a.M = M;
+  a.n_ctrl = c->n_ctrl;
+  a.n_jump = c->n_jump;
+  a.wc = c->wc;
+  a.wl = c->wl;
+  a.kmax = tk::kMaxTaylor;
+  a.dt = c->T / c->nt;
+  a.tol = c->precision == TK_FP64 ? 1e-16 : 6e-8;
+  a.ftol = c->precision == TK_FP64 ? 4.0 * 0x1.0p-52 : 4.0 * 0x1.0p-23;
+  a.b0 = c->b0;
+  for (int i = 0; i < tk::kMaxCtrl; ++i) a.bc[i] = c->bc[i];
+  a.inv_n[0] = 0.0;
+  for (int n = 1; n <= tk::kMaxTaylor; ++n) a.inv_n[n] = 1.0 / n;
+  if (!backward) {
+    a.scol = c->f_scol.as<int>();
+    a.sval = c->f_sval.p;
+    a.ccol = c->f_ccol.as<int>();
+    a.cval = c->f_cval.p;
+    a.psi_start = c->psi0_bulk.p;
+  } else {
+    a.scol = c->b_scol.as<int>();
+    a.sval = c->b_sval.p;
+    a.ccol = c->b_ccol.as<int>();
+    a.cval = c->b_cval.p;
+    a.psi_start = c->tgt_bulk.p;
+  }
+  a.lcol = c->lcol.as<int>();
+  a.lval = c->lval.p;
+  a.u = c->u_dev.as<double>();
+  a.tgt = c->tgt64.as<double>();
+  a.seed = seed;
+  a.iteration = iteration;
+  a.instance = 0;
+  a.err = c->err_dev.as<int>();
+  a.rec_count = c->rec_count.as<unsigned long long>();
+  a.spin_limit = 1ll << 22;
+  return a;
+}
+
+int prepare_pass(tk_ctx *c, int M, int64_t cap) {
+  if (!c->has_system) return fail(c, TK_ESTATE, "no system set");
+  if (!c->has_states) return fail(c, TK_ESTATE, "no states set");
+  if (!c->has_pulses) return fail(c, TK_ESTATE, "no pulses set");
+  if (M < 1) return fail(c, TK_EINVAL, "M must be >= 1");
+  if (cap < 0) return fail(c, TK_EINVAL, "negative record capacity");
+  TK_HIP(c, c->err_dev.ensure(sizeof(int)));
+  TK_HIP(c, c->rec_count.ensure(sizeof(unsigned long long)));
+  TK_HIP(c, c->rec.ensure(std::max<int64_t>(cap, 1) * sizeof(tk_jump)));
+  TK_HIP(c, c->tau.ensure(static_cast<size_t>(2) * M * sizeof(double)));
+  TK_HIP(c, c->psiT.ensure(static_cast<size_t>(M) * c->d * c->bulk_cplx()));
+  return TK_OK;
+}
+
+int reset_counters(tk_ctx *c) {
+  TK_HIP(c, hipMemsetAsync(c->err_dev.p, 0, sizeof(int), c->stream));
+  TK_HIP(c, hipMemsetAsync(c->rec_count.p, 0, sizeof(unsigned long long), c->stream));
+  return TK_OK;
+}
+
+int check_kernel_errors(tk_ctx *c) {
+  int e = 0;
+  TK_HIP(c, hipMemcpyAsync(&e, c->err_dev.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TK_HIP(c, hipStreamSynchronize(c->stream));
+  if (e & tk::kErrSyncTimeout)
+    return fail(c, TK_EHIP, "grid-wide step reduction timed out (blocks not co-resident)");
+  if (e & tk::kErrNoJumpWeight)
+    return fail(c, TK_ENUMERIC, "jump with all ||L_l psi||^2 = 0");
+  if (e & tk::kErrTaylorOrder)
+    return fail(c, TK_ENUMERIC, "time step too long for the polynomial propagator; raise nt");
+  if (e & tk::kErrJumpLoop) return fail(c, TK_ENUMERIC, "too many jumps inside one time step");
+  return TK_OK;
+}
+
+int fetch_records(tk_ctx *c, tk_jump *rec, int64_t cap, int64_t *n_rec) {
+  unsigned long long n = 0;
+  TK_HIP(c, hipMemcpy(&n, c->rec_count.p, sizeof(n), hipMemcpyDeviceToHost));
+  if (n_rec) *n_rec = static_cast<int64_t>(n);
+  const int64_t copy = std::min<int64_t>(static_cast<int64_t>(n), cap);
+  if (rec && copy > 0)
+    TK_HIP(c, hipMemcpy(rec, c->rec.p, copy * sizeof(tk_jump), hipMemcpyDeviceToHost));
+  if (static_cast<int64_t>(n) > cap && (rec || cap > 0))
+    return fail(c, TK_ERECCAP, "jump-record buffer too small");
+  return TK_OK;
+}
+
+void to_host_cplx(const tk_ctx *c, const void *dev_copy, size_t n, double *out) {
+  if (c->precision == TK_FP64) {
+    std::memcpy(out, dev_copy, n * 16);
+  } else {
+    const float *f = static_cast<const float *>(dev_copy);
+    for (size_t i = 0; i < 2 * n; ++i) out[i] = f[i];
+  }
+}
+
+struct TimedLaunch {
+  tk_ctx *c;
+  int kind;
+  explicit TimedLaunch(tk_ctx *ctx, int k) : c(ctx), kind(k) {
+    if (c->timing) (void)hipEventRecord(c->ev0, c->stream);
+  }
+  int finish(int64_t traj_steps, double flops, double bytes) {
+    if (!c->timing) return TK_OK;
+    TK_HIP(c, hipEventRecord(c->ev1, c->stream));
+    TK_HIP(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    TK_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    tk_kernel_timing &t = c->tstat[kind];
+    t.ms_total += ms;
+    t.launches += 1;
+    t.traj_steps += traj_steps;
+    t.flops += flops;
+    t.bytes += bytes;
+    return TK_OK;
+  }
+};
+
+int run_forward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap) {
+  tk::PassArgs a = base_args(c, M, seed, iteration, false);
+  a.psiT = c->psiT.p;
+  a.tau_out = c->tau.as<double>();
+  a.rec = c->rec.as<tk_jump>();
+  a.rec_cap = cap;
+  const int blocks = (M + tk::kWavesPerBlock - 1) / tk::kWavesPerBlock;
+  const size_t lds = tk::kWavesPerBlock * tk::pass_lds_bytes(*c->var);
+  void *args[] = {&a};
+  TimedLaunch tl(c, TK_KERNEL_FORWARD);
+  TK_HIP(c, hipLaunchKernel(c->var->k_forward, dim3(blocks), dim3(tk::kWave * tk::kWavesPerBlock),
+                            args, lds, c->stream));
+  int rc = tl.finish(static_cast<int64_t>(M) * c->nt, pass_flops(c, c->u, M),
+                     static_cast<double>(M) * c->d * c->bulk_cplx());
+  if (rc) return rc;
+  c->tau_M = M;
+  c->tau_seed = seed;
+  c->tau_iter = static_cast<int64_t>(iteration);
+  return TK_OK;
+}
+
+int run_backward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap) {
+  const size_t chi_bytes = static_cast<size_t>(c->nt) * M * c->d * c->bulk_cplx();
+  c->chi_M = -1;
+  TK_HIP(c, c->chi.ensure(chi_bytes));
+  tk::PassArgs a = base_args(c, M, seed, iteration, true);
+  a.tau_in = c->tau.as<double>();
+  a.chi = c->chi.p;
+  a.rec = c->rec.as<tk_jump>();
+  a.rec_cap = cap;
+  const int blocks = (M + tk::kWavesPerBlock - 1) / tk::kWavesPerBlock;
+  const size_t lds = tk::kWavesPerBlock * tk::pass_lds_bytes(*c->var);
+  void *args[] = {&a};
+  TimedLaunch tl(c, TK_KERNEL_BACKWARD);
+  TK_HIP(c, hipLaunchKernel(c->var->k_backward, dim3(blocks), dim3(tk::kWave * tk::kWavesPerBlock),
+                            args, lds, c->stream));
+  int rc = tl.finish(static_cast<int64_t>(M) * c->nt, pass_flops(c, c->u, M),
+                     static_cast<double>(chi_bytes));
+  if (rc) return rc;
+  c->chi_M = M;
+  return TK_OK;
+}
+
+int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap) {
+  if (c->chi_M != M) return fail(c, TK_ESTATE, "no costates stored for this M");
+  const int wpb = tk::kWavesPerBlock;
+  int tw = 1, blocks = 0;
+  size_t lds = 0;
+  for (tw = 1; tw <= 64; ++tw) {
+    blocks = (M + wpb * tw - 1) / (wpb * tw);
+    if (blocks > tk::kMaxBlocks) continue;
+    lds = wpb * tk::krotov_lds_bytes(*c->var, tw);
+    if (lds > 160 * 1024) return fail(c, TK_EUNSUPPORTED, "Krotov pass does not fit in LDS");
+    int occ = 0;
+    TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, c->var->k_krotov,
+                                                            tk::kWave * wpb, lds));
+    if (occ > 0 && static_cast<int64_t>(occ) * c->n_cu >= blocks) break;
+  }
+  if (tw > 64) return fail(c, TK_EUNSUPPORTED, "too many trajectories for one cooperative launch");
+  const int ncx = std::max(c->var->NC, 1);
+  const size_t nslot = static_cast<size_t>(c->nt) * tk::kMaxBlocks * ncx;
+  TK_HIP(c, c->slots.ensure(nslot * sizeof(unsigned long long)));
+  TK_HIP(c, c->u_new_dev.ensure(static_cast<size_t>(tk::kMaxCtrl) * c->nt * sizeof(double)));
+  {
+    unsigned long long *sp = c->slots.as<unsigned long long>();
+    long long n = static_cast<long long>(nslot);
+    int nb = blocks, nc = ncx;
+    void *fargs[] = {&sp, &n, &nb, &nc};
+    TK_HIP(c, hipLaunchKernel(c->var->k_fill, dim3(256), dim3(256), fargs, 0, c->stream));
+  }
+  tk::PassArgs a = base_args(c, M, seed, iteration, false);
+  a.psiT = c->psiT.p;
+  a.tau_out = c->tau.as<double>();
+  a.chi = c->chi.p;
+  a.rec = c->rec.as<tk_jump>();
+  a.rec_cap = cap;
+  a.u_old = c->u_dev.as<double>();
+  a.u_new = c->u_new_dev.as<double>();
+  a.S = c->S_dev.as<double>();
+  a.lam = c->lam_dev.as<double>();
+  a.slots = c->slots.as<unsigned long long>();
+  a.traj_per_wave = tw;
+  void *args[] = {&a};
+  c->last_wpb = wpb;
+  c->last_tw = tw;
+  c->last_blocks = blocks;
+  TimedLaunch tl(c, TK_KERNEL_KROTOV);
+  TK_HIP(c, hipLaunchCooperativeKernel(c->var->k_krotov, dim3(blocks), dim3(tk::kWave * wpb),
+                                       args, lds, c->stream));
+  // new pulses become the current ones
+  std::vector<double> unew(c->u.size());
+  if (!unew.empty()) {
+    TK_HIP(c, hipMemcpyAsync(unew.data(), c->u_new_dev.p, unew.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+  }
+  TK_HIP(c, hipStreamSynchronize(c->stream));
+  int rc = tl.finish(static_cast<int64_t>(M) * c->nt, pass_flops(c, unew.empty() ? c->u : unew, M),
+                     static_cast<double>(c->nt) * M * c->d * c->bulk_cplx());
+  if (rc) return rc;
+  rc = check_kernel_errors(c);
+  if (rc) return rc;
+  if (!unew.empty()) {
+    c->u = unew;
+    TK_HIP(c, hipMemcpyAsync(c->u_dev.p, c->u_new_dev.p, unew.size() * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+  }
+  c->tau_M = M;
+  c->tau_seed = seed;
+  c->tau_iter = static_cast<int64_t>(iteration);
+  c->chi_M = -1;  // costates belong to the pulses before the update
+  return TK_OK;
+}
+
+int functional_value(tk_ctx *c, int M, double *J) {
+  // J_T = 1 - (1/M) sum_k |tau_k|^2, reduced on the device in a fixed order
+  TK_HIP(c, c->jt_dev.ensure(sizeof(double)));
+  const double *tp = c->tau.as<double>();
+  double *jp = c->jt_dev.as<double>();
+  int m = M;
+  void *args[] = {&tp, &m, &jp};
+  TK_HIP(c, hipLaunchKernel(tk::functional_kernel(), dim3(1), dim3(256), args, 0, c->stream));
+  TK_HIP(c, hipMemcpyAsync(J, jp, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  TK_HIP(c, hipStreamSynchronize(c->stream));
+  return TK_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *tk_version(void) { return "trajkrotov 0.1 (gfx950)"; }
+
+const char *tk_last_error(const tk_ctx *ctx) {
+  if (!ctx) return "no context";
+  return ctx->err.c_str();
+}
+
+int tk_create(tk_ctx **out, int device, int precision) {
+  if (!out) return TK_EINVAL;
+  *out = nullptr;
+  if (precision != TK_FP64 && precision != TK_FP32) return TK_EINVAL;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TK_ENODEV;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TK_ENODEV;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TK_ENODEV;
+  tk_ctx *c = new (std::nothrow) tk_ctx();
+  if (!c) return TK_ENOMEM;
+  c->device = device;
+  c->precision = precision;
+  c->n_cu = prop.multiProcessorCount;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    tk_destroy(c);
+    return TK_EHIP;
+  }
+  *out = c;
+  return TK_OK;
+}
+
+void tk_destroy(tk_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const tk_csr *H_ctrl,
+                  int32_t n_jump, const tk_csr *L_jump) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  c->has_system = c->has_states = c->has_pulses = false;
+  c->chi_M = c->tau_M = -1;
+  if (d < 1 || d > (1 << 24)) return fail(c, TK_EINVAL, "d out of range");
+  if (n_ctrl < 0 || n_ctrl > tk::kMaxCtrl) return fail(c, TK_EINVAL, "n_ctrl out of range (0..8)");
+  if (n_jump < 0 || n_jump > tk::kMaxJump) return fail(c, TK_EINVAL, "n_jump out of range (0..8)");
+  if ((n_ctrl > 0 && !H_ctrl) || (n_jump > 0 && !L_jump))
+    return fail(c, TK_EINVAL, "operator array is NULL");
+  Csr h0;
+  int rc = read_csr(c, H0, d, "H0", h0);
+  if (rc) return rc;
+  std::vector<Csr> hc(n_ctrl), lj(n_jump);
+  for (int i = 0; i < n_ctrl; ++i)
+    if ((rc = read_csr(c, &H_ctrl[i], d, "H_ctrl", hc[i]))) return rc;
+  for (int l = 0; l < n_jump; ++l)
+    if ((rc = read_csr(c, &L_jump[l], d, "L_jump", lj[l]))) return rc;
+  if (!hermitian(h0)) return fail(c, TK_ENOTHERM, "H0 is not Hermitian");
+  for (int i = 0; i < n_ctrl; ++i)
+    if (!hermitian(hc[i])) return fail(c, TK_ENOTHERM, "a control Hamiltonian is not Hermitian");
+
+  // static part of H_eff: A = H0 - (i/2) sum_l L_l^+ L_l
+  Csr A = h0;
+  for (int l = 0; l < n_jump; ++l) A = axpy(A, cd(0.0, -0.5), multiply(adjoint(lj[l]), lj[l]));
+  const Csr Ad = adjoint(A);
+  std::vector<Csr> hcd(n_ctrl);
+  for (int i = 0; i < n_ctrl; ++i) hcd[i] = adjoint(hc[i]);
+
+  const int ws = std::max(A.max_row(), Ad.max_row());
+  int wc = 1;
+  for (int i = 0; i < n_ctrl; ++i) wc = std::max({wc, hc[i].max_row(), hcd[i].max_row()});
+  int wl = 1;
+  for (int l = 0; l < n_jump; ++l) wl = std::max(wl, lj[l].max_row());
+  const int nc = n_ctrl * wc;
+  const int r_need = static_cast<int>((d + tk::kWave - 1) / tk::kWave);
+
+  int nv = 0;
+  const tk::Variant *vs = tk::variants(&nv);
+  const tk::Variant *best = nullptr;
+  for (int k = 0; k < nv; ++k) {
+    const tk::Variant &v = vs[k];
+    if (v.precision != c->precision || v.R < r_need || v.WS < ws || v.NC < nc) continue;
+    if (!best || std::make_tuple(v.R, v.WS, v.NC) < std::make_tuple(best->R, best->WS, best->NC))
+      best = &v;
+  }
+  if (!best)
+    return fail(c, TK_EUNSUPPORTED,
+                "no compiled kernel variant for d=" + std::to_string(d) + " static width " +
+                    std::to_string(ws) + " control slots " + std::to_string(nc));
+  c->var = best;
+  c->d = d;
+  c->n_ctrl = n_ctrl;
+  c->n_jump = n_jump;
+  c->wc = wc;
+  c->wl = wl;
+  c->H_ctrl_host = hc;
+
+  const int R = best->R;
+  // LDS bank groups of one complex element (32 banks of 4 bytes)
+  const int nbg = c->precision == TK_FP64 ? 8 : 16;
+  Ell e;
+  pack({&A}, best->WS, R, nbg, e);
+  if ((rc = upload_ell(c, e, c->f_scol, c->f_sval))) return rc;
+  pack({&Ad}, best->WS, R, nbg, e);
+  if ((rc = upload_ell(c, e, c->b_scol, c->b_sval))) return rc;
+  pack_ctrl(hc, wc, best->NC, R, nbg, e);
+  if ((rc = upload_ell(c, e, c->f_ccol, c->f_cval))) return rc;
+  pack_ctrl(hcd, wc, best->NC, R, nbg, e);
+  if ((rc = upload_ell(c, e, c->b_ccol, c->b_cval))) return rc;
+  std::vector<const Csr *> lp;
+  for (int l = 0; l < n_jump; ++l) lp.push_back(&lj[l]);
+  if (lp.empty()) lp.push_back(nullptr);
+  pack(lp, wl, R, nbg, e);
+  if ((rc = upload_ell(c, e, c->lcol, c->lval))) return rc;
+
+  c->b0 = norm2_estimate(A);
+  for (int i = 0; i < tk::kMaxCtrl; ++i) c->bc[i] = i < n_ctrl ? norm2_estimate(hc[i]) : 0.0;
+  // algorithmic non-zeros of H_eff: union of the static and control patterns
+  Csr pat = A;
+  for (int i = 0; i < n_ctrl; ++i) {
+    Csr ones = hc[i];
+    for (auto &v : ones.val) v = cd(1.0, 0.0);
+    Csr absA = pat;
+    for (auto &v : absA.val) v = cd(std::abs(v), 0.0);
+    pat = axpy(absA, cd(1.0, 0.0), ones);
+  }
+  c->nnz_heff = pat.nnz();
+  c->has_system = true;
+  return TK_OK;
+}
+
+int tk_set_states(tk_ctx *c, const double *psi0, const double *psi_tgt) {
+  if (!c) return TK_EINVAL;
+  if (!c->has_system) return fail(c, TK_ESTATE, "no system set");
+  if (!psi0 || !psi_tgt) return fail(c, TK_EINVAL, "state pointer is NULL");
+  TK_HIP(c, hipSetDevice(c->device));
+  const int64_t d = c->d;
+  const int64_t dpad = static_cast<int64_t>(c->var->R) * tk::kWave;
+  double n0 = 0.0, nt = 0.0;
+  for (int64_t i = 0; i < 2 * d; ++i) {
+    if (!std::isfinite(psi0[i]) || !std::isfinite(psi_tgt[i]))
+      return fail(c, TK_EINVAL, "non-finite state entry");
+    n0 += psi0[i] * psi0[i];
+    nt += psi_tgt[i] * psi_tgt[i];
+  }
+  if (std::fabs(std::sqrt(n0) - 1.0) > 1e-10) return fail(c, TK_EINVAL, "psi0 is not normalised");
+  if (!(nt > 0.0)) return fail(c, TK_EINVAL, "target is zero");
+  const double inv = 1.0 / std::sqrt(nt);
+  std::vector<double> p(2 * dpad, 0.0), t(2 * dpad, 0.0);
+  for (int64_t i = 0; i < 2 * d; ++i) {
+    p[i] = psi0[i];
+    t[i] = psi_tgt[i] * inv;
+  }
+  int rc = upload_vec(c, c->psi0_bulk, p);
+  if (rc) return rc;
+  if ((rc = upload_vec(c, c->tgt_bulk, t))) return rc;
+  if ((rc = upload(c, c->tgt64, t.data(), t.size() * sizeof(double)))) return rc;
+  c->has_states = true;
+  c->chi_M = c->tau_M = -1;
+  return TK_OK;
+}
+
+int tk_set_pulses(tk_ctx *c, int32_t nt, double T, const double *u, const double *S,
+                  const double *lambda) {
+  if (!c) return TK_EINVAL;
+  if (!c->has_system) return fail(c, TK_ESTATE, "no system set");
+  if (nt < 1) return fail(c, TK_EINVAL, "nt must be >= 1");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(c, TK_EINVAL, "T must be positive");
+  const size_t n = static_cast<size_t>(c->n_ctrl) * nt;
+  if (n > 0 && !u) return fail(c, TK_EINVAL, "u is NULL");
+  TK_HIP(c, hipSetDevice(c->device));
+  std::vector<double> uu(u, u + n), ss(n, 1.0), ll(c->n_ctrl, 1.0);
+  if (S) ss.assign(S, S + n);
+  if (lambda) ll.assign(lambda, lambda + c->n_ctrl);
+  for (double x : uu)
+    if (!std::isfinite(x)) return fail(c, TK_EINVAL, "non-finite pulse value");
+  for (double x : ss)
+    if (!std::isfinite(x) || x < 0.0 || x > 1.0) return fail(c, TK_EINVAL, "S must be in [0, 1]");
+  for (double x : ll)
+    if (!(x > 0.0) || !std::isfinite(x)) return fail(c, TK_EINVAL, "lambda must be positive");
+  c->nt = nt;
+  c->T = T;
+  c->u = uu;
+  c->S = ss;
+  c->lam = ll;
+  // device copies have kMaxCtrl rows: zero pulses and shapes, lambda 1 past n_ctrl
+  std::vector<double> up(static_cast<size_t>(tk::kMaxCtrl) * nt, 0.0), sp(up.size(), 0.0),
+      lp(tk::kMaxCtrl, 1.0);
+  std::copy(uu.begin(), uu.end(), up.begin());
+  std::copy(ss.begin(), ss.end(), sp.begin());
+  std::copy(ll.begin(), ll.end(), lp.begin());
+  int rc = upload(c, c->u_dev, up.data(), up.size() * sizeof(double));
+  if (rc) return rc;
+  if ((rc = upload(c, c->S_dev, sp.data(), sp.size() * sizeof(double)))) return rc;
+  if ((rc = upload(c, c->lam_dev, lp.data(), lp.size() * sizeof(double)))) return rc;
+  c->has_pulses = true;
+  c->chi_M = c->tau_M = -1;
+  return TK_OK;
+}
+
+int tk_get_pulses(const tk_ctx *c, double *u_out) {
+  if (!c) return TK_EINVAL;
+  if (!c->has_pulses) return fail(const_cast<tk_ctx *>(c), TK_ESTATE, "no pulses set");
+  if (!u_out) return fail(const_cast<tk_ctx *>(c), TK_EINVAL, "u_out is NULL");
+  std::copy(c->u.begin(), c->u.end(), u_out);
+  return TK_OK;
+}
+
+int tk_propagate_forward(tk_ctx *c, int32_t M, uint64_t seed, uint64_t iteration, double *psiT_out,
+                         double *tau_out, tk_jump *rec, int64_t cap, int64_t *n_rec) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!rec) cap = 0;
+  int rc = prepare_pass(c, M, cap);
+  if (rc) return rc;
+  if ((rc = reset_counters(c))) return rc;
+  if ((rc = run_forward(c, M, seed, iteration, cap))) return rc;
+  if ((rc = check_kernel_errors(c))) return rc;
+  if (tau_out)
+    TK_HIP(c, hipMemcpy(tau_out, c->tau.p, 2 * static_cast<size_t>(M) * sizeof(double),
+                        hipMemcpyDeviceToHost));
+  if (psiT_out) {
+    std::vector<unsigned char> buf(static_cast<size_t>(M) * c->d * c->bulk_cplx());
+    TK_HIP(c, hipMemcpy(buf.data(), c->psiT.p, buf.size(), hipMemcpyDeviceToHost));
+    to_host_cplx(c, buf.data(), static_cast<size_t>(M) * c->d, psiT_out);
+  }
+  return fetch_records(c, rec, cap, n_rec);
+}
+
+int tk_propagate_backward(tk_ctx *c, int32_t M, uint64_t seed, uint64_t iteration,
+                          const double *tau, tk_jump *rec, int64_t cap, int64_t *n_rec) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!rec) cap = 0;
+  const bool had_tau = (c->tau_M == M);
+  int rc = prepare_pass(c, M, cap);
+  if (rc) return rc;
+  if (tau) {
+    for (int64_t i = 0; i < 2 * static_cast<int64_t>(M); ++i)
+      if (!std::isfinite(tau[i])) return fail(c, TK_EINVAL, "non-finite tau");
+    TK_HIP(c, hipMemcpy(c->tau.p, tau, 2 * static_cast<size_t>(M) * sizeof(double),
+                        hipMemcpyHostToDevice));
+  } else if (!had_tau) {
+    return fail(c, TK_ESTATE, "no overlaps kept for this M; pass tau");
+  }
+  if ((rc = reset_counters(c))) return rc;
+  if ((rc = run_backward(c, M, seed, iteration, cap))) return rc;
+  if ((rc = check_kernel_errors(c))) return rc;
+  return fetch_records(c, rec, cap, n_rec);
+}
+
+int tk_get_costate(const tk_ctx *cc, int32_t j, double *chi_out) {
+  tk_ctx *c = const_cast<tk_ctx *>(cc);
+  if (!c) return TK_EINVAL;
+  if (c->chi_M < 1) return fail(c, TK_ESTATE, "no costates stored");
+  if (j < 0 || j >= c->nt) return fail(c, TK_EINVAL, "time index out of range");
+  if (!chi_out) return fail(c, TK_EINVAL, "chi_out is NULL");
+  TK_HIP(c, hipSetDevice(c->device));
+  const size_t n = static_cast<size_t>(c->chi_M) * c->d;
+  std::vector<unsigned char> buf(n * c->bulk_cplx());
+  const unsigned char *src = c->chi.as<unsigned char>() + static_cast<size_t>(j) * buf.size();
+  TK_HIP(c, hipMemcpy(buf.data(), src, buf.size(), hipMemcpyDeviceToHost));
+  to_host_cplx(c, buf.data(), n, chi_out);
+  return TK_OK;
+}
+
+int tk_functional(tk_ctx *c, int32_t M, uint64_t seed, uint64_t iteration, double *J_T,
+                  double *tau_out) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!J_T) return fail(c, TK_EINVAL, "J_T is NULL");
+  int rc = prepare_pass(c, M, 0);
+  if (rc) return rc;
+  if ((rc = reset_counters(c))) return rc;
+  if ((rc = run_forward(c, M, seed, iteration, 0))) return rc;
+  if ((rc = check_kernel_errors(c))) return rc;
+  if ((rc = functional_value(c, M, J_T))) return rc;
+  if (tau_out)
+    TK_HIP(c, hipMemcpy(tau_out, c->tau.p, 2 * static_cast<size_t>(M) * sizeof(double),
+                        hipMemcpyDeviceToHost));
+  return TK_OK;
+}
+
+int tk_krotov_iterate(tk_ctx *c, int32_t M, uint64_t seed, uint64_t first_iteration,
+                      int32_t n_iter, double *J_T_out, tk_jump *rec, int64_t cap,
+                      int64_t *n_rec) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!rec) cap = 0;
+  if (n_iter < 0) return fail(c, TK_EINVAL, "n_iter must be >= 0");
+  if (!J_T_out) return fail(c, TK_EINVAL, "J_T_out is NULL");
+  const bool cont_ok = c->tau_M == M && c->tau_seed == seed &&
+                       c->tau_iter == static_cast<int64_t>(first_iteration) - 1;
+  int rc = prepare_pass(c, M, cap);
+  if (rc) return rc;
+  if ((rc = reset_counters(c))) return rc;
+  int out = 0;
+  uint64_t n = first_iteration;
+  if (first_iteration == 0) {
+    if ((rc = run_forward(c, M, seed, 0, cap))) return rc;
+    if ((rc = check_kernel_errors(c))) return rc;
+    if ((rc = functional_value(c, M, &J_T_out[out++]))) return rc;
+    n = 1;
+  } else if (!cont_ok) {
+    return fail(c, TK_ESTATE, "no forward pass of the previous iteration with this M and seed");
+  }
+  const uint64_t last = (first_iteration == 0 ? 0 : first_iteration - 1) + n_iter;
+  for (; n <= last; ++n) {
+    if ((rc = run_backward(c, M, seed, n, cap))) return rc;
+    if ((rc = check_kernel_errors(c))) return rc;
+    if ((rc = run_krotov(c, M, seed, n, cap))) return rc;
+    if ((rc = functional_value(c, M, &J_T_out[out++]))) return rc;
+  }
+  return fetch_records(c, rec, cap, n_rec);
+}
+
+int tk_set_timing(tk_ctx *c, int enable) {
+  if (!c) return TK_EINVAL;
+  c->timing = enable != 0;
+  return TK_OK;
+}
+
+int tk_get_timing(const tk_ctx *c, int kind, tk_kernel_timing *out) {
+  if (!c || !out || kind < 0 || kind >= TK_KERNEL_COUNT) return TK_EINVAL;
+  *out = c->tstat[kind];
+  return TK_OK;
+}
+
+int tk_reset_timing(tk_ctx *c) {
+  if (!c) return TK_EINVAL;
+  for (auto &t : c->tstat) t = tk_kernel_timing{};
+  return TK_OK;
+}
+
+int tk_get_launch_info(const tk_ctx *c, const char **variant, int32_t *waves_per_block,
+                       int32_t *traj_per_wave, int32_t *blocks) {
+  if (!c) return TK_EINVAL;
+  if (variant) *variant = c->var ? c->var->name : "";
+  if (waves_per_block) *waves_per_block = c->last_wpb;
+  if (traj_per_wave) *traj_per_wave = c->last_tw;
+  if (blocks) *blocks = c->last_blocks;
+  return TK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal definitions shared by the HIP kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "trajkrotov.h"
+
+namespace tk {
+
+constexpr int kWave = 64;          // lanes of a CDNA wavefront
+constexpr int kMaxCtrl = 8;        // controls per system
+constexpr int kMaxJump = 8;        // Lindblad operators per system
+constexpr int kMaxTaylor = 40;     // largest polynomial order of a step
+constexpr int kWavesPerBlock = 4;  // waves per workgroup in every kernel
+constexpr double kMaxStepNorm = 1.0;  // substeps keep ||H_eff|| h at most this
+constexpr int kMaxSubsteps = 4096;    // substeps per time step before an error
+constexpr int kPollPerLane = 4;       // blocks polled by one lane in the Krotov pass
+constexpr int kMaxBlocks = kWave * kPollPerLane;  // blocks of one Krotov launch
+
+// error bits a kernel may raise (device int, OR-ed)
+constexpr int kErrNoJumpWeight = 1;  // jump with all ||L_l psi||^2 == 0
+constexpr int kErrTaylorOrder = 2;   // step too long for kMaxTaylor terms
+constexpr int kErrSyncTimeout = 4;   // grid-wide step reduction did not complete
+constexpr int kErrJumpLoop = 8;      // more jumps in one step than allowed
+
+// Sentinel bit pattern of an unwritten reduction slot: a NaN whose payload
+// floating-point arithmetic never creates from finite inputs.
+constexpr uint64_t kSlotEmpty = 0xFFF7DEADBEEF5A5Aull;
+
+// Arguments of every propagation kernel.  Operator slices use the per-lane
+// padded layout [slot][m][lane]: row r = lane + 64 m of the Hilbert space;
+// a complex value is two consecutive reals of the bulk precision.
+struct PassArgs {
+  int d;        // Hilbert dimension
+  int nt;       // time steps
+  int M;        // trajectories
+  int n_ctrl;   // controls
+  int n_jump;   // Lindblad operators
+  int wc;       // control slots per control (slot c belongs to control c / wc)
+  int wl;       // slots per row of each jump operator
+  int kmax;     // largest Taylor order allowed
+  double dt;    // T / nt
+  double tol;   // truncation tolerance of one step (relative)
+  double b0;    // bound on ||H0 - (i/2) sum L^+L||_2
+  double bc[kMaxCtrl];  // bounds on ||H_i||_2
+  double ftol;  // relative tolerance of the jump-time root
+  double inv_n[kMaxTaylor + 1];  // 1/n for the Taylor recursion (entry 0 unused)
+  // operator used by the pass: H_eff pieces (forward) or their adjoints
+  const int *scol;
+  const void *sval;
+  const int *ccol;
+  const void *cval;
+  // jump operators [l][w][m][lane]
+  const int *lcol;
+  const void *lval;
+  // pulse-like arrays have kMaxCtrl rows; rows past n_ctrl are zero (lambda: 1)
+  const double *u;          // [kMaxCtrl][nt] pulses propagated with (plain passes)
+  const void *psi_start;    // [64 R] complex, bulk precision, zero padded
+  const double *tgt;        // [64 R] complex128, normalised, zero padded
+  uint64_t seed;
+  uint64_t iteration;
+  uint32_t instance;
+  void *psiT;               // [M][d] normalised final states (bulk), may be null
+  double *tau_out;          // [2M] overlaps <tgt|psi_hat(T)>, may be null
+  const double *tau_in;     // [2M] costate weights (backward pass)
+  void *chi;                // [nt][M][d] costates (bulk precision)
+  tk_jump *rec;             // [rec_cap] jump records
+  unsigned long long *rec_count;
+  long long rec_cap;
+  int *err;                 // error bits
+  // sequential Krotov pass
+  const double *u_old;      // [kMaxCtrl][nt] pulses of the previous iteration
+  double *u_new;            // [kMaxCtrl][nt] updated pulses (written by block 0)
+  const double *S;          // [kMaxCtrl][nt] update shape
+  const double *lam;        // [kMaxCtrl] lambda_i
+  unsigned long long *slots;  // [nt][kMaxBlocks][NC] per-block partial sums
+  int traj_per_wave;        // trajectories owned by one wave
+  long long spin_limit;     // polls before a step reduction gives up
+};
+
+// One compiled kernel variant: bulk precision, rows per lane R, static slots
+// per row WS, control slots per row NC.
+struct Variant {
+  const char *name;
+  int precision;  // TK_FP64 / TK_FP32
+  int R, WS, NC;
+  const void *k_forward;
+  const void *k_backward;
+  const void *k_krotov;
+  const void *k_fill;  // slot initialisation
+};
+
+// Table of compiled variants (defined in tk_kernels.hip).
+const Variant *variants(int *count);
+
+// Kernel reducing J_T = 1 - (1/M) sum |tau_k|^2 (one block of 256 threads).
+const void *functional_kernel();
+
+// Per-wave LDS bytes of the Krotov kernel for a variant and Tw trajectories.
+size_t krotov_lds_bytes(const Variant &v, int traj_per_wave);
+// Per-wave LDS bytes of the plain passes.
+size_t pass_lds_bytes(const Variant &v);
+
+}  // namespace tk

@@ -1,0 +1,878 @@
+// HIP kernels for gfx950: quantum-jump trajectories, costates and the
+// sequential Krotov pass.
+//
+// Mapping.  One wavefront (64 lanes) advances one trajectory at a time; lane
+// `l` owns the rows r = l + 64 m (m < R) of the state.  Each lane keeps its
+// rows of the effective Hamiltonian in registers as padded slots: WS static
+// slots (H0 - (i/2) sum L^+L) and NC control slots (H_i, scaled by u_ij once
+// per step).  The state's Taylor terms are exchanged through a per-wave LDS
+// vector (all gathers of a matrix-vector product are issued before the first
+// multiply, so their latencies overlap); norms and overlaps are FP64
+// wavefront reductions in a fixed order (DPP within 16-lane rows, then the
+// four row sums read as scalars), so every lane holds the identical sum.
+//
+// Step propagator.  exp(-i H_eff h) (forward) or exp(+i H_eff^+ h) (backward)
+// applied as a Taylor polynomial.  The step is split into n_sub equal
+// substeps so that ||H_eff|| h <= 1, and the order K of each substep is the
+// smallest with truncation bound below `tol`; both follow from a norm bound of
+// the step's H_eff and are uniform across the grid.
+//
+// Jumps (Sec. 2.1, MCWF steps 3-5 and the remark on precise jump times).  When
+// the norm at the end of a (sub)step is below the threshold r, the crossing
+// time is found by a safeguarded Newton iteration on ||U(tau) psi||^2 - r
+// (bracketed, falling back to bisection), using
+// d||psi||^2/dtau = 2 Im <psi|H_eff|psi> (forward); the jump operator is then
+// drawn with weights ||L_l psi||^2, applied, the state renormalised, and the
+// rest of the substep propagated, so several jumps may fall in one step.
+//
+// Sequential Krotov pass (Sec. 2.2 "sequential", Sec. 2.3 update).  One
+// cooperative persistent launch; waves own `traj_per_wave` trajectories
+// whose states stay in LDS across steps.  Right after a trajectory advances
+// to t_{j+1}, its share of sum_k Im <chi_k(t_{j+1})|H_i|psi_hat_k(t_{j+1})>
+// is formed (the costate loads were issued before the advance, so their
+// latency is hidden).  Each block sums its waves in a fixed order, publishes
+// the FP64 partials into its own slot of a per-step array (initialised to a
+// sentinel), and polls until every block's partial of that step is present;
+// all blocks then sum the partials in block order, so they obtain the same
+// u_ij bit for bit without a broadcast.
+#include <hip/hip_runtime.h>
+
+#include "tk_internal.h"
+
+namespace tk {
+namespace {
+
+template <typename real>
+struct cx {
+  real x, y;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a full wave; every lane receives the same value.
+// Within a 16-lane row: pairs (xor 1), pairs of pairs (xor 2), half-row
+// mirror, row mirror -- each lane adds a partner holding a disjoint partial
+// sum, and both partners add the same two operands.  Then the four row sums
+// are combined as (row0 + row1) + (row2 + row3).
+__device__ __forceinline__ double wave_sum(double x) {
+  x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_mov<0x141>(x);  // row_half_mirror
+  x += dpp_mov<0x140>(x);  // row_mirror
+  return (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
+}
+
+// ---- Philox4x64-10 (Salmon et al., SC'11) ---------------------------------
+__device__ __forceinline__ void philox4x64(uint64_t c0, uint64_t c1, uint64_t c2,
+                                           uint64_t c3, uint64_t k0, uint64_t k1,
+                                           uint64_t &w0, uint64_t &w1) {
+  constexpr uint64_t kMul0 = 0xD2E7470EE14C6C93ull;
+  constexpr uint64_t kMul1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kWeyl0 = 0x9E3779B97F4A7C15ull;
+  constexpr uint64_t kWeyl1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd) {
+      k0 += kWeyl0;
+      k1 += kWeyl1;
+    }
+    const uint64_t lo0 = kMul0 * c0, hi0 = __umul64hi(kMul0, c0);
+    const uint64_t lo1 = kMul1 * c2, hi1 = __umul64hi(kMul1, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  w0 = c0;
+  w1 = c1;
+}
+
+__device__ __forceinline__ double to_unit(uint64_t w) {
+  return static_cast<double>(w >> 11) * 0x1.0p-53;
+}
+
+struct Stream {
+  uint64_t k0, k1, iteration, direction;
+  __device__ void block(uint64_t ordinal, double &thr, double &choice) const {
+    uint64_t w0, w1;
+    philox4x64(ordinal, iteration, direction, 0, k0, k1, w0, w1);
+    thr = to_unit(w0);
+    choice = to_unit(w1);
+  }
+  __device__ double threshold(uint64_t ordinal) const {
+    double t, c;
+    block(ordinal, t, c);
+    return t;
+  }
+};
+
+__device__ __forceinline__ Stream make_stream(const PassArgs &a, int k, int dir) {
+  Stream s;
+  s.k0 = a.seed;
+  s.k1 = (static_cast<uint64_t>(a.instance) << 32) | static_cast<uint32_t>(k);
+  s.iteration = a.iteration;
+  s.direction = static_cast<uint64_t>(dir);
+  return s;
+}
+
+template <typename real>
+__device__ __forceinline__ void cfma(cx<real> &y, const cx<real> &a, const cx<real> &b) {
+  y.x = fma(a.x, b.x, y.x);
+  y.x = fma(-a.y, b.y, y.x);
+  y.y = fma(a.x, b.y, y.y);
+  y.y = fma(a.y, b.x, y.y);
+}
+
+// ---- per-lane operator slice ------------------------------------------------
+template <typename real, int R, int WS, int NC>
+struct LaneOp {
+  static constexpr int NCX = NC > 0 ? NC : 1;
+  int scol[WS][R];
+  cx<real> sval[WS][R];
+  int ccol[NCX][R];
+  cx<real> cv[NCX][R];  // control matrix elements scaled by the current pulses
+  const cx<real> *cval;  // unscaled control elements, [c][m][lane] in global memory
+
+  __device__ void load(const PassArgs &a, int lane) {
+    const cx<real> *sv = static_cast<const cx<real> *>(a.sval);
+    const cx<real> *cvv = static_cast<const cx<real> *>(a.cval);
+#pragma unroll
+    for (int s = 0; s < WS; ++s)
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int idx = (s * R + m) * kWave + lane;
+        scol[s][m] = a.scol[idx];
+        sval[s][m] = sv[idx];
+      }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int idx = (c * R + m) * kWave + lane;
+        ccol[c][m] = a.ccol[idx];
+        cv[c][m] = cx<real>{0, 0};
+      }
+    cval = cvv + lane;
+  }
+
+  // unscaled control element of slot c, row slot m
+  __device__ __forceinline__ cx<real> cval_at(int c, int m) const {
+    return cval[(c * R + m) * kWave];
+  }
+
+  // cv = u_{c / wc} * cval for the pulse values uj[0 .. NCX) (zero past n_ctrl)
+  __device__ void set_pulses(const double (&uj)[NCX], int wc) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int i = c / wc;  // < NC, hence a valid index
+      const real ui = static_cast<real>(uj[i]);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const cx<real> q = cval_at(c, m);
+        cv[c][m] = cx<real>{ui * q.x, ui * q.y};
+      }
+    }
+  }
+
+  // y = Op v for the lane's rows (v in LDS).  All gathers first.
+  __device__ void apply(const cx<real> *v, cx<real> (&y)[R]) const {
+    cx<real> b[WS + NC][R];
+#pragma unroll
+    for (int s = 0; s < WS; ++s)
+#pragma unroll
+      for (int m = 0; m < R; ++m) b[s][m] = v[scol[s][m]];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int m = 0; m < R; ++m) b[WS + c][m] = v[ccol[c][m]];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+#pragma unroll
+    for (int s = 0; s < WS; ++s)
+#pragma unroll
+      for (int m = 0; m < R; ++m) cfma(y[m], sval[s][m], b[s][m]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int m = 0; m < R; ++m) cfma(y[m], cv[c][m], b[WS + c][m]);
+  }
+};
+
+template <typename real, int R>
+__device__ __forceinline__ double norm2(const cx<real> (&p)[R]) {
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const double x = p[m].x, y = p[m].y;
+    s = fma(x, x, s);
+    s = fma(y, y, s);
+  }
+  return wave_sum(s);
+}
+
+template <typename real, int R>
+__device__ __forceinline__ void store_lds(cx<real> *v, const cx<real> (&p)[R], int lane) {
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[lane + kWave * m] = p[m];
+}
+
+// Smallest K with x^(K+1)/(K+1)! e^x <= tol (Taylor remainder bound), or -1.
+__device__ inline int taylor_order(double x, double tol, int kmax) {
+  const double ex = exp(x);
+  double t = x;
+  for (int K = 1; K <= kmax; ++K) {
+    t *= x / static_cast<double>(K + 1);
+    if (t * ex <= tol) return K;
+  }
+  return -1;
+}
+
+// out = sum_{n=0..K} (s i tau Op)^n / n! in   with s = -1 (forward) or +1.
+template <typename real, int R, int WS, int NC, int SGN>
+__device__ void taylor(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx<real> *v,
+                       const cx<real> (&in)[R], cx<real> (&out)[R], double tau, int K,
+                       int lane) {
+  cx<real> t[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    t[m] = in[m];
+    out[m] = in[m];
+  }
+  for (int n = 1; n <= K; ++n) {
+    store_lds(v, t, lane);
+    wave_sync();
+    cx<real> y[R];
+    op.apply(v, y);
+    wave_sync();
+    const real c = static_cast<real>(tau * a.inv_n[n]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      if (SGN < 0)
+        t[m] = cx<real>{c * y[m].y, -c * y[m].x};
+      else
+        t[m] = cx<real>{-c * y[m].y, c * y[m].x};
+      out[m].x += t[m].x;
+      out[m].y += t[m].y;
+    }
+  }
+}
+
+// y = L_l p for jump operator l (slices read from global memory; p in LDS v)
+template <typename real, int R>
+__device__ void apply_jump(const PassArgs &a, int l, const cx<real> *v, cx<real> (&y)[R],
+                           int lane) {
+  const cx<real> *lv = static_cast<const cx<real> *>(a.lval);
+#pragma unroll
+  for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+  for (int w = 0; w < a.wl; ++w)
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int idx = ((l * a.wl + w) * R + m) * kWave + lane;
+      cfma(y[m], lv[idx], v[a.lcol[idx]]);
+    }
+}
+
+struct TrajMeta {
+  double nrm2;  // squared norm of the unnormalised state (the MCWF clock)
+  double r;     // current threshold
+  int ordinal;  // jumps so far in this pass
+};
+
+// Advance one trajectory across one substep of length h starting at time t0
+// (MCWF with precise jump times).  DIR 0: forward, exp(-i H_eff tau), times
+// t0 + elapsed; DIR 1: backward, exp(+i H_eff^+ tau), times t0 - elapsed.
+template <typename real, int R, int WS, int NC, int DIR>
+__device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx<real> *v,
+                        cx<real> (&psi)[R], TrajMeta &st, const Stream &rng, int j, double t0,
+                        double h, int K, int k, int lane) {
+  constexpr int SGN = DIR == 0 ? -1 : 1;
+  double tau_rem = h;
+  double n_s = st.nrm2;
+  cx<real> ps[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) ps[m] = psi[m];
+  constexpr double eps_real = sizeof(real) == 8 ? 0x1.0p-52 : 0x1.0p-23;
+  for (int guard = 0;; ++guard) {
+    cx<real> out[R];
+    taylor<real, R, WS, NC, SGN>(op, a, v, ps, out, tau_rem, K, lane);
+    const double n_end = norm2(out);
+    if (!(n_end < st.r)) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = out[m];
+      st.nrm2 = n_end;
+      return;
+    }
+    if (guard >= 64) {  // pathological: give up on this step, keep the state
+      if (lane == 0) atomicOr(a.err, kErrJumpLoop);
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = out[m];
+      st.nrm2 = n_end;
+      st.r = 0.0;
+      return;
+    }
+    // ---- jump time: root of f(tau) = ||U(tau) ps||^2 - r in (0, tau_rem] ----
+    double lo = 0.0, hi = tau_rem;
+    double flo = n_s - st.r, fhi = n_end - st.r;
+    double tau = tau_rem * flo / (flo - fhi);
+    if (!(tau > lo && tau < hi)) tau = 0.5 * (lo + hi);
+    cx<real> pt[R];
+    for (int it = 0; it < 48; ++it) {
+      taylor<real, R, WS, NC, SGN>(op, a, v, ps, pt, tau, K, lane);
+      const double f = norm2(pt) - st.r;
+      // derivative of the norm: +2 Im<p|H_eff p> forward, -2 Im<p|H_eff^+ p> backward
+      store_lds(v, pt, lane);
+      wave_sync();
+      cx<real> y[R];
+      op.apply(v, y);
+      wave_sync();
+      double im = 0.0;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        im = fma(static_cast<double>(pt[m].x), static_cast<double>(y[m].y), im);
+        im = fma(-static_cast<double>(pt[m].y), static_cast<double>(y[m].x), im);
+      }
+      const double fp = (DIR == 0 ? 2.0 : -2.0) * wave_sum(im);
+      if (f >= 0.0) {
+        lo = tau;
+        flo = f;
+      } else {
+        hi = tau;
+        fhi = f;
+      }
+      if (fabs(f) <= a.ftol * st.r || (hi - lo) <= 4.0 * eps_real * h) break;
+      double tn = tau - f / fp;
+      if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+      if (fabs(tn - tau) <= 2.0 * eps_real * h) {
+        tau = tn;
+        taylor<real, R, WS, NC, SGN>(op, a, v, ps, pt, tau, K, lane);
+        break;
+      }
+      tau = tn;
+    }
+    // ---- jump (MCWF step 4) ----
+    store_lds(v, pt, lane);
+    wave_sync();
+    // weights ||L_l p||^2; pass 1 sums them, pass 2 walks the cumulative sum
+    double total = 0.0;
+    for (int l = 0; l < a.n_jump; ++l) {
+      cx<real> y[R];
+      apply_jump<real, R>(a, l, v, y, lane);
+      total += norm2(y);
+    }
+    double thr_unused, x;
+    rng.block(static_cast<uint64_t>(st.ordinal), thr_unused, x);
+    if (!(total > 0.0)) {
+      if (lane == 0) atomicOr(a.err, kErrNoJumpWeight);
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = pt[m];
+      st.nrm2 = norm2(pt);
+      st.r = 0.0;
+      wave_sync();
+      return;
+    }
+    const double target = x * total;
+    double acc = 0.0, wsel = 0.0;
+    int lsel = -1;
+    cx<real> y[R];
+    for (int l = 0; l < a.n_jump; ++l) {
+      apply_jump<real, R>(a, l, v, y, lane);
+      wsel = norm2(y);
+      acc += wsel;
+      if (target < acc) {
+        lsel = l;
+        break;
+      }
+    }
+    if (lsel < 0) {  // rounding left target >= total: take the last operator
+      lsel = a.n_jump - 1;
+      apply_jump<real, R>(a, lsel, v, y, lane);
+      wsel = norm2(y);
+    }
+    wave_sync();
+    const real inv = static_cast<real>(1.0 / sqrt(wsel));
+#pragma unroll
+    for (int m = 0; m < R; ++m) ps[m] = cx<real>{y[m].x * inv, y[m].y * inv};
+    const double elapsed = (h - tau_rem) + tau;
+    if (lane == 0) {
+      const unsigned long long slot = atomicAdd(a.rec_count, 1ull);
+      if (static_cast<long long>(slot) < a.rec_cap) {
+        tk_jump r;
+        r.instance = static_cast<int32_t>(a.instance);
+        r.traj = k;
+        r.step = j;
+        r.op = lsel;
+        r.ordinal = st.ordinal;
+        r.direction = DIR;
+        r.iteration = static_cast<int32_t>(a.iteration);
+        r.reserved = 0;
+        r.t = DIR == 0 ? t0 + elapsed : t0 - elapsed;
+        a.rec[slot] = r;
+      }
+    }
+    st.ordinal += 1;
+    st.r = rng.threshold(static_cast<uint64_t>(st.ordinal));
+    n_s = norm2(ps);
+    tau_rem = tau_rem - tau;
+  }
+}
+
+struct StepPlan {
+  int n_sub;  // substeps per step
+  int K;      // Taylor order of a substep
+  double h;   // substep length
+};
+
+// Substeps and polynomial order of step j from the norm bound of its H_eff.
+template <int N>
+__device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&uj)[N]) {
+  double b = a.b0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) b += fabs(uj[i]) * a.bc[i];
+  const double x = b * a.dt;
+  StepPlan p;
+  p.n_sub = x > kMaxStepNorm ? static_cast<int>(ceil(x / kMaxStepNorm)) : 1;
+  if (p.n_sub > kMaxSubsteps) {
+    atomicOr(a.err, kErrTaylorOrder);
+    p.n_sub = kMaxSubsteps;
+  }
+  p.h = a.dt / static_cast<double>(p.n_sub);
+  p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
+  if (p.K < 0) {
+    atomicOr(a.err, kErrTaylorOrder);
+    p.K = a.kmax;
+  }
+  return p;
+}
+
+// Advance across the whole step j (its substeps).
+template <typename real, int R, int WS, int NC, int DIR>
+__device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC> &op,
+                                             const PassArgs &a, cx<real> *v,
+                                             cx<real> (&psi)[R], TrajMeta &st,
+                                             const Stream &rng, int j, const StepPlan &p,
+                                             int k, int lane) {
+  for (int s = 0; s < p.n_sub; ++s) {
+    const double t0 = DIR == 0 ? static_cast<double>(j) * a.dt + s * p.h
+                               : static_cast<double>(j + 1) * a.dt - s * p.h;
+    advance<real, R, WS, NC, DIR>(op, a, v, psi, st, rng, j, t0, p.h, p.K, k, lane);
+  }
+}
+
+// ---- plain forward / backward passes --------------------------------------
+template <typename real, int R, int WS, int NC, int DIR>
+__global__ __launch_bounds__(kWave *kWavesPerBlock) void k_pass(PassArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  cx<real> *v = reinterpret_cast<cx<real> *>(smem_raw) + wib * (R * kWave + 1);
+  if (lane == 0) v[R * kWave] = cx<real>{0, 0};  // zero element read by padding slots
+  LaneOp<real, R, WS, NC> op;
+  op.load(a, lane);
+  const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
+  cx<real> *chi = static_cast<cx<real> *>(a.chi);
+  const int nwaves = gridDim.x * (blockDim.x / kWave);
+  for (int k = blockIdx.x * (blockDim.x / kWave) + wib; k < a.M; k += nwaves) {
+    cx<real> psi[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) psi[m] = start[lane + kWave * m];
+    const Stream rng = make_stream(a, k, DIR);
+    TrajMeta st;
+    st.nrm2 = norm2(psi);
+    st.ordinal = 0;
+    st.r = rng.threshold(0);
+    double tau_re = 0.0, tau_im = 0.0;
+    if (DIR == 1) {
+      tau_re = a.tau_in[2 * k];
+      tau_im = a.tau_in[2 * k + 1];
+    }
+    constexpr int NCX = NC > 0 ? NC : 1;
+    double un[NCX];  // pulses of the next step, loaded one step ahead (rows padded)
+    {
+      const int j0 = DIR == 0 ? 0 : a.nt - 1;
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + j0];
+    }
+    for (int jj = 0; jj < a.nt; ++jj) {
+      const int j = DIR == 0 ? jj : a.nt - 1 - jj;
+      double uj[NCX];
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) uj[i] = un[i];
+      if (jj + 1 < a.nt) {
+        const int jn = DIR == 0 ? j + 1 : j - 1;
+#pragma unroll
+        for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + jn];
+      }
+      op.set_pulses(uj, a.wc);
+      const StepPlan p = plan_step(a, uj);
+      advance_step<real, R, WS, NC, DIR>(op, a, v, psi, st, rng, j, p, k, lane);
+      if (DIR == 1) {
+        // chi_k(t_j) = tau_k chi_hat_k(t_j)
+        const double inv = 1.0 / sqrt(st.nrm2);
+        const size_t base = (static_cast<size_t>(j) * a.M + k) * a.d;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          const int row = lane + kWave * m;
+          if (row < a.d) {
+            const double px = psi[m].x * inv, py = psi[m].y * inv;
+            chi[base + row] = cx<real>{static_cast<real>(tau_re * px - tau_im * py),
+                                       static_cast<real>(tau_re * py + tau_im * px)};
+          }
+        }
+      }
+    }
+    if (DIR == 0) {
+      const double inv = 1.0 / sqrt(st.nrm2);
+      double tr = 0.0, ti = 0.0;
+      cx<real> *psiT = static_cast<cx<real> *>(a.psiT);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int row = lane + kWave * m;
+        const double px = psi[m].x * inv, py = psi[m].y * inv;
+        // tau_k = <tgt|psi_hat> = sum conj(tgt) psi_hat
+        const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
+        tr = fma(gx, px, fma(gy, py, tr));
+        ti = fma(gx, py, fma(-gy, px, ti));
+        if (psiT != nullptr && row < a.d)
+          psiT[static_cast<size_t>(k) * a.d + row] =
+              cx<real>{static_cast<real>(px), static_cast<real>(py)};
+      }
+      tr = wave_sum(tr);
+      ti = wave_sum(ti);
+      if (lane == 0 && a.tau_out != nullptr) {
+        a.tau_out[2 * k] = tr;
+        a.tau_out[2 * k + 1] = ti;
+      }
+    }
+  }
+}
+
+// ---- slot initialisation for the Krotov pass ---------------------------------
+// slots[j][b][c]: the sentinel for the nblk live blocks, zero for the others.
+__global__ void k_fill_slots(unsigned long long *slots, long long n, int nblk, int ncx) {
+  const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+       i += stride) {
+    const int b = static_cast<int>((i / ncx) % kMaxBlocks);
+    slots[i] = b < nblk ? kSlotEmpty : 0ull;
+  }
+}
+
+// Per-lane share of Im <chi|H_i|psi_hat> for every control slot c, added to pc.
+// v holds the (unnormalised) state, inv = 1/||psi||.
+template <typename real, int R, int WS, int NC>
+__device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC> &op,
+                                             const cx<real> *v, const cx<real> (&ch)[R],
+                                             double inv, double *pc) {
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const cx<real> q = op.cval_at(c, m);
+      const cx<real> b = v[op.ccol[c][m]];
+      const double hx = static_cast<double>(q.x) * b.x - static_cast<double>(q.y) * b.y;
+      const double hy = static_cast<double>(q.x) * b.y + static_cast<double>(q.y) * b.x;
+      // Im(conj(chi) h) = chi.x h.y - chi.y h.x
+      pc[c] = fma(inv * static_cast<double>(ch[m].x), hy, pc[c]);
+      pc[c] = fma(-inv * static_cast<double>(ch[m].y), hx, pc[c]);
+    }
+  }
+}
+
+template <typename real, int R>
+__device__ __forceinline__ void load_costate(const PassArgs &a, int j, int k, int lane,
+                                             cx<real> (&ch)[R]) {
+  const cx<real> *chi = static_cast<const cx<real> *>(a.chi);
+  const size_t base = (static_cast<size_t>(j) * a.M + k) * a.d;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int row = lane + kWave * m;
+    ch[m] = row < a.d ? chi[base + row] : cx<real>{0, 0};
+  }
+}
+
+// ---- sequential Krotov forward pass (cooperative launch) ---------------------
+template <typename real, int R, int WS, int NC>
+__global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int NCX = NC > 0 ? NC : 1;
+  __shared__ double wpart[kWavesPerBlock][NCX];
+  __shared__ double s_upd[NCX];
+  __shared__ int s_abort;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  const int Tw = a.traj_per_wave;
+  const int wave = blockIdx.x * kWavesPerBlock + wib;
+  // LDS per wave: work vector, then Tw state vectors, then Tw metadata
+  unsigned char *wbase =
+      smem_raw + static_cast<size_t>(wib) *
+                     ((static_cast<size_t>(1 + Tw) * R * kWave + 1) * sizeof(cx<real>) +
+                      static_cast<size_t>(Tw) * sizeof(TrajMeta));
+  cx<real> *v = reinterpret_cast<cx<real> *>(wbase);
+  cx<real> *states = v + R * kWave + 1;
+  if (lane == 0) v[R * kWave] = cx<real>{0, 0};  // zero element read by padding slots
+  TrajMeta *meta = reinterpret_cast<TrajMeta *>(states + static_cast<size_t>(Tw) * R * kWave);
+
+  LaneOp<real, R, WS, NC> op;
+  op.load(a, lane);
+  const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
+  if (threadIdx.x == 0) s_abort = 0;
+
+  // ---- start states and the first partial (t_0) ----
+  double pc[NCX];
+#pragma unroll
+  for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
+  for (int t = 0; t < Tw; ++t) {
+    const int k = wave * Tw + t;
+    cx<real> p[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) p[m] = start[lane + kWave * m];
+    store_lds(states + t * R * kWave, p, lane);
+    const double n = norm2(p);
+    if (lane == 0) {
+      TrajMeta st;
+      st.nrm2 = n;
+      st.ordinal = 0;
+      st.r = k < a.M ? make_stream(a, k, 0).threshold(0) : 0.0;
+      meta[t] = st;
+    }
+    if (k < a.M) {
+      cx<real> ch[R];
+      load_costate<real, R>(a, 0, k, lane, ch);
+      store_lds(v, p, lane);
+      wave_sync();
+      krotov_share<real, R, WS, NC>(op, v, ch, 1.0 / sqrt(n), pc);
+      wave_sync();
+    }
+  }
+
+  // pulse inputs of the step about to be updated (j = 0); rows past n_ctrl are
+  // zero padding (lambda padded with 1), so no guards are needed
+  double uo[NCX], sf[NCX];
+#pragma unroll
+  for (int i = 0; i < NCX; ++i) {
+    uo[i] = a.u_old[static_cast<size_t>(i) * a.nt];
+    sf[i] = a.S[static_cast<size_t>(i) * a.nt] / (a.lam[i] * a.M);
+  }
+
+  for (int j = 0; j < a.nt; ++j) {
+    // ---- reduce the partial of t_j: waves -> block (fixed order) -> publish ----
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double s = wave_sum(pc[c]);
+      if (lane == 0) wpart[wib][c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NCX) {  // control i's block partial (zero for padding controls)
+      const int i = threadIdx.x;
+      double s = 0.0;
+      for (int w = 0; w < kWavesPerBlock; ++w)
+        for (int c = i * a.wc; c < (i + 1) * a.wc && c < NC; ++c) s += wpart[w][c];
+      __hip_atomic_store(&a.slots[(static_cast<size_t>(j) * kMaxBlocks + blockIdx.x) * NCX + i],
+                         __double_as_longlong(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // ---- wait for every block's partial of step j; sum in block order --------
+    if (wib == 0 && a.n_ctrl > 0) {
+      // every lane reads kPollPerLane blocks' slots in one batch of loads; slots of
+      // blocks past the grid hold zero, so the sum over all kMaxBlocks is exact
+      double acc[NCX];
+      long long spins = 0;
+      bool abort = false;
+      for (;;) {
+        unsigned long long bits[kPollPerLane][NCX];
+        const unsigned long long *row = a.slots + static_cast<size_t>(j) * kMaxBlocks * NCX;
+#pragma unroll
+        for (int q = 0; q < kPollPerLane; ++q)
+#pragma unroll
+          for (int c = 0; c < NCX; ++c)
+            bits[q][c] = __hip_atomic_load(&row[(lane + kWave * q) * NCX + c], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        int missing = 0;
+#pragma unroll
+        for (int q = 0; q < kPollPerLane; ++q)
+#pragma unroll
+          for (int c = 0; c < NCX; ++c) missing |= bits[q][c] == kSlotEmpty;
+        if (!__any(missing)) {
+#pragma unroll
+          for (int c = 0; c < NCX; ++c) {
+            acc[c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kPollPerLane; ++q)
+              acc[c] += __longlong_as_double(static_cast<long long>(bits[q][c]));
+          }
+          break;
+        }
+        if (++spins > a.spin_limit ||
+            (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+             kErrSyncTimeout)) {
+#pragma unroll
+          for (int c = 0; c < NCX; ++c) acc[c] = 0.0;
+          abort = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+#pragma unroll
+      for (int c = 0; c < NCX; ++c) {
+        const double sc = wave_sum(acc[c]);
+        if (lane == 0) s_upd[c] = sc;
+      }
+      if (abort && lane == 0) {
+        atomicOr(a.err, kErrSyncTimeout);
+        s_abort = 1;
+      }
+    }
+    __syncthreads();
+    if (s_abort) return;  // uniform across the block
+    // ---- pulse update of interval j ---------------------------------------------
+    double uj[NCX];
+#pragma unroll
+    for (int i = 0; i < NCX; ++i) uj[i] = uo[i] + sf[i] * s_upd[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) a.u_new[static_cast<size_t>(i) * a.nt + j] = uj[i];
+    }
+    if (j + 1 < a.nt) {  // prefetch the next step's pulse inputs
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) {
+        const size_t ij = static_cast<size_t>(i) * a.nt + j + 1;
+        uo[i] = a.u_old[ij];
+        sf[i] = a.S[ij] / (a.lam[i] * a.M);
+      }
+    }
+    op.set_pulses(uj, a.wc);
+    const StepPlan p = plan_step(a, uj);
+    // ---- advance every trajectory; form the partial of t_{j+1} ----------------
+#pragma unroll
+    for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
+    for (int t = 0; t < Tw; ++t) {
+      const int k = wave * Tw + t;
+      if (k >= a.M) break;
+      cx<real> *sv = states + t * R * kWave;
+      cx<real> ch[R];
+      if (j + 1 < a.nt) load_costate<real, R>(a, j + 1, k, lane, ch);
+      cx<real> psi[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = sv[lane + kWave * m];
+      TrajMeta st = meta[t];
+      const Stream rng = make_stream(a, k, 0);
+      advance_step<real, R, WS, NC, 0>(op, a, v, psi, st, rng, j, p, k, lane);
+      wave_sync();
+      store_lds(sv, psi, lane);
+      if (lane == 0) meta[t] = st;
+      if (j + 1 < a.nt) {
+        store_lds(v, psi, lane);
+        wave_sync();
+        krotov_share<real, R, WS, NC>(op, v, ch, 1.0 / sqrt(st.nrm2), pc);
+      }
+      wave_sync();
+    }
+  }
+  // ---- functional: tau_k = <tgt|psi_hat_k(T)> and the final states ----------
+  cx<real> *psiT = static_cast<cx<real> *>(a.psiT);
+  for (int t = 0; t < Tw; ++t) {
+    const int k = wave * Tw + t;
+    if (k >= a.M) break;
+    const cx<real> *sv = states + t * R * kWave;
+    const double inv = 1.0 / sqrt(meta[t].nrm2);
+    double tr = 0.0, ti = 0.0;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int row = lane + kWave * m;
+      const cx<real> q = sv[row];
+      const double px = q.x * inv, py = q.y * inv;
+      const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
+      tr = fma(gx, px, fma(gy, py, tr));
+      ti = fma(gx, py, fma(-gy, px, ti));
+      if (psiT != nullptr && row < a.d)
+        psiT[static_cast<size_t>(k) * a.d + row] =
+            cx<real>{static_cast<real>(px), static_cast<real>(py)};
+    }
+    tr = wave_sum(tr);
+    ti = wave_sum(ti);
+    if (lane == 0 && a.tau_out != nullptr) {
+      a.tau_out[2 * k] = tr;
+      a.tau_out[2 * k + 1] = ti;
+    }
+  }
+}
+
+// J_T = 1 - (1/M) sum_k |tau_k|^2 (trajectory functional, Sec. 2.3); fixed order.
+__global__ __launch_bounds__(256) void k_functional(const double *tau, int M, double *J) {
+  __shared__ double part[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < M; k += 256)
+    s = fma(tau[2 * k], tau[2 * k], fma(tau[2 * k + 1], tau[2 * k + 1], s));
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *J = 1.0 - part[0] / static_cast<double>(M);
+}
+
+template <typename real, int R, int WS, int NC>
+Variant make_variant(const char *name) {
+  Variant v;
+  v.name = name;
+  v.precision = sizeof(real) == 8 ? TK_FP64 : TK_FP32;
+  v.R = R;
+  v.WS = WS;
+  v.NC = NC;
+  v.k_forward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, 0>);
+  v.k_backward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, 1>);
+  v.k_krotov = reinterpret_cast<const void *>(&k_krotov<real, R, WS, NC>);
+  v.k_fill = reinterpret_cast<const void *>(&k_fill_slots);
+  return v;
+}
+
+}  // namespace
+
+const Variant *variants(int *count) {
+  static const Variant table[] = {
+      make_variant<double, 1, 4, 2>("fp64 R=1 WS=4 NC=2"),
+      make_variant<double, 2, 4, 2>("fp64 R=2 WS=4 NC=2"),
+      make_variant<double, 4, 6, 3>("fp64 R=4 WS=6 NC=3"),
+      make_variant<double, 4, 8, 4>("fp64 R=4 WS=8 NC=4"),
+      make_variant<float, 1, 4, 2>("fp32 R=1 WS=4 NC=2"),
+      make_variant<float, 2, 4, 2>("fp32 R=2 WS=4 NC=2"),
+      make_variant<float, 4, 6, 3>("fp32 R=4 WS=6 NC=3"),
+      make_variant<float, 4, 8, 4>("fp32 R=4 WS=8 NC=4"),
+  };
+  *count = static_cast<int>(sizeof(table) / sizeof(table[0]));
+  return table;
+}
+
+const void *functional_kernel() { return reinterpret_cast<const void *>(&k_functional); }
+
+size_t pass_lds_bytes(const Variant &v) {
+  const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
+  return (static_cast<size_t>(v.R) * kWave + 1) * cplx;
+}
+
+size_t krotov_lds_bytes(const Variant &v, int traj_per_wave) {
+  const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
+  return (static_cast<size_t>(1 + traj_per_wave) * v.R * kWave + 1) * cplx +
+         static_cast<size_t>(traj_per_wave) * sizeof(TrajMeta);
+}
+
+}  // namespace tk

@@ -1,0 +1,391 @@
+"""Python binding of libtrajkrotov (ctypes; argument marshalling only).
+
+The module-level functions carry the C names of ``include/trajkrotov.h`` and
+take/return NumPy arrays; ``Context`` is a small convenience object over them.
+Every computation runs in the HIP library: if the shared library is missing
+the import of this module fails (build it with
+``python -m paper_1801_04382_amd.build``).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from .build import lib_path
+
+# ---------------------------------------------------------------------------
+# C types
+# ---------------------------------------------------------------------------
+TK_OK = 0
+TK_EINVAL = -1
+TK_EDIM = -2
+TK_ENOMEM = -3
+TK_EHIP = -4
+TK_ENOTHERM = -5
+TK_ERECCAP = -6
+TK_ENUMERIC = -7
+TK_ESTATE = -8
+TK_ENODEV = -9
+TK_EUNSUPPORTED = -10
+
+TK_FP64 = 0
+TK_FP32 = 1
+
+TK_KERNEL_FORWARD = 0
+TK_KERNEL_BACKWARD = 1
+TK_KERNEL_KROTOV = 2
+
+STATUS_NAMES = {
+    0: "TK_OK", -1: "TK_EINVAL", -2: "TK_EDIM", -3: "TK_ENOMEM", -4: "TK_EHIP",
+    -5: "TK_ENOTHERM", -6: "TK_ERECCAP", -7: "TK_ENUMERIC", -8: "TK_ESTATE",
+    -9: "TK_ENODEV", -10: "TK_EUNSUPPORTED",
+}
+
+
+class tk_csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("indptr", ctypes.POINTER(ctypes.c_int64)),
+                ("indices", ctypes.POINTER(ctypes.c_int32)),
+                ("values", ctypes.POINTER(ctypes.c_double))]
+
+
+class tk_jump(ctypes.Structure):
+    _fields_ = [("instance", ctypes.c_int32), ("traj", ctypes.c_int32),
+                ("step", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("ordinal", ctypes.c_int32), ("direction", ctypes.c_int32),
+                ("iteration", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t", ctypes.c_double)]
+
+
+class tk_kernel_timing(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("launches", ctypes.c_int64),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("traj_steps", ctypes.c_int64)]
+
+
+JUMP_DTYPE = np.dtype([("instance", np.int32), ("traj", np.int32), ("step", np.int32),
+                       ("op", np.int32), ("ordinal", np.int32), ("direction", np.int32),
+                       ("iteration", np.int32), ("reserved", np.int32), ("t", np.float64)])
+assert JUMP_DTYPE.itemsize == ctypes.sizeof(tk_jump)
+
+_P = ctypes.POINTER
+_dp = _P(ctypes.c_double)
+_ctx_p = ctypes.c_void_p
+
+_SIGNATURES = {
+    "tk_version": (ctypes.c_char_p, []),
+    "tk_last_error": (ctypes.c_char_p, [_ctx_p]),
+    "tk_create": (ctypes.c_int, [_P(_ctx_p), ctypes.c_int, ctypes.c_int]),
+    "tk_destroy": (None, [_ctx_p]),
+    "tk_set_system": (ctypes.c_int, [_ctx_p, ctypes.c_int64, _P(tk_csr), ctypes.c_int32,
+                                     _P(tk_csr), ctypes.c_int32, _P(tk_csr)]),
+    "tk_set_states": (ctypes.c_int, [_ctx_p, _dp, _dp]),
+    "tk_set_pulses": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_double, _dp, _dp, _dp]),
+    "tk_get_pulses": (ctypes.c_int, [_ctx_p, _dp]),
+    "tk_propagate_forward": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64,
+                                            ctypes.c_uint64, _dp, _dp, _P(tk_jump),
+                                            ctypes.c_int64, _P(ctypes.c_int64)]),
+    "tk_propagate_backward": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64,
+                                             ctypes.c_uint64, _dp, _P(tk_jump), ctypes.c_int64,
+                                             _P(ctypes.c_int64)]),
+    "tk_get_costate": (ctypes.c_int, [_ctx_p, ctypes.c_int32, _dp]),
+    "tk_functional": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64,
+                                     _dp, _dp]),
+    "tk_krotov_iterate": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_int32, _dp, _P(tk_jump),
+                                         ctypes.c_int64, _P(ctypes.c_int64)]),
+    "tk_set_timing": (ctypes.c_int, [_ctx_p, ctypes.c_int]),
+    "tk_get_timing": (ctypes.c_int, [_ctx_p, ctypes.c_int, _P(tk_kernel_timing)]),
+    "tk_reset_timing": (ctypes.c_int, [_ctx_p]),
+    "tk_get_launch_info": (ctypes.c_int, [_ctx_p, _P(ctypes.c_char_p), _P(ctypes.c_int32),
+                                          _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+}
+
+EXPORTED = tuple(_SIGNATURES)
+
+
+def load_library(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libtrajkrotov (``TRAJKROTOV_LIB`` may name another build of it)."""
+    path = path or os.environ.get("TRAJKROTOV_LIB") or lib_path()
+    if not os.path.exists(path):
+        raise ImportError(f"libtrajkrotov not built ({path}); run "
+                          "`python -m paper_1801_04382_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+class TkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(ctx, code: int) -> int:
+    if code != TK_OK:
+        msg = _lib.tk_last_error(ctx).decode() if ctx else ""
+        raise TkError(code, msg)
+    return code
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+def _cplx(v, n: Optional[int] = None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.complex128))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} complex entries, got {a.size}")
+    return a.view(np.float64)
+
+
+class _CsrHolder:
+    """Keeps the arrays a tk_csr points at alive."""
+
+    def __init__(self, m, d: int):
+        import scipy.sparse as sp
+        m = sp.csr_matrix(m, dtype=np.complex128)
+        if m.shape != (d, d):
+            raise ValueError(f"operator shape {m.shape} != ({d}, {d})")
+        self.indptr = np.ascontiguousarray(m.indptr, dtype=np.int64)
+        self.indices = np.ascontiguousarray(m.indices, dtype=np.int32)
+        self.values = np.ascontiguousarray(m.data, dtype=np.complex128).view(np.float64)
+        self.c = tk_csr(d, int(m.nnz), self.indptr.ctypes.data_as(_P(ctypes.c_int64)),
+                        self.indices.ctypes.data_as(_P(ctypes.c_int32)),
+                        self.values.ctypes.data_as(_dp))
+
+
+def records_array(buf: np.ndarray, n: int) -> np.ndarray:
+    """Jump records sorted by (iteration, direction, trajectory, ordinal)."""
+    rec = buf[:n].copy()
+    order = np.lexsort((rec["ordinal"], rec["traj"], rec["direction"], rec["iteration"]))
+    return rec[order]
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def tk_version() -> str:
+    return _lib.tk_version().decode()
+
+
+def tk_create(device: int = 0, precision: int = TK_FP64) -> int:
+    h = _ctx_p()
+    code = _lib.tk_create(ctypes.byref(h), device, precision)
+    if code != TK_OK:
+        raise TkError(code, "tk_create failed")
+    return h.value
+
+
+def tk_destroy(ctx: int) -> None:
+    _lib.tk_destroy(ctx)
+
+
+def tk_last_error(ctx: int) -> str:
+    return _lib.tk_last_error(ctx).decode()
+
+
+def tk_set_system(ctx: int, H0, H_ctrl: Sequence, L_jump: Sequence) -> None:
+    d = H0.shape[0]
+    h0 = _CsrHolder(H0, d)
+    hc = [_CsrHolder(h, d) for h in H_ctrl]
+    lj = [_CsrHolder(l, d) for l in L_jump]
+    hc_arr = (tk_csr * max(len(hc), 1))(*[h.c for h in hc])
+    lj_arr = (tk_csr * max(len(lj), 1))(*[h.c for h in lj])
+    _check(ctx, _lib.tk_set_system(ctx, d, ctypes.byref(h0.c), len(hc), hc_arr, len(lj), lj_arr))
+
+
+def tk_set_states(ctx: int, psi0, psi_tgt) -> None:
+    p = _cplx(psi0)
+    t = _cplx(psi_tgt, p.size // 2)
+    _check(ctx, _lib.tk_set_states(ctx, _dptr(p), _dptr(t)))
+
+
+def tk_set_pulses(ctx: int, u: np.ndarray, T: float, S=None, lam=None) -> None:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    nt = u.shape[1] if u.ndim == 2 else int(u.size)
+    s = None if S is None else np.ascontiguousarray(S, dtype=np.float64).reshape(u.shape)
+    l_ = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+    _check(ctx, _lib.tk_set_pulses(ctx, nt, float(T), _dptr(u), _dptr(s), _dptr(l_)))
+
+
+def tk_get_pulses(ctx: int, n_ctrl: int, nt: int) -> np.ndarray:
+    out = np.zeros((n_ctrl, nt))
+    _check(ctx, _lib.tk_get_pulses(ctx, _dptr(out)))
+    return out
+
+
+def _rec_buffer(cap: int):
+    buf = np.zeros(max(cap, 1), dtype=JUMP_DTYPE)
+    return buf, buf.ctypes.data_as(_P(tk_jump))
+
+
+def tk_propagate_forward(ctx: int, M: int, seed: int, iteration: int, d: int,
+                         want_states: bool = True, rec_cap: int = 0):
+    psiT = np.zeros(M * d, dtype=np.complex128) if want_states else None
+    tau = np.zeros(M, dtype=np.complex128)
+    buf, bp = _rec_buffer(rec_cap)
+    n = ctypes.c_int64(0)
+    _check(ctx, _lib.tk_propagate_forward(
+        ctx, M, seed, iteration, None if psiT is None else _dptr(psiT.view(np.float64)),
+        _dptr(tau.view(np.float64)), bp if rec_cap > 0 else None, rec_cap, ctypes.byref(n)))
+    return (None if psiT is None else psiT.reshape(M, d)), tau, records_array(buf, min(n.value, rec_cap)), n.value
+
+
+def tk_propagate_backward(ctx: int, M: int, seed: int, iteration: int, tau=None,
+                          rec_cap: int = 0):
+    t = None if tau is None else _cplx(tau, M)
+    buf, bp = _rec_buffer(rec_cap)
+    n = ctypes.c_int64(0)
+    _check(ctx, _lib.tk_propagate_backward(ctx, M, seed, iteration, _dptr(t),
+                                           bp if rec_cap > 0 else None, rec_cap,
+                                           ctypes.byref(n)))
+    return records_array(buf, min(n.value, rec_cap)), n.value
+
+
+def tk_get_costate(ctx: int, j: int, M: int, d: int) -> np.ndarray:
+    out = np.zeros(M * d, dtype=np.complex128)
+    _check(ctx, _lib.tk_get_costate(ctx, j, _dptr(out.view(np.float64))))
+    return out.reshape(M, d)
+
+
+def tk_functional(ctx: int, M: int, seed: int, iteration: int = 0):
+    J = ctypes.c_double(0.0)
+    tau = np.zeros(M, dtype=np.complex128)
+    _check(ctx, _lib.tk_functional(ctx, M, seed, iteration, ctypes.byref(J),
+                                   _dptr(tau.view(np.float64))))
+    return J.value, tau
+
+
+def tk_krotov_iterate(ctx: int, M: int, seed: int, n_iter: int, first_iteration: int = 0,
+                      rec_cap: int = 0):
+    nout = n_iter + 1 if first_iteration == 0 else n_iter
+    J = np.zeros(max(nout, 1))
+    buf, bp = _rec_buffer(rec_cap)
+    n = ctypes.c_int64(0)
+    _check(ctx, _lib.tk_krotov_iterate(ctx, M, seed, first_iteration, n_iter, _dptr(J),
+                                       bp if rec_cap > 0 else None, rec_cap, ctypes.byref(n)))
+    return J[:nout], records_array(buf, min(n.value, rec_cap)), n.value
+
+
+def tk_set_timing(ctx: int, enable: bool) -> None:
+    _check(ctx, _lib.tk_set_timing(ctx, 1 if enable else 0))
+
+
+def tk_get_timing(ctx: int, kind: int) -> dict:
+    t = tk_kernel_timing()
+    _check(ctx, _lib.tk_get_timing(ctx, kind, ctypes.byref(t)))
+    return {"ms_total": t.ms_total, "launches": t.launches, "flops": t.flops,
+            "bytes": t.bytes, "traj_steps": t.traj_steps}
+
+
+def tk_reset_timing(ctx: int) -> None:
+    _check(ctx, _lib.tk_reset_timing(ctx))
+
+
+def tk_get_launch_info(ctx: int) -> dict:
+    name = ctypes.c_char_p()
+    wpb, tw, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, _lib.tk_get_launch_info(ctx, ctypes.byref(name), ctypes.byref(wpb),
+                                        ctypes.byref(tw), ctypes.byref(nb)))
+    return {"variant": name.value.decode() if name.value else "",
+            "waves_per_block": wpb.value, "traj_per_wave": tw.value, "blocks": nb.value}
+
+
+# ---------------------------------------------------------------------------
+# convenience object
+# ---------------------------------------------------------------------------
+
+class Context:
+    """One library context (device memory, stream, current system and pulses)."""
+
+    def __init__(self, device: int = 0, precision: str = "fp64"):
+        prec = {"fp64": TK_FP64, "fp32": TK_FP32}[precision]
+        self.h = tk_create(device, prec)
+        self.precision = precision
+        self.d = 0
+        self.n_ctrl = 0
+        self.nt = 0
+
+    def close(self):
+        if self.h:
+            tk_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_system(self, H0, H_ctrl, L_jump):
+        tk_set_system(self.h, H0, H_ctrl, L_jump)
+        self.d = H0.shape[0]
+        self.n_ctrl = len(H_ctrl)
+
+    def set_states(self, psi0, psi_tgt):
+        tk_set_states(self.h, psi0, psi_tgt)
+
+    def set_pulses(self, u, T, S=None, lam=None):
+        u = np.asarray(u, dtype=np.float64).reshape(self.n_ctrl, -1) if self.n_ctrl else \
+            np.zeros((0, int(np.asarray(u).shape[-1])))
+        tk_set_pulses(self.h, u, T, S, lam)
+        self.nt = u.shape[1]
+
+    def load(self, w):
+        """Set system, states and pulses from a workloads.Workload."""
+        self.set_system(w.H0, w.H_ctrl, w.L_jump)
+        self.set_states(w.psi0, w.psi_tgt)
+        self.set_pulses(w.u0, w.T, w.S, w.lam)
+
+    def get_pulses(self) -> np.ndarray:
+        return tk_get_pulses(self.h, self.n_ctrl, self.nt)
+
+    def propagate_forward(self, M, seed, iteration=0, want_states=True, rec_cap=None):
+        cap = 4 * M + 64 if rec_cap is None else rec_cap
+        return tk_propagate_forward(self.h, M, seed, iteration, self.d, want_states, cap)
+
+    def propagate_backward(self, M, seed, iteration, tau=None, rec_cap=None):
+        cap = 4 * M + 64 if rec_cap is None else rec_cap
+        return tk_propagate_backward(self.h, M, seed, iteration, tau, cap)
+
+    def get_costate(self, j, M):
+        return tk_get_costate(self.h, j, M, self.d)
+
+    def functional(self, M, seed, iteration=0):
+        return tk_functional(self.h, M, seed, iteration)
+
+    def krotov_iterate(self, M, seed, n_iter, first_iteration=0, rec_cap=None):
+        cap = (8 * M + 64) * (n_iter + 1) if rec_cap is None else rec_cap
+        return tk_krotov_iterate(self.h, M, seed, n_iter, first_iteration, cap)
+
+    def set_timing(self, enable=True):
+        tk_set_timing(self.h, enable)
+
+    def timing(self, kind):
+        return tk_get_timing(self.h, kind)
+
+    def reset_timing(self):
+        tk_reset_timing(self.h)
+
+    def launch_info(self):
+        return tk_get_launch_info(self.h)
