@@ -32,6 +32,13 @@
  *     length n is a double array of length 2n.
  *   - Time steps are 0-based: step j is the interval (j dt, (j+1) dt], dt = T/nt.
  *   - One context per host thread; a context owns all of its device memory.
+ *   - The sequential Krotov pass is one persistent launch whose blocks wait
+ *     for each other every time step; it is launched with
+ *     hipLaunchCooperativeKernel (all blocks co-resident or a launch error).
+ *     With the environment variable TK_KROTOV_LAUNCH=plain at tk_create the
+ *     same grid (sized to fit the device) is launched normally, for tools
+ *     that do not handle cooperative launches; a block that waits longer than
+ *     a fixed spin limit aborts the pass with TK_EHIP instead of hanging.
  *   - Random numbers: Philox4x64-10 (Salmon et al., SC'11).  Block n of
  *     trajectory k uses counter [n, iteration, direction, 0] and key
  *     [seed, (instance << 32) | k]; word 0 is the norm threshold of waiting

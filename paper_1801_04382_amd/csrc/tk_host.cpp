@@ -6,6 +6,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -246,6 +247,7 @@ struct tk_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   tk_kernel_timing tstat[TK_KERNEL_COUNT] = {};
   int last_wpb = 0, last_tw = 0, last_blocks = 0;
+  bool cooperative = true;  // launch the Krotov pass with hipLaunchCooperativeKernel
 
   size_t bulk_cplx() const { return precision == TK_FP64 ? 16 : 8; }
 };
@@ -409,18 +411,46 @@ int taylor_order_host(double x, double tol, int kmax) {
   return kmax;
 }
 
+double step_tol(const tk_ctx *c) { return c->precision == TK_FP64 ? 1e-16 : 6e-8; }
+
+// Substeps and Taylor order of step j for pulses u (the kernels' rule without
+// the term-buffer limit).
+void plan_step_host(const tk_ctx *c, const std::vector<double> &u, int j, int *n_sub, int *K) {
+  double b = c->b0;
+  for (int i = 0; i < c->n_ctrl; ++i)
+    b += std::fabs(u[static_cast<size_t>(i) * c->nt + j]) * c->bc[i];
+  const double x = b * (c->T / c->nt);
+  *n_sub = x > tk::kMaxStepNorm ? static_cast<int>(std::ceil(x / tk::kMaxStepNorm)) : 1;
+  *K = taylor_order_host(x / *n_sub, step_tol(c), tk::kMaxTaylor);
+}
+
+// Term vectors a pass needs: the largest order over its steps, plus one for
+// the zeroth term and `margin` for pulses that grow during a Krotov pass.
+int plan_kbuf(const tk_ctx *c, const std::vector<double> &u, int margin) {
+  int kmax = 1;
+  for (int j = 0; j < c->nt; ++j) {
+    int n_sub, K;
+    plan_step_host(c, u, j, &n_sub, &K);
+    kmax = std::max(kmax, K);
+  }
+  return std::min(kmax + 1 + margin, tk::kMaxTaylor + 1);
+}
+
 double pass_flops(const tk_ctx *c, const std::vector<double> &u, int M) {
   double f = 0.0;
-  const double tol = c->precision == TK_FP64 ? 1e-16 : 6e-8;
   for (int j = 0; j < c->nt; ++j) {
-    double b = c->b0;
-    for (int i = 0; i < c->n_ctrl; ++i) b += std::fabs(u[static_cast<size_t>(i) * c->nt + j]) * c->bc[i];
-    const double x = b * (c->T / c->nt);
-    const int n_sub = x > tk::kMaxStepNorm ? static_cast<int>(std::ceil(x / tk::kMaxStepNorm)) : 1;
-    const int K = taylor_order_host(x / n_sub, tol, tk::kMaxTaylor);
+    int n_sub, K;
+    plan_step_host(c, u, j, &n_sub, &K);
     f += n_sub * (8.0 * K * c->nnz_heff + 8.0 * K * c->d + 4.0 * c->d);
   }
   return f * M;
+}
+
+// Waves per block for a plain pass: as many as fit the LDS (at most 4).
+int pass_waves(const tk_ctx *c, int kbuf) {
+  for (int w = tk::kWavesPerBlock; w >= 1; w /= 2)
+    if (tk::block_lds_bytes(*c->var, w, kbuf, 0) <= tk::kLdsBytes) return w;
+  return 0;
 }
 
 tk::PassArgs base_args(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, bool backward) {
@@ -434,6 +464,7 @@ tk::PassArgs base_args(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, bool
   a.wc = c->wc;
   a.wl = c->wl;
   a.kmax = tk::kMaxTaylor;
+  a.kbuf = plan_kbuf(c, c->u, 0);
   a.dt = c->T / c->nt;
   a.tol = c->precision == TK_FP64 ? 1e-16 : 6e-8;
   a.ftol = c->precision == TK_FP64 ? 4.0 * 0x1.0p-52 : 4.0 * 0x1.0p-23;
@@ -550,12 +581,16 @@ int run_forward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap
   a.tau_out = c->tau.as<double>();
   a.rec = c->rec.as<tk_jump>();
   a.rec_cap = cap;
-  const int blocks = (M + tk::kWavesPerBlock - 1) / tk::kWavesPerBlock;
-  const size_t lds = tk::kWavesPerBlock * tk::pass_lds_bytes(*c->var);
+  const int wpb = pass_waves(c, a.kbuf);
+  if (!wpb) return fail(c, TK_EUNSUPPORTED, "the step's Taylor terms do not fit in LDS");
+  const int blocks = (M + wpb - 1) / wpb;
+  const size_t lds = tk::block_lds_bytes(*c->var, wpb, a.kbuf, 0);
+  TK_HIP(c, hipFuncSetAttribute(c->var->k_forward, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(lds)));
   void *args[] = {&a};
   TimedLaunch tl(c, TK_KERNEL_FORWARD);
-  TK_HIP(c, hipLaunchKernel(c->var->k_forward, dim3(blocks), dim3(tk::kWave * tk::kWavesPerBlock),
-                            args, lds, c->stream));
+  TK_HIP(c, hipLaunchKernel(c->var->k_forward, dim3(blocks), dim3(tk::kWave * wpb), args, lds,
+                            c->stream));
   int rc = tl.finish(static_cast<int64_t>(M) * c->nt, pass_flops(c, c->u, M),
                      static_cast<double>(M) * c->d * c->bulk_cplx());
   if (rc) return rc;
@@ -574,12 +609,16 @@ int run_backward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t ca
   a.chi = c->chi.p;
   a.rec = c->rec.as<tk_jump>();
   a.rec_cap = cap;
-  const int blocks = (M + tk::kWavesPerBlock - 1) / tk::kWavesPerBlock;
-  const size_t lds = tk::kWavesPerBlock * tk::pass_lds_bytes(*c->var);
+  const int wpb = pass_waves(c, a.kbuf);
+  if (!wpb) return fail(c, TK_EUNSUPPORTED, "the step's Taylor terms do not fit in LDS");
+  const int blocks = (M + wpb - 1) / wpb;
+  const size_t lds = tk::block_lds_bytes(*c->var, wpb, a.kbuf, 0);
+  TK_HIP(c, hipFuncSetAttribute(c->var->k_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(lds)));
   void *args[] = {&a};
   TimedLaunch tl(c, TK_KERNEL_BACKWARD);
-  TK_HIP(c, hipLaunchKernel(c->var->k_backward, dim3(blocks), dim3(tk::kWave * tk::kWavesPerBlock),
-                            args, lds, c->stream));
+  TK_HIP(c, hipLaunchKernel(c->var->k_backward, dim3(blocks), dim3(tk::kWave * wpb), args, lds,
+                            c->stream));
   int rc = tl.finish(static_cast<int64_t>(M) * c->nt, pass_flops(c, c->u, M),
                      static_cast<double>(chi_bytes));
   if (rc) return rc;
@@ -589,20 +628,30 @@ int run_backward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t ca
 
 int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap) {
   if (c->chi_M != M) return fail(c, TK_ESTATE, "no costates stored for this M");
-  const int wpb = tk::kWavesPerBlock;
-  int tw = 1, blocks = 0;
+  // pulses grow during the pass: one spare term vector; the kernel adds
+  // substeps if a step would still need more terms
+  const int kbuf = plan_kbuf(c, c->u, 1);
+  int tw = 0, wpb = 0, blocks = 0;
   size_t lds = 0;
-  for (tw = 1; tw <= 64; ++tw) {
-    blocks = (M + wpb * tw - 1) / (wpb * tw);
-    if (blocks > tk::kMaxBlocks) continue;
-    lds = wpb * tk::krotov_lds_bytes(*c->var, tw);
-    if (lds > 160 * 1024) return fail(c, TK_EUNSUPPORTED, "Krotov pass does not fit in LDS");
-    int occ = 0;
-    TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, c->var->k_krotov,
-                                                            tk::kWave * wpb, lds));
-    if (occ > 0 && static_cast<int64_t>(occ) * c->n_cu >= blocks) break;
-  }
-  if (tw > 64) return fail(c, TK_EUNSUPPORTED, "too many trajectories for one cooperative launch");
+  for (int t = 1; t <= 64 && !tw; ++t)
+    for (int w = tk::kWavesPerBlock; w >= 1; w /= 2) {
+      const int b = (M + w * t - 1) / (w * t);
+      const size_t l = tk::block_lds_bytes(*c->var, w, kbuf, t);
+      if (b > tk::kMaxBlocks || l > tk::kLdsBytes) continue;
+      TK_HIP(c, hipFuncSetAttribute(c->var->k_krotov, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(l)));
+      int occ = 0;
+      TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, c->var->k_krotov, tk::kWave * w,
+                                                              l));
+      if (occ > 0 && static_cast<int64_t>(occ) * c->n_cu >= b) {
+        tw = t;
+        wpb = w;
+        blocks = b;
+        lds = l;
+        break;
+      }
+    }
+  if (!tw) return fail(c, TK_EUNSUPPORTED, "too many trajectories for one cooperative launch");
   const int ncx = std::max(c->var->NC, 1);
   const size_t nslot = static_cast<size_t>(c->nt) * tk::kMaxBlocks * ncx;
   TK_HIP(c, c->slots.ensure(nslot * sizeof(unsigned long long)));
@@ -626,13 +675,19 @@ int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap)
   a.lam = c->lam_dev.as<double>();
   a.slots = c->slots.as<unsigned long long>();
   a.traj_per_wave = tw;
+  a.kbuf = kbuf;
   void *args[] = {&a};
   c->last_wpb = wpb;
   c->last_tw = tw;
   c->last_blocks = blocks;
   TimedLaunch tl(c, TK_KERNEL_KROTOV);
-  TK_HIP(c, hipLaunchCooperativeKernel(c->var->k_krotov, dim3(blocks), dim3(tk::kWave * wpb),
-                                       args, lds, c->stream));
+  if (c->cooperative) {
+    TK_HIP(c, hipLaunchCooperativeKernel(c->var->k_krotov, dim3(blocks),
+                                         dim3(tk::kWave * wpb), args, lds, c->stream));
+  } else {  // occupancy was checked above; a stalled grid ends at the spin limit
+    TK_HIP(c, hipLaunchKernel(c->var->k_krotov, dim3(blocks), dim3(tk::kWave * wpb), args, lds,
+                              c->stream));
+  }
   // new pulses become the current ones
   std::vector<double> unew(c->u.size());
   if (!unew.empty()) {
@@ -697,6 +752,8 @@ int tk_create(tk_ctx **out, int device, int precision) {
   if (!c) return TK_ENOMEM;
   c->device = device;
   c->precision = precision;
+  const char *launch = std::getenv("TK_KROTOV_LAUNCH");
+  c->cooperative = !(launch && std::strcmp(launch, "plain") == 0);
   c->n_cu = prop.multiProcessorCount;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {

@@ -13,8 +13,9 @@ constexpr int kWave = 64;          // lanes of a CDNA wavefront
 constexpr int kMaxCtrl = 8;        // controls per system
 constexpr int kMaxJump = 8;        // Lindblad operators per system
 constexpr int kMaxTaylor = 40;     // largest polynomial order of a step
-constexpr int kWavesPerBlock = 4;  // waves per workgroup in every kernel
-constexpr double kMaxStepNorm = 1.0;  // substeps keep ||H_eff|| h at most this
+constexpr int kWavesPerBlock = 4;  // most waves per workgroup (fewer if LDS is short)
+constexpr double kMaxStepNorm = 0.5;  // substeps keep ||H_eff|| h at most this
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 compute unit
 constexpr int kMaxSubsteps = 4096;    // substeps per time step before an error
 constexpr int kPollPerLane = 4;       // blocks polled by one lane in the Krotov pass
 constexpr int kMaxBlocks = kWave * kPollPerLane;  // blocks of one Krotov launch
@@ -29,6 +30,14 @@ constexpr int kErrJumpLoop = 8;      // more jumps in one step than allowed
 // floating-point arithmetic never creates from finite inputs.
 constexpr uint64_t kSlotEmpty = 0xFFF7DEADBEEF5A5Aull;
 
+// Per-trajectory bookkeeping of the MCWF clock (kept in LDS by the Krotov pass).
+struct TrajMeta {
+  double nrm2;  // squared norm of the unnormalised state
+  double r;     // current threshold
+  int ordinal;  // jumps so far in this pass
+  int pad;
+};
+
 // Arguments of every propagation kernel.  Operator slices use the per-lane
 // padded layout [slot][m][lane]: row r = lane + 64 m of the Hilbert space;
 // a complex value is two consecutive reals of the bulk precision.
@@ -41,6 +50,7 @@ struct PassArgs {
   int wc;       // control slots per control (slot c belongs to control c / wc)
   int wl;       // slots per row of each jump operator
   int kmax;     // largest Taylor order allowed
+  int kbuf;     // LDS term buffers per wave: a substep uses at most kbuf - 1 terms
   double dt;    // T / nt
   double tol;   // truncation tolerance of one step (relative)
   double b0;    // bound on ||H0 - (i/2) sum L^+L||_2
@@ -98,9 +108,9 @@ const Variant *variants(int *count);
 // Kernel reducing J_T = 1 - (1/M) sum |tau_k|^2 (one block of 256 threads).
 const void *functional_kernel();
 
-// Per-wave LDS bytes of the Krotov kernel for a variant and Tw trajectories.
-size_t krotov_lds_bytes(const Variant &v, int traj_per_wave);
-// Per-wave LDS bytes of the plain passes.
-size_t pass_lds_bytes(const Variant &v);
+// LDS bytes of one block of `waves` waves: the block's copy of the control
+// slots, then per wave `kbuf` term vectors of 64 R + 1 elements and, for the
+// Krotov pass, `traj_per_wave` state vectors and their bookkeeping.
+size_t block_lds_bytes(const Variant &v, int waves, int kbuf, int traj_per_wave);
 
 }  // namespace tk

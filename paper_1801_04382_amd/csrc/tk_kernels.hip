@@ -5,11 +5,14 @@
 // `l` owns the rows r = l + 64 m (m < R) of the state.  Each lane keeps its
 // rows of the effective Hamiltonian in registers as padded slots: WS static
 // slots (H0 - (i/2) sum L^+L) and NC control slots (H_i, scaled by u_ij once
-// per step).  The state's Taylor terms are exchanged through a per-wave LDS
-// vector (all gathers of a matrix-vector product are issued before the first
-// multiply, so their latencies overlap); norms and overlaps are FP64
-// wavefront reductions in a fixed order (DPP within 16-lane rows, then the
-// four row sums read as scalars), so every lane holds the identical sum.
+// per step; the unscaled values sit in LDS, one copy per block).  Every Taylor
+// term of a substep is written to its own per-wave LDS vector; the next term
+// gathers from it (all gathers of a matrix-vector product are issued before
+// the first multiply, so their latencies overlap).  A padding slot points at
+// a trailing zero element that every lane may read at once.  Norms and
+// overlaps are FP64 wavefront reductions in a fixed order (DPP within 16-lane
+// rows, then the four row sums read as scalars), so every lane holds the
+// identical sum.
 //
 // Step propagator.  exp(-i H_eff h) (forward) or exp(+i H_eff^+ h) (backward)
 // applied as a Taylor polynomial.  The step is split into n_sub equal
@@ -19,11 +22,13 @@
 //
 // Jumps (Sec. 2.1, MCWF steps 3-5 and the remark on precise jump times).  When
 // the norm at the end of a (sub)step is below the threshold r, the crossing
-// time is found by a safeguarded Newton iteration on ||U(tau) psi||^2 - r
-// (bracketed, falling back to bisection), using
-// d||psi||^2/dtau = 2 Im <psi|H_eff|psi> (forward); the jump operator is then
-// drawn with weights ||L_l psi||^2, applied, the state renormalised, and the
-// rest of the substep propagated, so several jumps may fall in one step.
+// time is found by a safeguarded Newton iteration (bracketed, falling back to
+// bisection) on f(s) = ||p(s)||^2 - r, where p(s) = sum_n s^n t_n is the
+// substep's Taylor polynomial evaluated from the stored terms t_n (dense
+// output: U(s tau) psi for s in [0, 1], to the same truncation error), so no
+// step is propagated again.  The jump operator is then drawn with weights
+// ||L_l psi||^2, applied, the state renormalised, and the rest of the substep
+// propagated, so several jumps may fall in one step.
 //
 // Sequential Krotov pass (Sec. 2.2 "sequential", Sec. 2.3 update).  One
 // cooperative persistent launch; waves own `traj_per_wave` trajectories
@@ -148,12 +153,11 @@ struct LaneOp {
   int scol[WS][R];
   cx<real> sval[WS][R];
   int ccol[NCX][R];
-  cx<real> cv[NCX][R];  // control matrix elements scaled by the current pulses
-  const cx<real> *cval;  // unscaled control elements, [c][m][lane] in global memory
+  cx<real> cv[NCX][R];   // control matrix elements scaled by the current pulses
+  const cx<real> *cval;  // unscaled control elements of this lane in LDS, [c][m][lane]
 
-  __device__ void load(const PassArgs &a, int lane) {
+  __device__ void load(const PassArgs &a, const cx<real> *cval_lds, int lane) {
     const cx<real> *sv = static_cast<const cx<real> *>(a.sval);
-    const cx<real> *cvv = static_cast<const cx<real> *>(a.cval);
 #pragma unroll
     for (int s = 0; s < WS; ++s)
 #pragma unroll
@@ -166,11 +170,10 @@ struct LaneOp {
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const int idx = (c * R + m) * kWave + lane;
-        ccol[c][m] = a.ccol[idx];
+        ccol[c][m] = a.ccol[(c * R + m) * kWave + lane];
         cv[c][m] = cx<real>{0, 0};
       }
-    cval = cvv + lane;
+    cval = cval_lds + lane;
   }
 
   // unscaled control element of slot c, row slot m
@@ -235,6 +238,21 @@ __device__ __forceinline__ void store_lds(cx<real> *v, const cx<real> (&p)[R], i
   for (int m = 0; m < R; ++m) v[lane + kWave * m] = p[m];
 }
 
+template <typename real, int R>
+__device__ __forceinline__ void load_lds(const cx<real> *v, cx<real> (&p)[R], int lane) {
+#pragma unroll
+  for (int m = 0; m < R; ++m) p[m] = v[lane + kWave * m];
+}
+
+// Per-wave LDS view: term vectors T_0 .. T_{kbuf-1}, each 64 R + 1 elements
+// (element 64 R is the zero read by padding slots).
+template <typename real, int R>
+struct Terms {
+  static constexpr int kLen = R * kWave + 1;
+  cx<real> *base;
+  __device__ cx<real> *operator[](int n) const { return base + n * kLen; }
+};
+
 // Smallest K with x^(K+1)/(K+1)! e^x <= tol (Taylor remainder bound), or -1.
 __device__ inline int taylor_order(double x, double tol, int kmax) {
   const double ex = exp(x);
@@ -246,23 +264,25 @@ __device__ inline int taylor_order(double x, double tol, int kmax) {
   return -1;
 }
 
-// out = sum_{n=0..K} (s i tau Op)^n / n! in   with s = -1 (forward) or +1.
+// out = sum_{n=0..K} t_n with t_n = (s i tau Op)^n / n! in, s = -1 (forward)
+// or +1 (backward); t_n is also left in T[n] for dense output.  The small
+// increment sum_{n>=1} t_n is accumulated on its own and added to t_0 once, so
+// the state is rounded once per substep rather than once per term.
 template <typename real, int R, int WS, int NC, int SGN>
-__device__ void taylor(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx<real> *v,
-                       const cx<real> (&in)[R], cx<real> (&out)[R], double tau, int K,
-                       int lane) {
-  cx<real> t[R];
+__device__ void taylor(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
+                       const Terms<real, R> &T, const cx<real> (&in)[R], cx<real> (&out)[R],
+                       double tau, int K, int lane) {
+  cx<real> t[R], inc[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     t[m] = in[m];
-    out[m] = in[m];
+    inc[m] = cx<real>{0, 0};
   }
+  store_lds(T[0], t, lane);
   for (int n = 1; n <= K; ++n) {
-    store_lds(v, t, lane);
     wave_sync();
     cx<real> y[R];
-    op.apply(v, y);
-    wave_sync();
+    op.apply(T[n - 1], y);
     const real c = static_cast<real>(tau * a.inv_n[n]);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -270,8 +290,29 @@ __device__ void taylor(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx<
         t[m] = cx<real>{c * y[m].y, -c * y[m].x};
       else
         t[m] = cx<real>{-c * y[m].y, c * y[m].x};
-      out[m].x += t[m].x;
-      out[m].y += t[m].y;
+      inc[m].x += t[m].x;
+      inc[m].y += t[m].y;
+    }
+    store_lds(T[n], t, lane);
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) out[m] = cx<real>{in[m].x + inc[m].x, in[m].y + inc[m].y};
+}
+
+// p(s) = sum_n s^n t_n and dp/ds from the stored terms (own rows only; Horner)
+template <typename real, int R>
+__device__ __forceinline__ void dense_output(const Terms<real, R> &T, int K, real s,
+                                             cx<real> (&p)[R], cx<real> (&dp)[R], int lane) {
+  load_lds(T[K], p, lane);
+#pragma unroll
+  for (int m = 0; m < R; ++m) dp[m] = cx<real>{0, 0};
+  for (int n = K - 1; n >= 0; --n) {
+    cx<real> tn[R];
+    load_lds(T[n], tn, lane);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      dp[m] = cx<real>{fma(dp[m].x, s, p[m].x), fma(dp[m].y, s, p[m].y)};
+      p[m] = cx<real>{fma(p[m].x, s, tn[m].x), fma(p[m].y, s, tn[m].y)};
     }
   }
 }
@@ -291,19 +332,13 @@ __device__ void apply_jump(const PassArgs &a, int l, const cx<real> *v, cx<real>
     }
 }
 
-struct TrajMeta {
-  double nrm2;  // squared norm of the unnormalised state (the MCWF clock)
-  double r;     // current threshold
-  int ordinal;  // jumps so far in this pass
-};
-
 // Advance one trajectory across one substep of length h starting at time t0
 // (MCWF with precise jump times).  DIR 0: forward, exp(-i H_eff tau), times
 // t0 + elapsed; DIR 1: backward, exp(+i H_eff^+ tau), times t0 - elapsed.
 template <typename real, int R, int WS, int NC, int DIR>
-__device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx<real> *v,
-                        cx<real> (&psi)[R], TrajMeta &st, const Stream &rng, int j, double t0,
-                        double h, int K, int k, int lane) {
+__device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
+                        const Terms<real, R> &T, cx<real> (&psi)[R], TrajMeta &st,
+                        const Stream &rng, int j, double t0, double h, int K, int k, int lane) {
   constexpr int SGN = DIR == 0 ? -1 : 1;
   double tau_rem = h;
   double n_s = st.nrm2;
@@ -313,7 +348,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx
   constexpr double eps_real = sizeof(real) == 8 ? 0x1.0p-52 : 0x1.0p-23;
   for (int guard = 0;; ++guard) {
     cx<real> out[R];
-    taylor<real, R, WS, NC, SGN>(op, a, v, ps, out, tau_rem, K, lane);
+    taylor<real, R, WS, NC, SGN>(op, a, T, ps, out, tau_rem, K, lane);
     const double n_end = norm2(out);
     if (!(n_end < st.r)) {
 #pragma unroll
@@ -329,53 +364,45 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx
       st.r = 0.0;
       return;
     }
-    // ---- jump time: root of f(tau) = ||U(tau) ps||^2 - r in (0, tau_rem] ----
-    double lo = 0.0, hi = tau_rem;
-    double flo = n_s - st.r, fhi = n_end - st.r;
-    double tau = tau_rem * flo / (flo - fhi);
-    if (!(tau > lo && tau < hi)) tau = 0.5 * (lo + hi);
-    cx<real> pt[R];
-    for (int it = 0; it < 48; ++it) {
-      taylor<real, R, WS, NC, SGN>(op, a, v, ps, pt, tau, K, lane);
+    // ---- jump time: root of f(s) = ||p(s)||^2 - r for s in (0, 1] (tau = s tau_rem) ----
+    double lo = 0.0, hi = 1.0;
+    const double flo = n_s - st.r, fhi = n_end - st.r;
+    double s = flo / (flo - fhi);
+    if (!(s > lo && s < hi)) s = 0.5;
+    cx<real> pt[R], dp[R];
+    for (int it = 0; it < 64; ++it) {
+      dense_output<real, R>(T, K, static_cast<real>(s), pt, dp, lane);
       const double f = norm2(pt) - st.r;
-      // derivative of the norm: +2 Im<p|H_eff p> forward, -2 Im<p|H_eff^+ p> backward
-      store_lds(v, pt, lane);
-      wave_sync();
-      cx<real> y[R];
-      op.apply(v, y);
-      wave_sync();
-      double im = 0.0;
+      double g = 0.0;  // Re <p|dp/ds>
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        im = fma(static_cast<double>(pt[m].x), static_cast<double>(y[m].y), im);
-        im = fma(-static_cast<double>(pt[m].y), static_cast<double>(y[m].x), im);
+        g = fma(static_cast<double>(pt[m].x), static_cast<double>(dp[m].x), g);
+        g = fma(static_cast<double>(pt[m].y), static_cast<double>(dp[m].y), g);
       }
-      const double fp = (DIR == 0 ? 2.0 : -2.0) * wave_sum(im);
-      if (f >= 0.0) {
-        lo = tau;
-        flo = f;
-      } else {
-        hi = tau;
-        fhi = f;
-      }
-      if (fabs(f) <= a.ftol * st.r || (hi - lo) <= 4.0 * eps_real * h) break;
-      double tn = tau - f / fp;
-      if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-      if (fabs(tn - tau) <= 2.0 * eps_real * h) {
-        tau = tn;
-        taylor<real, R, WS, NC, SGN>(op, a, v, ps, pt, tau, K, lane);
+      const double fp = 2.0 * wave_sum(g);
+      if (f >= 0.0)
+        lo = s;
+      else
+        hi = s;
+      if (fabs(f) <= a.ftol * st.r || (hi - lo) <= 4.0 * eps_real) break;
+      double sn = s - f / fp;
+      if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+      if (fabs(sn - s) <= 2.0 * eps_real) {
+        s = sn;
+        dense_output<real, R>(T, K, static_cast<real>(s), pt, dp, lane);
         break;
       }
-      tau = tn;
+      s = sn;
     }
+    const double tau = s * tau_rem;
     // ---- jump (MCWF step 4) ----
-    store_lds(v, pt, lane);
+    store_lds(T[0], pt, lane);
     wave_sync();
     // weights ||L_l p||^2; pass 1 sums them, pass 2 walks the cumulative sum
     double total = 0.0;
     for (int l = 0; l < a.n_jump; ++l) {
       cx<real> y[R];
-      apply_jump<real, R>(a, l, v, y, lane);
+      apply_jump<real, R>(a, l, T[0], y, lane);
       total += norm2(y);
     }
     double thr_unused, x;
@@ -394,7 +421,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx
     int lsel = -1;
     cx<real> y[R];
     for (int l = 0; l < a.n_jump; ++l) {
-      apply_jump<real, R>(a, l, v, y, lane);
+      apply_jump<real, R>(a, l, T[0], y, lane);
       wsel = norm2(y);
       acc += wsel;
       if (target < acc) {
@@ -404,7 +431,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a, cx
     }
     if (lsel < 0) {  // rounding left target >= total: take the last operator
       lsel = a.n_jump - 1;
-      apply_jump<real, R>(a, lsel, v, y, lane);
+      apply_jump<real, R>(a, lsel, T[0], y, lane);
       wsel = norm2(y);
     }
     wave_sync();
@@ -441,7 +468,9 @@ struct StepPlan {
   double h;   // substep length
 };
 
-// Substeps and polynomial order of step j from the norm bound of its H_eff.
+// Substeps and polynomial order of step j from the norm bound of its H_eff:
+// enough substeps that ||H_eff|| h <= kMaxStepNorm and that the order fits the
+// kbuf - 1 term vectors in LDS.
 template <int N>
 __device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&uj)[N]) {
   double b = a.b0;
@@ -450,31 +479,56 @@ __device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&
   const double x = b * a.dt;
   StepPlan p;
   p.n_sub = x > kMaxStepNorm ? static_cast<int>(ceil(x / kMaxStepNorm)) : 1;
-  if (p.n_sub > kMaxSubsteps) {
+  p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
+  while ((p.K < 0 || p.K > a.kbuf - 1) && p.n_sub < kMaxSubsteps) {
+    p.n_sub += 1;
+    p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
+  }
+  if (p.K < 0 || p.K > a.kbuf - 1) {
     atomicOr(a.err, kErrTaylorOrder);
-    p.n_sub = kMaxSubsteps;
+    p.K = a.kbuf - 1;
   }
   p.h = a.dt / static_cast<double>(p.n_sub);
-  p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
-  if (p.K < 0) {
-    atomicOr(a.err, kErrTaylorOrder);
-    p.K = a.kmax;
-  }
   return p;
 }
 
 // Advance across the whole step j (its substeps).
 template <typename real, int R, int WS, int NC, int DIR>
 __device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC> &op,
-                                             const PassArgs &a, cx<real> *v,
+                                             const PassArgs &a, const Terms<real, R> &T,
                                              cx<real> (&psi)[R], TrajMeta &st,
                                              const Stream &rng, int j, const StepPlan &p,
                                              int k, int lane) {
   for (int s = 0; s < p.n_sub; ++s) {
     const double t0 = DIR == 0 ? static_cast<double>(j) * a.dt + s * p.h
                                : static_cast<double>(j + 1) * a.dt - s * p.h;
-    advance<real, R, WS, NC, DIR>(op, a, v, psi, st, rng, j, t0, p.h, p.K, k, lane);
+    advance<real, R, WS, NC, DIR>(op, a, T, psi, st, rng, j, t0, p.h, p.K, k, lane);
   }
+}
+
+// Block prologue shared by the kernels: copy the unscaled control slots to LDS,
+// zero the trailing element of this wave's term vectors, load the lane's
+// operator slice.  Returns the wave's term vectors.
+template <typename real, int R, int WS, int NC>
+__device__ __forceinline__ Terms<real, R> block_setup(const PassArgs &a, unsigned char *smem,
+                                                      int wib, int lane, size_t wave_bytes,
+                                                      LaneOp<real, R, WS, NC> &op) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  cx<real> *cval_lds = reinterpret_cast<cx<real> *>(smem);
+  const cx<real> *cval_g = static_cast<const cx<real> *>(a.cval);
+  for (int i = threadIdx.x; i < NCX * R * kWave; i += blockDim.x) cval_lds[i] = cval_g[i];
+  Terms<real, R> T;
+  T.base = reinterpret_cast<cx<real> *>(smem + sizeof(cx<real>) * NCX * R * kWave +
+                                        static_cast<size_t>(wib) * wave_bytes);
+  if (lane < a.kbuf) T[lane][R * kWave] = cx<real>{0, 0};
+  __syncthreads();
+  op.load(a, cval_lds, lane);
+  return T;
+}
+
+template <typename real, int R>
+__device__ __forceinline__ size_t terms_bytes(int kbuf) {
+  return static_cast<size_t>(kbuf) * Terms<real, R>::kLen * sizeof(cx<real>);
 }
 
 // ---- plain forward / backward passes --------------------------------------
@@ -483,14 +537,14 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_pass(PassArgs a) {
   extern __shared__ unsigned char smem_raw[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  cx<real> *v = reinterpret_cast<cx<real> *>(smem_raw) + wib * (R * kWave + 1);
-  if (lane == 0) v[R * kWave] = cx<real>{0, 0};  // zero element read by padding slots
+  const int wpb = blockDim.x / kWave;
   LaneOp<real, R, WS, NC> op;
-  op.load(a, lane);
+  const Terms<real, R> T = block_setup<real, R, WS, NC>(a, smem_raw, wib, lane,
+                                                         terms_bytes<real, R>(a.kbuf), op);
   const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
   cx<real> *chi = static_cast<cx<real> *>(a.chi);
-  const int nwaves = gridDim.x * (blockDim.x / kWave);
-  for (int k = blockIdx.x * (blockDim.x / kWave) + wib; k < a.M; k += nwaves) {
+  const int nwaves = gridDim.x * wpb;
+  for (int k = blockIdx.x * wpb + wib; k < a.M; k += nwaves) {
     cx<real> psi[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) psi[m] = start[lane + kWave * m];
@@ -523,7 +577,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_pass(PassArgs a) {
       }
       op.set_pulses(uj, a.wc);
       const StepPlan p = plan_step(a, uj);
-      advance_step<real, R, WS, NC, DIR>(op, a, v, psi, st, rng, j, p, k, lane);
+      advance_step<real, R, WS, NC, DIR>(op, a, T, psi, st, rng, j, p, k, lane);
       if (DIR == 1) {
         // chi_k(t_j) = tau_k chi_hat_k(t_j)
         const double inv = 1.0 / sqrt(st.nrm2);
@@ -609,6 +663,18 @@ __device__ __forceinline__ void load_costate(const PassArgs &a, int j, int k, in
   }
 }
 
+// One batch of agent-scope loads of the slots of blocks lane + 64 q.
+template <int NCX>
+__device__ __forceinline__ void poll_slots(const unsigned long long *row, int lane,
+                                           unsigned long long (&bits)[kPollPerLane][NCX]) {
+#pragma unroll
+  for (int q = 0; q < kPollPerLane; ++q)
+#pragma unroll
+    for (int c = 0; c < NCX; ++c)
+      bits[q][c] = __hip_atomic_load(&row[(lane + kWave * q) * NCX + c], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---- sequential Krotov forward pass (cooperative launch) ---------------------
 template <typename real, int R, int WS, int NC>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
@@ -619,20 +685,18 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
   __shared__ int s_abort;
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  const int wpb = blockDim.x / kWave;
   const int Tw = a.traj_per_wave;
-  const int wave = blockIdx.x * kWavesPerBlock + wib;
-  // LDS per wave: work vector, then Tw state vectors, then Tw metadata
-  unsigned char *wbase =
-      smem_raw + static_cast<size_t>(wib) *
-                     ((static_cast<size_t>(1 + Tw) * R * kWave + 1) * sizeof(cx<real>) +
-                      static_cast<size_t>(Tw) * sizeof(TrajMeta));
-  cx<real> *v = reinterpret_cast<cx<real> *>(wbase);
-  cx<real> *states = v + R * kWave + 1;
-  if (lane == 0) v[R * kWave] = cx<real>{0, 0};  // zero element read by padding slots
-  TrajMeta *meta = reinterpret_cast<TrajMeta *>(states + static_cast<size_t>(Tw) * R * kWave);
-
+  const int wave = blockIdx.x * wpb + wib;
+  // LDS per wave: term vectors, then Tw state vectors, then Tw bookkeeping
+  const size_t tb = terms_bytes<real, R>(a.kbuf);
+  const size_t wave_bytes = tb + static_cast<size_t>(Tw) * R * kWave * sizeof(cx<real>) +
+                            static_cast<size_t>(Tw) * sizeof(TrajMeta);
   LaneOp<real, R, WS, NC> op;
-  op.load(a, lane);
+  const Terms<real, R> T = block_setup<real, R, WS, NC>(a, smem_raw, wib, lane, wave_bytes, op);
+  cx<real> *states = reinterpret_cast<cx<real> *>(reinterpret_cast<unsigned char *>(T.base) + tb);
+  TrajMeta *meta = reinterpret_cast<TrajMeta *>(states + static_cast<size_t>(Tw) * R * kWave);
+  cx<real> *v = T[0];  // scratch vector for the update's gathers
   const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
   if (threadIdx.x == 0) s_abort = 0;
 
@@ -651,6 +715,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
       TrajMeta st;
       st.nrm2 = n;
       st.ordinal = 0;
+      st.pad = 0;
       st.r = k < a.M ? make_stream(a, k, 0).threshold(0) : 0.0;
       meta[t] = st;
     }
@@ -666,11 +731,12 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
 
   // pulse inputs of the step about to be updated (j = 0); rows past n_ctrl are
   // zero padding (lambda padded with 1), so no guards are needed
-  double uo[NCX], sf[NCX];
+  double uo[NCX], sf[NCX], inv_lm[NCX];
 #pragma unroll
   for (int i = 0; i < NCX; ++i) {
+    inv_lm[i] = 1.0 / (a.lam[i] * a.M);
     uo[i] = a.u_old[static_cast<size_t>(i) * a.nt];
-    sf[i] = a.S[static_cast<size_t>(i) * a.nt] / (a.lam[i] * a.M);
+    sf[i] = a.S[static_cast<size_t>(i) * a.nt] * inv_lm[i];
   }
 
   for (int j = 0; j < a.nt; ++j) {
@@ -684,51 +750,56 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
     if (threadIdx.x < NCX) {  // control i's block partial (zero for padding controls)
       const int i = threadIdx.x;
       double s = 0.0;
-      for (int w = 0; w < kWavesPerBlock; ++w)
+      for (int w = 0; w < wpb; ++w)
         for (int c = i * a.wc; c < (i + 1) * a.wc && c < NC; ++c) s += wpart[w][c];
       __hip_atomic_store(&a.slots[(static_cast<size_t>(j) * kMaxBlocks + blockIdx.x) * NCX + i],
                          __double_as_longlong(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // ---- wait for every block's partial of step j; sum in block order --------
     if (wib == 0 && a.n_ctrl > 0) {
-      // every lane reads kPollPerLane blocks' slots in one batch of loads; slots of
-      // blocks past the grid hold zero, so the sum over all kMaxBlocks is exact
+      // every lane reads kPollPerLane blocks' slots in one batch of loads (slots of
+      // blocks past the grid hold zero, so the sum over all kMaxBlocks is exact);
+      // the next batch is issued before the current one is checked, so two polls
+      // are always in flight
+      const unsigned long long *row = a.slots + static_cast<size_t>(j) * kMaxBlocks * NCX;
       double acc[NCX];
+      unsigned long long cur[kPollPerLane][NCX], nxt[kPollPerLane][NCX];
+      poll_slots<NCX>(row, lane, cur);
       long long spins = 0;
       bool abort = false;
       for (;;) {
-        unsigned long long bits[kPollPerLane][NCX];
-        const unsigned long long *row = a.slots + static_cast<size_t>(j) * kMaxBlocks * NCX;
-#pragma unroll
-        for (int q = 0; q < kPollPerLane; ++q)
-#pragma unroll
-          for (int c = 0; c < NCX; ++c)
-            bits[q][c] = __hip_atomic_load(&row[(lane + kWave * q) * NCX + c], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+        poll_slots<NCX>(row, lane, nxt);
+        __builtin_amdgcn_sched_barrier(0);
         int missing = 0;
 #pragma unroll
         for (int q = 0; q < kPollPerLane; ++q)
 #pragma unroll
-          for (int c = 0; c < NCX; ++c) missing |= bits[q][c] == kSlotEmpty;
+          for (int c = 0; c < NCX; ++c) missing |= cur[q][c] == kSlotEmpty;
         if (!__any(missing)) {
 #pragma unroll
           for (int c = 0; c < NCX; ++c) {
             acc[c] = 0.0;
 #pragma unroll
             for (int q = 0; q < kPollPerLane; ++q)
-              acc[c] += __longlong_as_double(static_cast<long long>(bits[q][c]));
+              acc[c] += __longlong_as_double(static_cast<long long>(cur[q][c]));
           }
           break;
         }
+        // another block's abort is looked for only now and then: the flag load
+        // waits for the poll in flight
         if (++spins > a.spin_limit ||
-            (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-             kErrSyncTimeout)) {
+            ((spins & 255) == 0 &&
+             (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+              kErrSyncTimeout))) {
 #pragma unroll
           for (int c = 0; c < NCX; ++c) acc[c] = 0.0;
           abort = true;
           break;
         }
-        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int q = 0; q < kPollPerLane; ++q)
+#pragma unroll
+          for (int c = 0; c < NCX; ++c) cur[q][c] = nxt[q][c];
       }
 #pragma unroll
       for (int c = 0; c < NCX; ++c) {
@@ -755,7 +826,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
       for (int i = 0; i < NCX; ++i) {
         const size_t ij = static_cast<size_t>(i) * a.nt + j + 1;
         uo[i] = a.u_old[ij];
-        sf[i] = a.S[ij] / (a.lam[i] * a.M);
+        sf[i] = a.S[ij] * inv_lm[i];
       }
     }
     op.set_pulses(uj, a.wc);
@@ -770,11 +841,10 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
       cx<real> ch[R];
       if (j + 1 < a.nt) load_costate<real, R>(a, j + 1, k, lane, ch);
       cx<real> psi[R];
-#pragma unroll
-      for (int m = 0; m < R; ++m) psi[m] = sv[lane + kWave * m];
+      load_lds(sv, psi, lane);
       TrajMeta st = meta[t];
       const Stream rng = make_stream(a, k, 0);
-      advance_step<real, R, WS, NC, 0>(op, a, v, psi, st, rng, j, p, k, lane);
+      advance_step<real, R, WS, NC, 0>(op, a, T, psi, st, rng, j, p, k, lane);
       wave_sync();
       store_lds(sv, psi, lane);
       if (lane == 0) meta[t] = st;
@@ -864,15 +934,13 @@ const Variant *variants(int *count) {
 
 const void *functional_kernel() { return reinterpret_cast<const void *>(&k_functional); }
 
-size_t pass_lds_bytes(const Variant &v) {
+size_t block_lds_bytes(const Variant &v, int waves, int kbuf, int traj_per_wave) {
   const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
-  return (static_cast<size_t>(v.R) * kWave + 1) * cplx;
-}
-
-size_t krotov_lds_bytes(const Variant &v, int traj_per_wave) {
-  const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
-  return (static_cast<size_t>(1 + traj_per_wave) * v.R * kWave + 1) * cplx +
-         static_cast<size_t>(traj_per_wave) * sizeof(TrajMeta);
+  const size_t ncx = v.NC > 0 ? v.NC : 1;
+  const size_t per_wave = static_cast<size_t>(kbuf) * (v.R * kWave + 1) * cplx +
+                          static_cast<size_t>(traj_per_wave) * v.R * kWave * cplx +
+                          static_cast<size_t>(traj_per_wave) * sizeof(TrajMeta);
+  return ncx * v.R * kWave * cplx + static_cast<size_t>(waves) * per_wave;
 }
 
 }  // namespace tk
