@@ -24,6 +24,36 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3}  # published MI355X vector peaks, TFLOP/s
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+# each scaled by what the counter reads for a device copy of known size
+# (a 1 GiB copy reads FETCH_SIZE 524300 KiB and WRITE_SIZE 1048576 KiB, hence
+# factors 2.0 and 1.0).  Keyed by kernel, workload and the hash of the kernel
+# sources the counters were taken with; a different hash reports null.
+TRAFFIC = {
+    ("krotov", "chain2_fock3", "fp64", 1024, 2000): {
+        "sources": "e0b3b5c7841951dc", "fetch_kib": 1444762, "write_kib": 17371,
+        "fetch_scale": 2.0, "write_scale": 1.0},
+}
+KERNEL_SOURCES = ["paper_1801_04382_amd/csrc/tk_kernels.hip",
+                  "paper_1801_04382_amd/csrc/tk_internal.h"]
+
+
+def sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, prec: str, M: int, nt: int):
+    """HBM bytes per launch of `kernel` from the stored counters, or None."""
+    t = TRAFFIC.get((kernel, workload, prec, M, nt))
+    if t is None or t["sources"] != sources_hash():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def cpu_baseline(name: str, M_sub: int, nt: int) -> dict:
     """The FP64 oracle timed on this host for one Krotov iteration (bounded sample)."""
@@ -53,6 +83,20 @@ def cpu_baseline(name: str, M_sub: int, nt: int) -> dict:
                       f"{el:.1f} s; host cores {cores}, BLAS threads {blas_threads}"}
 
 
+def copy_probe(mib: int, reps: int) -> int:
+    """Device-to-device copies of known size: each reads and writes mib MiB."""
+    import torch
+    n = mib * (1 << 20)
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "reps": reps}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,12 +109,18 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the method "
               "shards across GPUs by trajectories, which this build does not run.",
               file=sys.stderr)
         return 2
+
+    if args.copy_probe:
+        return copy_probe(args.copy_probe, args.steps)
 
     from paper_1801_04382_amd import trajkrotov as tk
     from workloads import CONFIGS, config_workload
@@ -103,7 +153,8 @@ def main() -> int:
     kd = kernels[dom]
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(kd["tflops"], 4),
                 "peak": PEAK[prec], "unit": "TFLOP/s",
-                "frac": round(kd["tflops"] / PEAK[prec], 5), "traffic": None,
+                "frac": round(kd["tflops"] / PEAK[prec], 5),
+                "traffic": measured_traffic(dom, args.workload, prec, w.M, w.nt),
                 "hbm_gbs": round(kd["gbs"], 2)}
     info = ctx.launch_info()
     out = {
