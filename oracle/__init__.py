@@ -20,4 +20,6 @@ Modules:
   mcwf     -- effective Hamiltonian, exact step propagators, MCWF passes
   krotov   -- trajectory functional, costates, sequential Krotov update
   lindblad -- dense density-matrix propagation (ensemble check)
+  gradient -- pathwise dJ_T/du with the jump record fixed: replay, adjoint
+              sweep with Van Loan's block exponential, finite differences
 """
