@@ -121,7 +121,8 @@ enum tk_kernel_kind {
   TK_KERNEL_FORWARD = 0,   /* plain forward pass (iteration 0, functional) */
   TK_KERNEL_BACKWARD = 1,  /* costate pass                                  */
   TK_KERNEL_KROTOV = 2,    /* sequential forward pass with pulse update     */
-  TK_KERNEL_COUNT = 3
+  TK_KERNEL_GRAD = 3,      /* pathwise gradient (replay + reverse sweep)    */
+  TK_KERNEL_COUNT = 4
 };
 
 typedef struct tk_ctx tk_ctx; /* opaque */
@@ -226,6 +227,33 @@ TK_API int tk_functional(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t iterati
 TK_API int tk_krotov_iterate(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t first_iteration,
                       int32_t n_iter, double *J_T_out, tk_jump *rec, int64_t cap,
                       int64_t *n_rec);
+
+/* ---- pathwise gradient ------------------------------------------------------ */
+
+/* Gradient of the trajectory functional with the jump record held fixed.
+ * Every trajectory k < M is replayed from psi0 with the current pulses: a
+ * forward record (direction 0) of trajectory k at time t in step j ends a
+ * propagator piece there, applies L_op and renormalises (MCWF step 4), in the
+ * order of the records' ordinals; no thresholds are drawn.  This makes
+ *   J_T(u) = 1 - (1/M) sum_k |<Psi_tgt|phi_hat_k(T)>|^2      (Sec. 2.3)
+ * a smooth function of the pulse values, and the call returns J_T, the
+ * overlaps tau_k of the replay (tau_out [2M], may be NULL) and
+ * dJdu [n_ctrl * nt] = dJ_T/du_ij (control i, step j at dJdu[i * nt + j]).
+ * The derivative is exact up to the propagators' truncation: each piece's
+ * d exp(-i H_eff tau)/du_i comes from an augmented Taylor series (the block
+ * exponential of Van Loan, 1978) and the sweep runs backward from the seed
+ * dF_k/d<phi_k| with L_l^+ and exp(+i H_eff^+ tau); forward states are
+ * checkpointed every 64 steps and recomputed.  The renormalisation after a
+ * jump is held constant (it does not change phi_hat_k(T)).
+ * rec [n_rec]: jump records as written by tk_propagate_forward (any order;
+ * backward records are ignored).  A record with traj >= M, a step outside
+ * [0, nt), an operator >= n_jump, a time outside its step (beyond 1e-9 dt)
+ * or out of time order within its trajectory gives TK_EINVAL.  Seeds and
+ * iterations play no part.  Invalidates the overlaps kept for a following
+ * backward pass.  Errors: TK_ESTATE, TK_EINVAL, TK_ENOMEM, TK_ENUMERIC (a
+ * recorded jump with ||L_l psi|| = 0), TK_EHIP, TK_EUNSUPPORTED. */
+TK_API int tk_grad_pathwise(tk_ctx *ctx, int32_t M, const tk_jump *rec, int64_t n_rec,
+                     double *J_T, double *tau_out, double *dJdu);
 
 /* ---- instrumentation ------------------------------------------------------ */
 

@@ -1,0 +1,510 @@
+// Device-side building blocks shared by the propagation kernels:
+// complex helpers, wavefront reductions, Philox4x64-10, the per-lane
+// operator slice, Taylor steps, dense output, jump handling and step
+// planning.  Included by every kernel source (internal linkage).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tk_internal.h"
+
+namespace tk {
+namespace {
+
+template <typename real>
+struct cx {
+  real x, y;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a full wave; every lane receives the same value.
+// Within a 16-lane row: pairs (xor 1), pairs of pairs (xor 2), half-row
+// mirror, row mirror -- each lane adds a partner holding a disjoint partial
+// sum, and both partners add the same two operands.  Then the four row sums
+// are combined as (row0 + row1) + (row2 + row3).
+__device__ __forceinline__ double wave_sum(double x) {
+  x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_mov<0x141>(x);  // row_half_mirror
+  x += dpp_mov<0x140>(x);  // row_mirror
+  return (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
+}
+
+// ---- Philox4x64-10 (Salmon et al., SC'11) ---------------------------------
+__device__ __forceinline__ void philox4x64(uint64_t c0, uint64_t c1, uint64_t c2,
+                                           uint64_t c3, uint64_t k0, uint64_t k1,
+                                           uint64_t &w0, uint64_t &w1) {
+  constexpr uint64_t kMul0 = 0xD2E7470EE14C6C93ull;
+  constexpr uint64_t kMul1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kWeyl0 = 0x9E3779B97F4A7C15ull;
+  constexpr uint64_t kWeyl1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd) {
+      k0 += kWeyl0;
+      k1 += kWeyl1;
+    }
+    const uint64_t lo0 = kMul0 * c0, hi0 = __umul64hi(kMul0, c0);
+    const uint64_t lo1 = kMul1 * c2, hi1 = __umul64hi(kMul1, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  w0 = c0;
+  w1 = c1;
+}
+
+__device__ __forceinline__ double to_unit(uint64_t w) {
+  return static_cast<double>(w >> 11) * 0x1.0p-53;
+}
+
+struct Stream {
+  uint64_t k0, k1, iteration, direction;
+  __device__ void block(uint64_t ordinal, double &thr, double &choice) const {
+    uint64_t w0, w1;
+    philox4x64(ordinal, iteration, direction, 0, k0, k1, w0, w1);
+    thr = to_unit(w0);
+    choice = to_unit(w1);
+  }
+  __device__ double threshold(uint64_t ordinal) const {
+    double t, c;
+    block(ordinal, t, c);
+    return t;
+  }
+};
+
+__device__ __forceinline__ Stream make_stream(const PassArgs &a, int k, int dir) {
+  Stream s;
+  s.k0 = a.seed;
+  s.k1 = (static_cast<uint64_t>(a.instance) << 32) | static_cast<uint32_t>(k);
+  s.iteration = a.iteration;
+  s.direction = static_cast<uint64_t>(dir);
+  return s;
+}
+
+template <typename real>
+__device__ __forceinline__ void cfma(cx<real> &y, const cx<real> &a, const cx<real> &b) {
+  y.x = fma(a.x, b.x, y.x);
+  y.x = fma(-a.y, b.y, y.x);
+  y.y = fma(a.x, b.y, y.y);
+  y.y = fma(a.y, b.x, y.y);
+}
+
+// ---- per-lane operator slice ------------------------------------------------
+template <typename real, int R, int WS, int NC>
+struct LaneOp {
+  static constexpr int NCX = NC > 0 ? NC : 1;
+  int scol[WS][R];
+  cx<real> sval[WS][R];
+  int ccol[NCX][R];
+  cx<real> cv[NCX][R];   // control matrix elements scaled by the current pulses
+  const cx<real> *cval;  // unscaled control elements of this lane in LDS, [c][m][lane]
+
+  // static slots (scol_g, sval_g) and control columns (ccol_g) from global
+  // memory; the unscaled control values stay in LDS (cval_lds)
+  __device__ void load(const int *scol_g, const void *sval_g, const int *ccol_g,
+                       const cx<real> *cval_lds, int lane) {
+    const cx<real> *sv = static_cast<const cx<real> *>(sval_g);
+#pragma unroll
+    for (int s = 0; s < WS; ++s)
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int idx = (s * R + m) * kWave + lane;
+        scol[s][m] = scol_g[idx];
+        sval[s][m] = sv[idx];
+      }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        ccol[c][m] = ccol_g[(c * R + m) * kWave + lane];
+        cv[c][m] = cx<real>{0, 0};
+      }
+    cval = cval_lds + lane;
+  }
+
+  // unscaled control element of slot c, row slot m
+  __device__ __forceinline__ cx<real> cval_at(int c, int m) const {
+    return cval[(c * R + m) * kWave];
+  }
+
+  // cv = u_{c / wc} * cval for the pulse values uj[0 .. NCX) (zero past n_ctrl)
+  __device__ void set_pulses(const double (&uj)[NCX], int wc) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int i = c / wc;  // < NC, hence a valid index
+      const real ui = static_cast<real>(uj[i]);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const cx<real> q = cval_at(c, m);
+        cv[c][m] = cx<real>{ui * q.x, ui * q.y};
+      }
+    }
+  }
+
+  // y = Op v for the lane's rows (v in LDS).  All gathers first.
+  __device__ void apply(const cx<real> *v, cx<real> (&y)[R]) const {
+    cx<real> b[WS + NC][R];
+#pragma unroll
+    for (int s = 0; s < WS; ++s)
+#pragma unroll
+      for (int m = 0; m < R; ++m) b[s][m] = v[scol[s][m]];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int m = 0; m < R; ++m) b[WS + c][m] = v[ccol[c][m]];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+#pragma unroll
+    for (int s = 0; s < WS; ++s)
+#pragma unroll
+      for (int m = 0; m < R; ++m) cfma(y[m], sval[s][m], b[s][m]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int m = 0; m < R; ++m) cfma(y[m], cv[c][m], b[WS + c][m]);
+  }
+};
+
+template <typename real, int R>
+__device__ __forceinline__ double norm2(const cx<real> (&p)[R]) {
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const double x = p[m].x, y = p[m].y;
+    s = fma(x, x, s);
+    s = fma(y, y, s);
+  }
+  return wave_sum(s);
+}
+
+template <typename real, int R>
+__device__ __forceinline__ void store_lds(cx<real> *v, const cx<real> (&p)[R], int lane) {
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[lane + kWave * m] = p[m];
+}
+
+template <typename real, int R>
+__device__ __forceinline__ void load_lds(const cx<real> *v, cx<real> (&p)[R], int lane) {
+#pragma unroll
+  for (int m = 0; m < R; ++m) p[m] = v[lane + kWave * m];
+}
+
+// Per-wave LDS view: term vectors T_0 .. T_{kbuf-1}, each 64 R + 1 elements
+// (element 64 R is the zero read by padding slots).
+template <typename real, int R>
+struct Terms {
+  static constexpr int kLen = R * kWave + 1;
+  cx<real> *base;
+  __device__ cx<real> *operator[](int n) const { return base + n * kLen; }
+};
+
+// Smallest K with x^(K+1)/(K+1)! e^x <= tol (Taylor remainder bound), or -1.
+__device__ inline int taylor_order(double x, double tol, int kmax) {
+  const double ex = exp(x);
+  double t = x;
+  for (int K = 1; K <= kmax; ++K) {
+    t *= x / static_cast<double>(K + 1);
+    if (t * ex <= tol) return K;
+  }
+  return -1;
+}
+
+// out = sum_{n=0..K} t_n with t_n = (s i tau Op)^n / n! in, s = -1 (forward)
+// or +1 (backward); t_n is also left in T[n] for dense output.  The small
+// increment sum_{n>=1} t_n is accumulated on its own and added to t_0 once, so
+// the state is rounded once per substep rather than once per term.
+template <typename real, int R, int WS, int NC, int SGN>
+__device__ void taylor(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
+                       const Terms<real, R> &T, const cx<real> (&in)[R], cx<real> (&out)[R],
+                       double tau, int K, int lane) {
+  cx<real> t[R], inc[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    t[m] = in[m];
+    inc[m] = cx<real>{0, 0};
+  }
+  store_lds(T[0], t, lane);
+  for (int n = 1; n <= K; ++n) {
+    wave_sync();
+    cx<real> y[R];
+    op.apply(T[n - 1], y);
+    const real c = static_cast<real>(tau * a.inv_n[n]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      if (SGN < 0)
+        t[m] = cx<real>{c * y[m].y, -c * y[m].x};
+      else
+        t[m] = cx<real>{-c * y[m].y, c * y[m].x};
+      inc[m].x += t[m].x;
+      inc[m].y += t[m].y;
+    }
+    store_lds(T[n], t, lane);
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) out[m] = cx<real>{in[m].x + inc[m].x, in[m].y + inc[m].y};
+}
+
+// p(s) = sum_n s^n t_n and dp/ds from the stored terms (own rows only; Horner)
+template <typename real, int R>
+__device__ __forceinline__ void dense_output(const Terms<real, R> &T, int K, real s,
+                                             cx<real> (&p)[R], cx<real> (&dp)[R], int lane) {
+  load_lds(T[K], p, lane);
+#pragma unroll
+  for (int m = 0; m < R; ++m) dp[m] = cx<real>{0, 0};
+  for (int n = K - 1; n >= 0; --n) {
+    cx<real> tn[R];
+    load_lds(T[n], tn, lane);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      dp[m] = cx<real>{fma(dp[m].x, s, p[m].x), fma(dp[m].y, s, p[m].y)};
+      p[m] = cx<real>{fma(p[m].x, s, tn[m].x), fma(p[m].y, s, tn[m].y)};
+    }
+  }
+}
+
+// y = L_l p for operator l of a group packed [l][w][m][lane] with wl slots per
+// row (slices read from global memory; p in LDS v)
+template <typename real, int R>
+__device__ void apply_packed(const int *lcol, const void *lval, int wl, int l,
+                             const cx<real> *v, cx<real> (&y)[R], int lane) {
+  const cx<real> *lv = static_cast<const cx<real> *>(lval);
+#pragma unroll
+  for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+  for (int w = 0; w < wl; ++w)
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int idx = ((l * wl + w) * R + m) * kWave + lane;
+      cfma(y[m], lv[idx], v[lcol[idx]]);
+    }
+}
+
+// y = L_l p for the jump operators of the pass
+template <typename real, int R>
+__device__ __forceinline__ void apply_jump(const PassArgs &a, int l, const cx<real> *v,
+                                           cx<real> (&y)[R], int lane) {
+  apply_packed<real, R>(a.lcol, a.lval, a.wl, l, v, y, lane);
+}
+
+// Advance one trajectory across one substep of length h starting at time t0
+// (MCWF with precise jump times).  DIR 0: forward, exp(-i H_eff tau), times
+// t0 + elapsed; DIR 1: backward, exp(+i H_eff^+ tau), times t0 - elapsed.
+template <typename real, int R, int WS, int NC, int DIR>
+__device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
+                        const Terms<real, R> &T, cx<real> (&psi)[R], TrajMeta &st,
+                        const Stream &rng, int j, double t0, double h, int K, int k, int lane) {
+  constexpr int SGN = DIR == 0 ? -1 : 1;
+  double tau_rem = h;
+  double n_s = st.nrm2;
+  cx<real> ps[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) ps[m] = psi[m];
+  constexpr double eps_real = sizeof(real) == 8 ? 0x1.0p-52 : 0x1.0p-23;
+  for (int guard = 0;; ++guard) {
+    cx<real> out[R];
+    taylor<real, R, WS, NC, SGN>(op, a, T, ps, out, tau_rem, K, lane);
+    const double n_end = norm2(out);
+    if (!(n_end < st.r)) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = out[m];
+      st.nrm2 = n_end;
+      return;
+    }
+    if (guard >= 64) {  // pathological: give up on this step, keep the state
+      if (lane == 0) atomicOr(a.err, kErrJumpLoop);
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = out[m];
+      st.nrm2 = n_end;
+      st.r = 0.0;
+      return;
+    }
+    // ---- jump time: root of f(s) = ||p(s)||^2 - r for s in (0, 1] (tau = s tau_rem) ----
+    double lo = 0.0, hi = 1.0;
+    const double flo = n_s - st.r, fhi = n_end - st.r;
+    double s = flo / (flo - fhi);
+    if (!(s > lo && s < hi)) s = 0.5;
+    cx<real> pt[R], dp[R];
+    for (int it = 0; it < 64; ++it) {
+      dense_output<real, R>(T, K, static_cast<real>(s), pt, dp, lane);
+      const double f = norm2(pt) - st.r;
+      double g = 0.0;  // Re <p|dp/ds>
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        g = fma(static_cast<double>(pt[m].x), static_cast<double>(dp[m].x), g);
+        g = fma(static_cast<double>(pt[m].y), static_cast<double>(dp[m].y), g);
+      }
+      const double fp = 2.0 * wave_sum(g);
+      if (f >= 0.0)
+        lo = s;
+      else
+        hi = s;
+      if (fabs(f) <= a.ftol * st.r || (hi - lo) <= 4.0 * eps_real) break;
+      double sn = s - f / fp;
+      if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+      if (fabs(sn - s) <= 2.0 * eps_real) {
+        s = sn;
+        dense_output<real, R>(T, K, static_cast<real>(s), pt, dp, lane);
+        break;
+      }
+      s = sn;
+    }
+    const double tau = s * tau_rem;
+    // ---- jump (MCWF step 4) ----
+    store_lds(T[0], pt, lane);
+    wave_sync();
+    // weights ||L_l p||^2; pass 1 sums them, pass 2 walks the cumulative sum
+    double total = 0.0;
+    for (int l = 0; l < a.n_jump; ++l) {
+      cx<real> y[R];
+      apply_jump<real, R>(a, l, T[0], y, lane);
+      total += norm2(y);
+    }
+    double thr_unused, x;
+    rng.block(static_cast<uint64_t>(st.ordinal), thr_unused, x);
+    if (!(total > 0.0)) {
+      if (lane == 0) atomicOr(a.err, kErrNoJumpWeight);
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = pt[m];
+      st.nrm2 = norm2(pt);
+      st.r = 0.0;
+      wave_sync();
+      return;
+    }
+    const double target = x * total;
+    double acc = 0.0, wsel = 0.0;
+    int lsel = -1;
+    cx<real> y[R];
+    for (int l = 0; l < a.n_jump; ++l) {
+      apply_jump<real, R>(a, l, T[0], y, lane);
+      wsel = norm2(y);
+      acc += wsel;
+      if (target < acc) {
+        lsel = l;
+        break;
+      }
+    }
+    if (lsel < 0) {  // rounding left target >= total: take the last operator
+      lsel = a.n_jump - 1;
+      apply_jump<real, R>(a, lsel, T[0], y, lane);
+      wsel = norm2(y);
+    }
+    wave_sync();
+    const real inv = static_cast<real>(1.0 / sqrt(wsel));
+#pragma unroll
+    for (int m = 0; m < R; ++m) ps[m] = cx<real>{y[m].x * inv, y[m].y * inv};
+    const double elapsed = (h - tau_rem) + tau;
+    if (lane == 0) {
+      const unsigned long long slot = atomicAdd(a.rec_count, 1ull);
+      if (static_cast<long long>(slot) < a.rec_cap) {
+        tk_jump r;
+        r.instance = static_cast<int32_t>(a.instance);
+        r.traj = k;
+        r.step = j;
+        r.op = lsel;
+        r.ordinal = st.ordinal;
+        r.direction = DIR;
+        r.iteration = static_cast<int32_t>(a.iteration);
+        r.reserved = 0;
+        r.t = DIR == 0 ? t0 + elapsed : t0 - elapsed;
+        a.rec[slot] = r;
+      }
+    }
+    st.ordinal += 1;
+    st.r = rng.threshold(static_cast<uint64_t>(st.ordinal));
+    n_s = norm2(ps);
+    tau_rem = tau_rem - tau;
+  }
+}
+
+struct StepPlan {
+  int n_sub;  // substeps per step
+  int K;      // Taylor order of a substep
+  double h;   // substep length
+};
+
+// Substeps and polynomial order of step j from the norm bound of its H_eff:
+// enough substeps that ||H_eff|| h <= kMaxStepNorm and that the order fits the
+// kbuf - 1 term vectors in LDS.
+template <int N>
+__device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&uj)[N]) {
+  double b = a.b0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) b += fabs(uj[i]) * a.bc[i];
+  const double x = b * a.dt;
+  StepPlan p;
+  p.n_sub = x > kMaxStepNorm ? static_cast<int>(ceil(x / kMaxStepNorm)) : 1;
+  p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
+  while ((p.K < 0 || p.K > a.kbuf - 1) && p.n_sub < kMaxSubsteps) {
+    p.n_sub += 1;
+    p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
+  }
+  if (p.K < 0 || p.K > a.kbuf - 1) {
+    atomicOr(a.err, kErrTaylorOrder);
+    p.K = a.kbuf - 1;
+  }
+  p.h = a.dt / static_cast<double>(p.n_sub);
+  return p;
+}
+
+// Advance across the whole step j (its substeps).
+template <typename real, int R, int WS, int NC, int DIR>
+__device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC> &op,
+                                             const PassArgs &a, const Terms<real, R> &T,
+                                             cx<real> (&psi)[R], TrajMeta &st,
+                                             const Stream &rng, int j, const StepPlan &p,
+                                             int k, int lane) {
+  for (int s = 0; s < p.n_sub; ++s) {
+    const double t0 = DIR == 0 ? static_cast<double>(j) * a.dt + s * p.h
+                               : static_cast<double>(j + 1) * a.dt - s * p.h;
+    advance<real, R, WS, NC, DIR>(op, a, T, psi, st, rng, j, t0, p.h, p.K, k, lane);
+  }
+}
+
+// Block prologue shared by the kernels: copy the unscaled control slots to LDS,
+// zero the trailing element of this wave's term vectors, load the lane's
+// operator slice.  Returns the wave's term vectors.
+template <typename real, int R, int WS, int NC>
+__device__ __forceinline__ Terms<real, R> block_setup(const PassArgs &a, unsigned char *smem,
+                                                      int wib, int lane, size_t wave_bytes,
+                                                      LaneOp<real, R, WS, NC> &op) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  cx<real> *cval_lds = reinterpret_cast<cx<real> *>(smem);
+  const cx<real> *cval_g = static_cast<const cx<real> *>(a.cval);
+  for (int i = threadIdx.x; i < NCX * R * kWave; i += blockDim.x) cval_lds[i] = cval_g[i];
+  Terms<real, R> T;
+  T.base = reinterpret_cast<cx<real> *>(smem + sizeof(cx<real>) * NCX * R * kWave +
+                                        static_cast<size_t>(wib) * wave_bytes);
+  if (lane < a.kbuf) T[lane][R * kWave] = cx<real>{0, 0};
+  __syncthreads();
+  op.load(a.scol, a.sval, a.ccol, cval_lds, lane);
+  return T;
+}
+
+template <typename real, int R>
+__device__ __forceinline__ size_t terms_bytes(int kbuf) {
+  return static_cast<size_t>(kbuf) * Terms<real, R>::kLen * sizeof(cx<real>);
+}
+
+}  // namespace
+}  // namespace tk

@@ -230,6 +230,8 @@ struct tk_ctx {
   std::vector<Csr> H_ctrl_host;
 
   DevBuf f_scol, f_sval, f_ccol, f_cval, b_scol, b_sval, b_ccol, b_cval, lcol, lval;
+  DevBuf ldcol, ldval;  // L_l^+ (pathwise gradient)
+  int wld = 1;
   DevBuf psi0_bulk, tgt_bulk, tgt64;
 
   int nt = 0;
@@ -238,6 +240,7 @@ struct tk_ctx {
   DevBuf u_dev, u_new_dev, S_dev, lam_dev;
 
   DevBuf chi, tau, psiT, slots, rec, rec_count, err_dev, jt_dev;
+  DevBuf path_off, path_step, path_t, path_op, ckpt, stash, gk, dJdu;
   int chi_M = -1;
   int tau_M = -1;
   uint64_t tau_seed = 0;
@@ -712,6 +715,111 @@ int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap)
   return TK_OK;
 }
 
+// Jump paths of the pathwise gradient: forward records (direction 0) of
+// trajectories k < M, ordered per trajectory by ordinal, as offsets + arrays.
+int build_paths(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec, std::vector<int> &off,
+                std::vector<int> &step, std::vector<double> &t, std::vector<int> &op) {
+  if (n_rec < 0 || (n_rec > 0 && !rec)) return fail(c, TK_EINVAL, "bad jump-record array");
+  std::vector<const tk_jump *> use;
+  for (int64_t q = 0; q < n_rec; ++q) {
+    const tk_jump &r = rec[q];
+    if (r.direction != 0) continue;
+    if (r.traj < 0 || r.traj >= M) return fail(c, TK_EINVAL, "jump record of a trajectory >= M");
+    if (r.step < 0 || r.step >= c->nt) return fail(c, TK_EINVAL, "jump record outside the grid");
+    if (r.op < 0 || r.op >= c->n_jump) return fail(c, TK_EINVAL, "jump record with a bad operator");
+    const double dt = c->T / c->nt, slack = 1e-9 * dt;
+    if (!std::isfinite(r.t) || r.t < r.step * dt - slack || r.t > (r.step + 1) * dt + slack)
+      return fail(c, TK_EINVAL, "jump time outside its step");
+    use.push_back(&r);
+  }
+  std::sort(use.begin(), use.end(), [](const tk_jump *x, const tk_jump *y) {
+    return std::make_tuple(x->traj, x->ordinal) < std::make_tuple(y->traj, y->ordinal);
+  });
+  off.assign(M + 1, 0);
+  step.clear();
+  t.clear();
+  op.clear();
+  for (size_t q = 0; q < use.size(); ++q) {
+    const tk_jump &r = *use[q];
+    if (q > 0 && use[q - 1]->traj == r.traj) {
+      const tk_jump &p = *use[q - 1];
+      if (p.ordinal == r.ordinal) return fail(c, TK_EINVAL, "duplicate jump ordinal");
+      if (r.step < p.step || r.t < p.t) return fail(c, TK_EINVAL, "jump records out of time order");
+    }
+    off[r.traj + 1]++;
+    step.push_back(r.step);
+    t.push_back(r.t);
+    op.push_back(r.op);
+  }
+  for (int k = 0; k < M; ++k) off[k + 1] += off[k];
+  return TK_OK;
+}
+
+int run_grad(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec) {
+  std::vector<int> off, step, op;
+  std::vector<double> t;
+  int rc = build_paths(c, M, rec, n_rec, off, step, t, op);
+  if (rc) return rc;
+  if ((rc = upload(c, c->path_off, off.data(), off.size() * sizeof(int)))) return rc;
+  if ((rc = upload(c, c->path_step, step.data(), step.size() * sizeof(int)))) return rc;
+  if ((rc = upload(c, c->path_t, t.data(), t.size() * sizeof(double)))) return rc;
+  if ((rc = upload(c, c->path_op, op.data(), op.size() * sizeof(int)))) return rc;
+  const void *kern = c->var->k_grad;
+  if (!kern) return fail(c, TK_EUNSUPPORTED, "no gradient kernel for this variant");
+  tk::PassArgs a = base_args(c, M, 0, 0, false);
+  int wpb = 0;
+  for (int w = tk::kWavesPerBlock; w >= 1 && !wpb; w /= 2)
+    if (tk::grad_lds_bytes(*c->var, w, a.kbuf) <= tk::kLdsBytes) wpb = w;
+  if (!wpb) return fail(c, TK_EUNSUPPORTED, "the gradient's term vectors do not fit in LDS");
+  const int blocks = (M + wpb - 1) / wpb;
+  const size_t lds = tk::grad_lds_bytes(*c->var, wpb, a.kbuf);
+  const size_t vec = static_cast<size_t>(c->var->R) * tk::kWave * c->bulk_cplx();
+  const int nseg = (c->nt + tk::kGradCheckpoint - 1) / tk::kGradCheckpoint;
+  TK_HIP(c, c->ckpt.ensure(static_cast<size_t>(M) * nseg * vec));
+  TK_HIP(c, c->stash.ensure(static_cast<size_t>(blocks) * wpb * tk::kGradCheckpoint * vec));
+  const size_t ng = static_cast<size_t>(c->n_ctrl) * c->nt;
+  TK_HIP(c, c->gk.ensure(std::max<size_t>(ng * M, 1) * sizeof(double)));
+  TK_HIP(c, c->dJdu.ensure(std::max<size_t>(ng, 1) * sizeof(double)));
+  a.tau_out = c->tau.as<double>();
+  a.a_scol = c->b_scol.as<int>();
+  a.a_sval = c->b_sval.p;
+  a.a_ccol = c->b_ccol.as<int>();
+  a.a_cval = c->b_cval.p;
+  a.ldcol = c->ldcol.as<int>();
+  a.ldval = c->ldval.p;
+  a.wld = c->wld;
+  a.bc_max = 0.0;
+  for (int i = 0; i < c->n_ctrl; ++i) a.bc_max = std::max(a.bc_max, c->bc[i]);
+  a.path_off = c->path_off.as<int>();
+  a.path_step = c->path_step.as<int>();
+  a.path_t = c->path_t.as<double>();
+  a.path_op = c->path_op.as<int>();
+  a.ckpt = c->ckpt.p;
+  a.stash = c->stash.p;
+  a.gk = c->gk.as<double>();
+  TK_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(lds)));
+  void *args[] = {&a};
+  TimedLaunch tl(c, TK_KERNEL_GRAD);
+  TK_HIP(c, hipLaunchKernel(kern, dim3(blocks), dim3(tk::kWave * wpb), args, lds, c->stream));
+  // replay, recompute and adjoint sweeps (3 plain passes) plus the augmented
+  // series (1 + n_ctrl chains); bytes: checkpoints and the stash, written and
+  // read once, and the per-trajectory terms
+  const double bytes = 2.0 * M * nseg * c->d * c->bulk_cplx() +
+                       2.0 * M * c->nt * c->d * c->bulk_cplx() + 8.0 * ng * M;
+  rc = tl.finish(static_cast<int64_t>(M) * c->nt, (4.0 + c->n_ctrl) * pass_flops(c, c->u, M), bytes);
+  if (rc) return rc;
+  if (ng > 0) {
+    const double *gp = c->gk.as<double>();
+    double *op_ = c->dJdu.as<double>();
+    int m = M;
+    void *rargs[] = {&gp, &m, &op_};
+    TK_HIP(c, hipLaunchKernel(tk::grad_reduce_kernel(), dim3(static_cast<unsigned>(ng)),
+                              dim3(tk::kWave), rargs, 0, c->stream));
+  }
+  return TK_OK;
+}
+
 int functional_value(tk_ctx *c, int M, double *J) {
   // J_T = 1 - (1/M) sum_k |tau_k|^2, reduced on the device in a fixed order
   TK_HIP(c, c->jt_dev.ensure(sizeof(double)));
@@ -807,8 +915,13 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   const int ws = std::max(A.max_row(), Ad.max_row());
   int wc = 1;
   for (int i = 0; i < n_ctrl; ++i) wc = std::max({wc, hc[i].max_row(), hcd[i].max_row()});
-  int wl = 1;
-  for (int l = 0; l < n_jump; ++l) wl = std::max(wl, lj[l].max_row());
+  int wl = 1, wld = 1;
+  std::vector<Csr> ljd(n_jump);
+  for (int l = 0; l < n_jump; ++l) {
+    ljd[l] = adjoint(lj[l]);
+    wl = std::max(wl, lj[l].max_row());
+    wld = std::max(wld, ljd[l].max_row());
+  }
   const int nc = n_ctrl * wc;
   const int r_need = static_cast<int>((d + tk::kWave - 1) / tk::kWave);
 
@@ -831,6 +944,7 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   c->n_jump = n_jump;
   c->wc = wc;
   c->wl = wl;
+  c->wld = wld;
   c->H_ctrl_host = hc;
 
   const int R = best->R;
@@ -850,6 +964,11 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   if (lp.empty()) lp.push_back(nullptr);
   pack(lp, wl, R, nbg, e);
   if ((rc = upload_ell(c, e, c->lcol, c->lval))) return rc;
+  std::vector<const Csr *> ldp;
+  for (int l = 0; l < n_jump; ++l) ldp.push_back(&ljd[l]);
+  if (ldp.empty()) ldp.push_back(nullptr);
+  pack(ldp, wld, R, nbg, e);
+  if ((rc = upload_ell(c, e, c->ldcol, c->ldval))) return rc;
 
   c->b0 = norm2_estimate(A);
   for (int i = 0; i < tk::kMaxCtrl; ++i) c->bc[i] = i < n_ctrl ? norm2_estimate(hc[i]) : 0.0;
@@ -1016,6 +1135,26 @@ int tk_functional(tk_ctx *c, int32_t M, uint64_t seed, uint64_t iteration, doubl
   if (tau_out)
     TK_HIP(c, hipMemcpy(tau_out, c->tau.p, 2 * static_cast<size_t>(M) * sizeof(double),
                         hipMemcpyDeviceToHost));
+  return TK_OK;
+}
+
+int tk_grad_pathwise(tk_ctx *c, int32_t M, const tk_jump *rec, int64_t n_rec, double *J_T,
+                     double *tau_out, double *dJdu) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!J_T || !dJdu) return fail(c, TK_EINVAL, "J_T or dJdu is NULL");
+  int rc = prepare_pass(c, M, 0);
+  if (rc) return rc;
+  if ((rc = reset_counters(c))) return rc;
+  if ((rc = run_grad(c, M, rec, n_rec))) return rc;
+  if ((rc = check_kernel_errors(c))) return rc;
+  if ((rc = functional_value(c, M, J_T))) return rc;
+  const size_t ng = static_cast<size_t>(c->n_ctrl) * c->nt;
+  if (ng > 0) TK_HIP(c, hipMemcpy(dJdu, c->dJdu.p, ng * sizeof(double), hipMemcpyDeviceToHost));
+  if (tau_out)
+    TK_HIP(c, hipMemcpy(tau_out, c->tau.p, 2 * static_cast<size_t>(M) * sizeof(double),
+                        hipMemcpyDeviceToHost));
+  c->tau_M = -1;  // the overlaps now belong to the replay, not to a forward pass
   return TK_OK;
 }
 

@@ -19,6 +19,7 @@ constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 compute unit
 constexpr int kMaxSubsteps = 4096;    // substeps per time step before an error
 constexpr int kPollPerLane = 4;       // blocks polled by one lane in the Krotov pass
 constexpr int kMaxBlocks = kWave * kPollPerLane;  // blocks of one Krotov launch
+constexpr int kGradCheckpoint = 64;   // steps between forward checkpoints (gradient)
 
 // error bits a kernel may raise (device int, OR-ed)
 constexpr int kErrNoJumpWeight = 1;  // jump with all ||L_l psi||^2 == 0
@@ -88,6 +89,22 @@ struct PassArgs {
   unsigned long long *slots;  // [nt][kMaxBlocks][NC] per-block partial sums
   int traj_per_wave;        // trajectories owned by one wave
   long long spin_limit;     // polls before a step reduction gives up
+  // pathwise gradient with the jump record fixed
+  const int *a_scol;        // adjoint operator H_eff^+: static slots
+  const void *a_sval;
+  const int *a_ccol;        // adjoint control slots (H_i^+ = H_i)
+  const void *a_cval;
+  const int *ldcol;         // adjoint jump operators L_l^+ [l][w][m][lane]
+  const void *ldval;
+  int wld;                  // slots per row of each L_l^+
+  double bc_max;            // max_i bc[i]
+  const int *path_off;      // [M + 1] first jump of each trajectory
+  const int *path_step;     // [n] step of each jump (time order per trajectory)
+  const double *path_t;     // [n] jump time
+  const int *path_op;       // [n] operator
+  void *ckpt;               // [M][nseg][64 R] forward checkpoints (bulk)
+  void *stash;              // [waves][kGradCheckpoint][64 R] step-start states (bulk)
+  double *gk;               // [n_ctrl][nt][M] per-trajectory gradient terms
 };
 
 // One compiled kernel variant: bulk precision, rows per lane R, static slots
@@ -100,6 +117,7 @@ struct Variant {
   const void *k_backward;
   const void *k_krotov;
   const void *k_fill;  // slot initialisation
+  const void *k_grad;  // pathwise gradient (replay + reverse sweep)
 };
 
 // Table of compiled variants (defined in tk_kernels.hip).
@@ -107,6 +125,14 @@ const Variant *variants(int *count);
 
 // Kernel reducing J_T = 1 - (1/M) sum |tau_k|^2 (one block of 256 threads).
 const void *functional_kernel();
+
+// Gradient kernel of a variant (defined in tk_grad.hip), and the kernel that
+// reduces the per-trajectory terms: one 64-thread block per pulse value.
+const void *grad_kernel(int precision, int R, int WS, int NC);
+const void *grad_reduce_kernel();
+
+// LDS bytes of one block of the gradient kernel with `waves` waves.
+size_t grad_lds_bytes(const Variant &v, int waves, int kbuf);
 
 // LDS bytes of one block of `waves` waves: the block's copy of the control
 // slots, then per wave `kbuf` term vectors of 64 R + 1 elements and, for the

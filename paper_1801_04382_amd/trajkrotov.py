@@ -38,6 +38,7 @@ TK_FP32 = 1
 TK_KERNEL_FORWARD = 0
 TK_KERNEL_BACKWARD = 1
 TK_KERNEL_KROTOV = 2
+TK_KERNEL_GRAD = 3
 
 STATUS_NAMES = {
     0: "TK_OK", -1: "TK_EINVAL", -2: "TK_EDIM", -3: "TK_ENOMEM", -4: "TK_EHIP",
@@ -98,6 +99,8 @@ _SIGNATURES = {
     "tk_krotov_iterate": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64,
                                          ctypes.c_uint64, ctypes.c_int32, _dp, _P(tk_jump),
                                          ctypes.c_int64, _P(ctypes.c_int64)]),
+    "tk_grad_pathwise": (ctypes.c_int, [_ctx_p, ctypes.c_int32, _P(tk_jump), ctypes.c_int64,
+                                        _dp, _dp, _dp]),
     "tk_set_timing": (ctypes.c_int, [_ctx_p, ctypes.c_int]),
     "tk_get_timing": (ctypes.c_int, [_ctx_p, ctypes.c_int, _P(tk_kernel_timing)]),
     "tk_reset_timing": (ctypes.c_int, [_ctx_p]),
@@ -281,6 +284,18 @@ def tk_krotov_iterate(ctx: int, M: int, seed: int, n_iter: int, first_iteration:
     return J[:nout], records_array(buf, min(n.value, rec_cap)), n.value
 
 
+def tk_grad_pathwise(ctx: int, M: int, records: np.ndarray, n_ctrl: int, nt: int):
+    """J_T, overlaps and dJ_T/du [n_ctrl, nt] of the replay with the records fixed."""
+    rec = np.ascontiguousarray(records, dtype=JUMP_DTYPE)
+    J = ctypes.c_double(0.0)
+    tau = np.zeros(M, dtype=np.complex128)
+    g = np.zeros(max(n_ctrl * nt, 1))
+    _check(ctx, _lib.tk_grad_pathwise(ctx, M, rec.ctypes.data_as(_P(tk_jump)) if rec.size else None,
+                                      rec.size, ctypes.byref(J), _dptr(tau.view(np.float64)),
+                                      _dptr(g)))
+    return J.value, tau, g[:n_ctrl * nt].reshape(n_ctrl, nt)
+
+
 def tk_set_timing(ctx: int, enable: bool) -> None:
     _check(ctx, _lib.tk_set_timing(ctx, 1 if enable else 0))
 
@@ -350,6 +365,7 @@ class Context:
             np.zeros((0, int(np.asarray(u).shape[-1])))
         tk_set_pulses(self.h, u, T, S, lam)
         self.nt = u.shape[1]
+        self.T, self.S, self.lam = float(T), S, lam
 
     def load(self, w):
         """Set system, states and pulses from a workloads.Workload."""
@@ -377,6 +393,9 @@ class Context:
     def krotov_iterate(self, M, seed, n_iter, first_iteration=0, rec_cap=None):
         cap = (8 * M + 64) * (n_iter + 1) if rec_cap is None else rec_cap
         return tk_krotov_iterate(self.h, M, seed, n_iter, first_iteration, cap)
+
+    def grad_pathwise(self, M, records):
+        return tk_grad_pathwise(self.h, M, records, self.n_ctrl, self.nt)
 
     def set_timing(self, enable=True):
         tk_set_timing(self.h, enable)
