@@ -255,6 +255,71 @@ TK_API int tk_krotov_iterate(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t fir
 TK_API int tk_grad_pathwise(tk_ctx *ctx, int32_t M, const tk_jump *rec, int64_t n_rec,
                      double *J_T, double *tau_out, double *dJdu);
 
+/* ---- batched form: many optimisation instances at once --------------------- */
+
+/* A batch holds independent optimisation instances -- each a full problem as
+ * set by tk_set_system / tk_set_states / tk_set_pulses, with its own M and
+ * seed -- and advances all of them together: one launch runs the costate
+ * passes of every instance, one persistent launch runs their sequential
+ * Krotov passes side by side (each instance with its own per-step reduction),
+ * and one iteration of every instance is replayed as a HIP graph.  Instances
+ * may differ in Hilbert dimension, sparsity, M and nt.  The instance id is
+ * part of the random streams' key ([seed, (id << 32) | k], Sec. 2.1 MCWF
+ * random numbers), so an instance's trajectories do not depend on the other
+ * instances.  The per-step reduction of an instance sums the trajectories'
+ * FP64 shares in one fixed order, independent of the tile shapes: results are
+ * bit-identical whatever the autotuner picks and whatever else is in the
+ * batch (they may differ from tk_krotov_iterate in the last bits, whose
+ * reduction order follows its launch shape). */
+typedef struct tk_batch tk_batch; /* opaque */
+
+typedef struct tk_batch_info {
+  int32_t n_instances;
+  int32_t pass_waves_per_block;    /* plain (costate / guess) passes         */
+  int32_t pass_blocks;
+  int32_t krotov_waves_per_block;  /* persistent Krotov launch               */
+  int32_t krotov_blocks;
+  int32_t autotuned;               /* 1 once the tile shapes are chosen      */
+  double last_iteration_ms;        /* last replayed iteration (HIP events)  */
+  double tuned_pass_ms;            /* best costate pass seen by the tuner   */
+  double tuned_krotov_ms;          /* best Krotov pass seen by the tuner    */
+  int64_t traj_steps_per_iteration; /* sum over instances of 2 M nt         */
+} tk_batch_info;
+
+/* Create an empty batch on `device` in `precision` (as tk_create). */
+TK_API int tk_batch_create(tk_batch **out, int device, int precision);
+TK_API void tk_batch_destroy(tk_batch *batch);
+TK_API const char *tk_batch_last_error(const tk_batch *batch);
+
+/* Add an instance: the arguments of tk_set_system, tk_set_states and
+ * tk_set_pulses, its trajectory count M and seed, and a distinct instance id
+ * for the random streams.  *index_out receives its position in the batch.
+ * Only before the first tk_batch_krotov_iterate.  Errors: as those calls,
+ * TK_EINVAL (duplicate id, M < 1), TK_ESTATE, TK_EUNSUPPORTED. */
+TK_API int tk_batch_add(tk_batch *batch, uint32_t instance_id, int64_t d, const tk_csr *H0,
+                 int32_t n_ctrl, const tk_csr *H_ctrl, int32_t n_jump, const tk_csr *L_jump,
+                 const double *psi0, const double *psi_tgt, int32_t nt, double T,
+                 const double *u, const double *S, const double *lambda, int32_t M,
+                 uint64_t seed, int32_t *index_out);
+
+/* Krotov iterations of every instance, as tk_krotov_iterate: first_iteration
+ * 0 runs the guess passes (iteration 0) and iterations 1..n_iter, writing
+ * n_iter + 1 values per instance; first_iteration = n0 continues the previous
+ * call (n0 must be the next iteration) and writes n_iter values.  J_T_out is
+ * [n_instances][n_out] (row per instance); n_out <= 64.  The first iteration
+ * runs pass by pass while an autotuner times candidate tile shapes (waves per
+ * block, blocks per instance); later iterations replay a captured graph.
+ * Errors: TK_ESTATE (no instances, wrong first_iteration), TK_EINVAL,
+ * TK_ENOMEM, TK_EHIP, TK_ENUMERIC, TK_EUNSUPPORTED. */
+TK_API int tk_batch_krotov_iterate(tk_batch *batch, uint64_t first_iteration, int32_t n_iter,
+                            double *J_T_out);
+
+/* Current pulses of instance `index`, u_out [n_ctrl * nt]. */
+TK_API int tk_batch_get_pulses(tk_batch *batch, int32_t index, double *u_out);
+
+/* Launch shapes and timings of the batch. */
+TK_API int tk_batch_get_info(const tk_batch *batch, tk_batch_info *out);
+
 /* ---- instrumentation ------------------------------------------------------ */
 
 /* Enable (1) or disable (0) HIP-event timing of every kernel launch. */

@@ -1,0 +1,371 @@
+// Batched kernels: many independent optimisation instances in one launch.
+//
+// Every instance has its own system (operator slices), states, pulses,
+// costates and random streams (the instance index is part of the Philox key),
+// and its own kernel shape (rows per lane, slots); a launch serves all of them
+// and selects the shape per instance with a switch, so one persistent grid
+// runs instances of different Hilbert dimension side by side.
+//
+// Plain passes (guess forward, costates): a list of (instance, trajectory)
+// items, costliest first, dealt round-robin to the waves; an item is one
+// trajectory over all of its instance's steps, computed by the same device
+// code as the single-system passes.
+//
+// Sequential Krotov pass: each instance owns a contiguous range of blocks,
+// all co-resident.  Trajectory states live in device memory between steps.
+// After a trajectory reaches t_j its own FP64 share of
+// s_ij = sum_k Im <chi_k(t_j)|H_i|psi_hat_k(t_j)> is published into a
+// per-trajectory slot (initialised to a sentinel); every block of the instance
+// waits for the M shares of step j and sums them in one fixed order (lane l
+// adds k = l, l + 64, ... in increasing k; then the wave tree).  The update is
+// therefore independent of how trajectories are split over waves and blocks:
+// an instance gives bit-identical pulses whatever the tile shape chosen and
+// whatever else runs in the batch.
+#include <hip/hip_runtime.h>
+
+#include "tk_device.h"
+#include "tk_internal.h"
+
+namespace tk {
+namespace {
+
+// Kernel shapes of the batch, in the order of variants() within a precision.
+#define TK_BATCH_SHAPES(X) \
+  X(0, 1, 4, 2)            \
+  X(1, 2, 4, 2)            \
+  X(2, 4, 6, 3)            \
+  X(3, 4, 8, 4)
+
+// ---- plain passes ------------------------------------------------------------
+template <typename real, int R, int WS, int NC, int DIR>
+__device__ void batch_pass_item(const PassArgs &a, int k, uint64_t it, unsigned char *wave_lds,
+                                int lane) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  cx<real> *cval_lds = reinterpret_cast<cx<real> *>(wave_lds);
+  const cx<real> *cval_g = static_cast<const cx<real> *>(a.cval);
+  wave_sync();  // the previous item's reads of this wave's LDS are done
+  for (int i = lane; i < NCX * R * kWave; i += kWave) cval_lds[i] = cval_g[i];
+  Terms<real, R> T;
+  T.base = cval_lds + NCX * R * kWave;
+  if (lane < a.kbuf) T[lane][R * kWave] = cx<real>{0, 0};
+  wave_sync();
+  LaneOp<real, R, WS, NC> op;
+  op.load(a.scol, a.sval, a.ccol, cval_lds, lane);
+  pass_trajectory<real, R, WS, NC, DIR>(op, a, T, k, make_stream(a, k, DIR, it), lane);
+}
+
+template <typename real, int DIR>
+__global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_pass(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wpb = blockDim.x / kWave;
+  unsigned char *wl = smem_raw + static_cast<size_t>(wib) * b.wave_lds;
+  const uint64_t it = *b.iteration;
+  const int nwaves = gridDim.x * wpb;
+  for (int q = blockIdx.x * wpb + wib; q < b.n_items; q += nwaves) {
+    const int2 item = b.items[q];
+    const BatchInstance &I = b.inst[__builtin_amdgcn_readfirstlane(item.x)];
+    const PassArgs &a = DIR == 0 ? I.fw : I.bw;
+    const int k = __builtin_amdgcn_readfirstlane(item.y);
+    switch (I.variant) {
+#define TK_CASE(idx, R, WS, NC) \
+  case idx:                     \
+    batch_pass_item<real, R, WS, NC, DIR>(a, k, it, wl, lane); \
+    break;
+      TK_BATCH_SHAPES(TK_CASE)
+#undef TK_CASE
+      default:
+        break;
+    }
+  }
+}
+
+// ---- sequential Krotov pass ------------------------------------------------------
+// slots[(j M + k) NCX + i] <- the trajectory's share of control i (lane 0)
+template <int NC>
+__device__ __forceinline__ void publish_share(const PassArgs &a, unsigned long long *row, int k,
+                                              const double (&pc)[NC > 0 ? NC : 1], int lane) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  double sc[NCX];
+#pragma unroll
+  for (int c = 0; c < NCX; ++c) sc[c] = c < NC ? wave_sum(pc[c]) : 0.0;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NCX; ++i) {
+      double s = 0.0;  // control i owns slots i wc .. i wc + wc - 1
+#pragma unroll
+      for (int c = 0; c < NCX; ++c)
+        if (c >= i * a.wc && c < (i + 1) * a.wc) s += sc[c];
+      __hip_atomic_store(&row[static_cast<size_t>(k) * NCX + i], __double_as_longlong(s),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Waits for the M shares of one step and sums them in a fixed order (lane l
+// takes k = l, l + 64, ... in increasing k; then the wave reduction).
+// Returns false if the spin limit is reached or another block gave up.
+template <int NCX>
+__device__ bool gather_shares(const unsigned long long *row, int M, int lane,
+                              long long spin_limit, int *err, double (&acc)[NCX]) {
+  constexpr int CH = 4;  // 64-trajectory groups whose loads are in flight together
+#pragma unroll
+  for (int c = 0; c < NCX; ++c) acc[c] = 0.0;
+  long long spins = 0;
+  for (int q0 = 0; q0 * kWave < M; q0 += CH) {
+    unsigned long long v[CH][NCX];
+    for (;;) {
+#pragma unroll
+      for (int qq = 0; qq < CH; ++qq) {
+        const int k = lane + kWave * (q0 + qq);
+#pragma unroll
+        for (int c = 0; c < NCX; ++c)
+          v[qq][c] = k < M ? __hip_atomic_load(&row[static_cast<size_t>(k) * NCX + c],
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : 0ull;
+      }
+      int missing = 0;
+#pragma unroll
+      for (int qq = 0; qq < CH; ++qq)
+#pragma unroll
+        for (int c = 0; c < NCX; ++c) missing |= v[qq][c] == kSlotEmpty;
+      if (!__any(missing)) break;
+      if (++spins > spin_limit ||
+          ((spins & 255) == 0 &&
+           (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrSyncTimeout)))
+        return false;
+    }
+#pragma unroll
+    for (int qq = 0; qq < CH; ++qq)
+#pragma unroll
+      for (int c = 0; c < NCX; ++c) acc[c] += __longlong_as_double(static_cast<long long>(v[qq][c]));
+  }
+#pragma unroll
+  for (int c = 0; c < NCX; ++c) acc[c] = wave_sum(acc[c]);
+  return true;
+}
+
+template <typename real, int R, int WS, int NC>
+__device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I, int lb,
+                                      uint64_t it, unsigned char *smem, double *s_upd,
+                                      int *s_abort) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  constexpr int kRows = R * kWave;
+  const PassArgs &a = I.fw;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wpb = blockDim.x / kWave;
+  LaneOp<real, R, WS, NC> op;
+  const Terms<real, R> T =
+      block_setup<real, R, WS, NC>(a, smem, wib, lane, terms_bytes<real, R>(a.kbuf), op);
+  const int nw = I.nblocks * wpb;
+  const int w = lb * wpb + wib;
+  cx<real> *psi_g = static_cast<cx<real> *>(I.psi);
+  TrajMeta *meta_g = I.meta;
+  cx<real> *v = T[0];  // scratch vector for the update's gathers
+  const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
+  const size_t row_len = static_cast<size_t>(a.M) * NCX;
+
+  // ---- start states and their shares at t_0 ----
+  for (int k = w; k < a.M; k += nw) {
+    cx<real> p[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      p[m] = start[lane + kWave * m];
+      psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m] = p[m];
+    }
+    const double n = norm2(p);
+    if (lane == 0) {
+      TrajMeta st;
+      st.nrm2 = n;
+      st.r = make_stream(a, k, 0, it).threshold(0);
+      st.ordinal = 0;
+      st.pad = 0;
+      meta_g[k] = st;
+    }
+    cx<real> ch[R];
+    load_costate<real, R>(a, 0, k, lane, ch);
+    double pc[NCX];
+#pragma unroll
+    for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
+    wave_sync();
+    store_lds(v, p, lane);
+    wave_sync();
+    krotov_share<real, R, WS, NC>(op, v, ch, 1.0 / sqrt(n), pc);
+    publish_share<NC>(a, I.tslots, k, pc, lane);
+  }
+
+  double uo[NCX], sf[NCX], inv_lm[NCX];
+#pragma unroll
+  for (int i = 0; i < NCX; ++i) {
+    inv_lm[i] = 1.0 / (a.lam[i] * a.M);
+    uo[i] = a.u_old[static_cast<size_t>(i) * a.nt];
+    sf[i] = a.S[static_cast<size_t>(i) * a.nt] * inv_lm[i];
+  }
+  for (int j = 0; j < a.nt; ++j) {
+    __syncthreads();  // every wave has used the previous step's s_upd
+    if (wib == 0) {
+      double acc[NCX];
+      const bool ok = a.n_ctrl == 0 ||
+                      gather_shares<NCX>(I.tslots + static_cast<size_t>(j) * row_len, a.M, lane,
+                                         b.spin_limit, b.err, acc);
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < NCX; ++c) s_upd[c] = ok && a.n_ctrl > 0 ? acc[c] : 0.0;
+        if (!ok) {
+          atomicOr(b.err, kErrSyncTimeout);
+          *s_abort = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (*s_abort) return;  // uniform across the block
+    double uj[NCX];
+#pragma unroll
+    for (int i = 0; i < NCX; ++i) uj[i] = uo[i] + sf[i] * s_upd[i];
+    if (lb == 0 && threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) a.u_new[static_cast<size_t>(i) * a.nt + j] = uj[i];
+    }
+    if (j + 1 < a.nt) {
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) {
+        const size_t ij = static_cast<size_t>(i) * a.nt + j + 1;
+        uo[i] = a.u_old[ij];
+        sf[i] = a.S[ij] * inv_lm[i];
+      }
+    }
+    op.set_pulses(uj, a.wc);
+    const StepPlan p = plan_step(a, uj);
+    for (int k = w; k < a.M; k += nw) {
+      cx<real> ch[R];
+      if (j + 1 < a.nt) load_costate<real, R>(a, j + 1, k, lane, ch);
+      cx<real> psi[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m];
+      TrajMeta st = meta_g[k];
+      const Stream rng = make_stream(a, k, 0, it);
+      advance_step<real, R, WS, NC, 0>(op, a, T, psi, st, rng, j, p, k, lane);
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m] = psi[m];
+      if (lane == 0) meta_g[k] = st;
+      if (j + 1 < a.nt) {
+        double pc[NCX];
+#pragma unroll
+        for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
+        wave_sync();
+        store_lds(v, psi, lane);
+        wave_sync();
+        krotov_share<real, R, WS, NC>(op, v, ch, 1.0 / sqrt(st.nrm2), pc);
+        publish_share<NC>(a, I.tslots + static_cast<size_t>(j + 1) * row_len, k, pc, lane);
+      }
+      wave_sync();
+    }
+  }
+  // ---- tau_k = <tgt|psi_hat_k(T)> ----
+  for (int k = w; k < a.M; k += nw) {
+    const double inv = 1.0 / sqrt(meta_g[k].nrm2);
+    double tr = 0.0, ti = 0.0;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int row = lane + kWave * m;
+      const cx<real> q = psi_g[static_cast<size_t>(k) * kRows + row];
+      const double px = q.x * inv, py = q.y * inv;
+      const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
+      tr = fma(gx, px, fma(gy, py, tr));
+      ti = fma(gx, py, fma(-gy, px, ti));
+    }
+    tr = wave_sum(tr);
+    ti = wave_sum(ti);
+    if (lane == 0) {
+      a.tau_out[2 * k] = tr;
+      a.tau_out[2 * k + 1] = ti;
+    }
+  }
+}
+
+template <typename real>
+__global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double s_upd[kMaxCtrl];
+  __shared__ int s_abort;
+  if (threadIdx.x == 0) s_abort = 0;
+  const int i = __builtin_amdgcn_readfirstlane(b.block_inst[blockIdx.x]);
+  const BatchInstance &I = b.inst[i];
+  const int lb = blockIdx.x - I.block0;
+  const uint64_t it = *b.iteration;
+  switch (I.variant) {
+#define TK_CASE(idx, R, WS, NC)                                                         \
+  case idx:                                                                             \
+    batch_krotov_instance<real, R, WS, NC>(b, I, lb, it, smem_raw, s_upd, &s_abort); \
+    break;
+    TK_BATCH_SHAPES(TK_CASE)
+#undef TK_CASE
+    default:
+      break;
+  }
+}
+
+// ---- bookkeeping kernels ------------------------------------------------------------
+// Per-trajectory slots of every instance <- sentinel (one block per instance).
+__global__ __launch_bounds__(256) void k_batch_fill(BatchArgs b) {
+  const BatchInstance &I = b.inst[blockIdx.x];
+  const size_t n = static_cast<size_t>(I.fw.nt) * I.fw.M * I.ncx;
+  for (size_t q = threadIdx.x; q < n; q += blockDim.x) I.tslots[q] = kSlotEmpty;
+}
+
+// J_T = 1 - (1/M) sum_k |tau_k|^2 of every instance (one block each, fixed
+// order), kept in the history ring at the current iteration.
+__global__ __launch_bounds__(256) void k_batch_functional(BatchArgs b) {
+  __shared__ double part[256];
+  const BatchInstance &I = b.inst[blockIdx.x];
+  const double *tau = I.fw.tau_out;
+  const int M = I.fw.M;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < M; k += 256)
+    s = fma(tau[2 * k], tau[2 * k], fma(tau[2 * k + 1], tau[2 * k + 1], s));
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    b.J_hist[static_cast<size_t>(blockIdx.x) * kBatchHistory + (*b.iteration % kBatchHistory)] =
+        1.0 - part[0] / static_cast<double>(M);
+}
+
+// End of an iteration: the updated pulses become the current ones (one block
+// per instance); block 0 advances the iteration counter after every block has
+// read it (the counter is read only by the next launches).
+__global__ __launch_bounds__(256) void k_batch_finish(BatchArgs b, int copy_pulses) {
+  const BatchInstance &I = b.inst[blockIdx.x];
+  if (copy_pulses) {
+    const size_t n = static_cast<size_t>(I.fw.n_ctrl) * I.fw.nt;
+    double *u = const_cast<double *>(I.fw.u_old);
+    for (size_t q = threadIdx.x; q < n; q += blockDim.x) u[q] = I.fw.u_new[q];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *b.iteration += 1;
+}
+
+}  // namespace
+
+BatchKernels batch_kernels(int precision) {
+  BatchKernels k;
+  if (precision == TK_FP64) {
+    k.pass_fw = reinterpret_cast<const void *>(&k_batch_pass<double, 0>);
+    k.pass_bw = reinterpret_cast<const void *>(&k_batch_pass<double, 1>);
+    k.krotov = reinterpret_cast<const void *>(&k_batch_krotov<double>);
+  } else {
+    k.pass_fw = reinterpret_cast<const void *>(&k_batch_pass<float, 0>);
+    k.pass_bw = reinterpret_cast<const void *>(&k_batch_pass<float, 1>);
+    k.krotov = reinterpret_cast<const void *>(&k_batch_krotov<float>);
+  }
+  k.fill = reinterpret_cast<const void *>(&k_batch_fill);
+  k.functional = reinterpret_cast<const void *>(&k_batch_functional);
+  k.finish = reinterpret_cast<const void *>(&k_batch_finish);
+  return k;
+}
+
+}  // namespace tk

@@ -1,0 +1,575 @@
+// Host driver of the batched form: many independent optimisation instances,
+// each a full problem (system, states, pulses, M, seed), advanced together.
+//
+// Every instance is held by a context of its own (operator packing, pulses and
+// per-instance buffers come from the single-system code); the batch adds the
+// buffers of the batched Krotov pass, the instance table the kernels read,
+// the launch plan, an autotuner for the tile shapes and a HIP graph that
+// replays one Krotov iteration of every instance.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "tk_host_internal.h"
+#include "tk_internal.h"
+
+using namespace tkh;
+
+namespace {
+
+struct Member {
+  tk_ctx *c = nullptr;
+  uint32_t id = 0;  // instance index in the random streams' key
+  int M = 0;
+  uint64_t seed = 0;
+  int variant = -1;  // index among the kernel shapes of the precision
+  int kbuf_fw = 0, kbuf_bw = 0;
+  double step_cost = 0.0;  // model of one trajectory-step (relative units)
+  DevBuf psi, meta, tslots;
+  ~Member() {
+    if (c) tk_destroy(c);
+  }
+};
+
+struct LaunchPlan {
+  int pass_wpb = 0, pass_blocks = 0;
+  int kro_wpb = 0, kro_blocks = 0;
+  size_t pass_lds = 0, kro_lds = 0;
+  std::vector<int> nblocks;  // Krotov blocks per instance
+};
+
+}  // namespace
+
+struct tk_batch {
+  int device = 0;
+  int precision = TK_FP64;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+  int n_cu = 0;
+  std::vector<std::unique_ptr<Member>> mem;
+  tk::BatchKernels kern{};
+  bool ready = false;
+  uint64_t next_iter = 0;  // iteration the next call starts with
+  LaunchPlan plan;
+  bool tuned = false;
+  DevBuf inst_dev, items_dev, block_inst_dev, iter_dev, J_hist_dev, err_dev, rec_dev, rec_count_dev;
+  std::vector<tk::BatchInstance> inst;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  double last_iter_ms = 0.0, tuned_pass_ms = 0.0, tuned_krotov_ms = 0.0;
+  int64_t traj_steps = 0;
+};
+
+namespace {
+
+int bfail(tk_batch *b, int code, const std::string &msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+int bhip(tk_batch *b, hipError_t e, const char *what) {
+  return bfail(b, e == hipErrorOutOfMemory ? TK_ENOMEM : TK_EHIP,
+               std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define TK_BHIP(b, call)                              \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return bhip(b, e_, #call);  \
+  } while (0)
+
+int shape_index(const tk::Variant *v) {
+  int nv = 0;
+  const tk::Variant *vs = tk::variants(&nv);
+  int idx = 0;
+  for (int k = 0; k < nv; ++k) {
+    if (vs[k].precision != v->precision) continue;
+    if (&vs[k] == v) return idx;
+    ++idx;
+  }
+  return -1;
+}
+
+size_t cplx_bytes(int precision) { return precision == TK_FP64 ? 16 : 8; }
+
+// LDS bytes per wave of the batched plain passes for member m
+size_t pass_wave_lds(const tk_batch *b, const Member &m) {
+  const tk::Variant &v = *m.c->var;
+  const size_t ncx = v.NC > 0 ? v.NC : 1;
+  const size_t kb = std::max(m.kbuf_fw, m.kbuf_bw);
+  const size_t bytes =
+      (ncx * v.R * tk::kWave + kb * (v.R * tk::kWave + 1)) * cplx_bytes(b->precision);
+  return (bytes + 15) / 16 * 16;
+}
+
+// Krotov blocks per instance: every instance gets one, then blocks go one at a
+// time to the instance with the longest estimated pass,
+//   nt (ceil(M / (blocks * wpb)) step_cost + sync_cost),
+// until `capacity` blocks are given out or the longest cannot gain.
+std::vector<int> split_blocks(const tk_batch *b, int capacity, int wpb, double sync_cost) {
+  const size_t n = b->mem.size();
+  std::vector<int> nb(n, 1);
+  auto est = [&](size_t i) {
+    const Member &m = *b->mem[i];
+    const double tw = std::ceil(static_cast<double>(m.M) / (static_cast<double>(nb[i]) * wpb));
+    return m.c->nt * (tw * m.step_cost + sync_cost);
+  };
+  int used = static_cast<int>(n);
+  while (used < capacity) {
+    size_t worst = 0;
+    for (size_t i = 1; i < n; ++i)
+      if (est(i) > est(worst)) worst = i;
+    const Member &m = *b->mem[worst];
+    if (nb[worst] >= tk::kMaxBlocks || static_cast<int64_t>(nb[worst]) * wpb >= m.M) break;
+    nb[worst]++;
+    used++;
+  }
+  return nb;
+}
+
+// Instance table and Krotov block map for a launch plan.
+int upload_tables(tk_batch *b) {
+  const size_t n = b->mem.size();
+  std::vector<int> block_inst;
+  for (size_t i = 0; i < n; ++i) {
+    b->inst[i].block0 = static_cast<int>(block_inst.size());
+    b->inst[i].nblocks = b->plan.nblocks[i];
+    for (int q = 0; q < b->plan.nblocks[i]; ++q) block_inst.push_back(static_cast<int>(i));
+  }
+  b->plan.kro_blocks = static_cast<int>(block_inst.size());
+  TK_BHIP(b, b->inst_dev.ensure(n * sizeof(tk::BatchInstance)));
+  TK_BHIP(b, hipMemcpy(b->inst_dev.p, b->inst.data(), n * sizeof(tk::BatchInstance),
+                       hipMemcpyHostToDevice));
+  TK_BHIP(b, b->block_inst_dev.ensure(block_inst.size() * sizeof(int)));
+  TK_BHIP(b, hipMemcpy(b->block_inst_dev.p, block_inst.data(), block_inst.size() * sizeof(int),
+                       hipMemcpyHostToDevice));
+  return TK_OK;
+}
+
+tk::BatchArgs batch_args(tk_batch *b) {
+  tk::BatchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.inst = b->inst_dev.as<tk::BatchInstance>();
+  a.n_inst = static_cast<int>(b->mem.size());
+  a.wave_lds = static_cast<int>(b->plan.pass_lds / std::max(b->plan.pass_wpb, 1));
+  a.items = b->items_dev.as<int2>();
+  int64_t items = 0;
+  for (const auto &m : b->mem) items += m->M;
+  a.n_items = static_cast<int>(items);
+  a.block_inst = b->block_inst_dev.as<int>();
+  a.iteration = b->iter_dev.as<uint64_t>();
+  a.J_hist = b->J_hist_dev.as<double>();
+  a.err = b->err_dev.as<int>();
+  a.spin_limit = 1ll << 22;
+  return a;
+}
+
+// Pass plan with `wpb` waves per block: as many blocks as are co-resident.
+int plan_pass(tk_batch *b, int wpb) {
+  size_t wl = 0;
+  for (const auto &m : b->mem) wl = std::max(wl, pass_wave_lds(b, *m));
+  const size_t lds = wl * wpb;
+  if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
+  for (const void *k : {b->kern.pass_fw, b->kern.pass_bw})
+    TK_BHIP(b, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(lds)));
+  int occ = 0;
+  TK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, b->kern.pass_bw, tk::kWave * wpb,
+                                                          lds));
+  if (occ < 1) return TK_EUNSUPPORTED;
+  int64_t items = 0;
+  for (const auto &m : b->mem) items += m->M;
+  const int64_t blocks = std::min<int64_t>(static_cast<int64_t>(occ) * b->n_cu, (items + wpb - 1) / wpb);
+  b->plan.pass_wpb = wpb;
+  b->plan.pass_lds = lds;
+  b->plan.pass_blocks = static_cast<int>(std::max<int64_t>(blocks, 1));
+  return TK_OK;
+}
+
+// Krotov plan with `wpb` waves per block and a fraction of the co-resident blocks.
+int plan_krotov(tk_batch *b, int wpb, double frac, double sync_cost) {
+  size_t lds = 0;
+  for (const auto &m : b->mem)
+    lds = std::max(lds, tk::block_lds_bytes(*m->c->var, wpb, m->kbuf_fw, 0));
+  if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
+  TK_BHIP(b, hipFuncSetAttribute(b->kern.krotov, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 static_cast<int>(lds)));
+  int occ = 0;
+  TK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, b->kern.krotov, tk::kWave * wpb,
+                                                          lds));
+  const int capacity = static_cast<int>(frac * occ * b->n_cu);
+  if (capacity < static_cast<int>(b->mem.size())) return TK_EUNSUPPORTED;
+  b->plan.kro_wpb = wpb;
+  b->plan.kro_lds = lds;
+  b->plan.nblocks = split_blocks(b, capacity, wpb, sync_cost);
+  return upload_tables(b);
+}
+
+int launch_pass(tk_batch *b, int dir) {
+  tk::BatchArgs a = batch_args(b);
+  void *args[] = {&a};
+  TK_BHIP(b, hipLaunchKernel(dir == 0 ? b->kern.pass_fw : b->kern.pass_bw,
+                             dim3(b->plan.pass_blocks), dim3(tk::kWave * b->plan.pass_wpb), args,
+                             b->plan.pass_lds, b->stream));
+  return TK_OK;
+}
+
+int launch_krotov(tk_batch *b) {
+  tk::BatchArgs a = batch_args(b);
+  void *args[] = {&a};
+  TK_BHIP(b, hipLaunchKernel(b->kern.fill, dim3(static_cast<unsigned>(b->mem.size())), dim3(256),
+                             args, 0, b->stream));
+  // blocks are co-resident by the occupancy check of the plan; a block that
+  // waits past the spin limit aborts the pass with an error instead of hanging
+  TK_BHIP(b, hipLaunchKernel(b->kern.krotov, dim3(b->plan.kro_blocks),
+                             dim3(tk::kWave * b->plan.kro_wpb), args, b->plan.kro_lds, b->stream));
+  return TK_OK;
+}
+
+int launch_tail(tk_batch *b, int copy_pulses) {
+  tk::BatchArgs a = batch_args(b);
+  void *args[] = {&a};
+  const dim3 grid(static_cast<unsigned>(b->mem.size()));
+  TK_BHIP(b, hipLaunchKernel(b->kern.functional, grid, dim3(256), args, 0, b->stream));
+  int cp = copy_pulses;
+  void *fargs[] = {&a, &cp};
+  TK_BHIP(b, hipLaunchKernel(b->kern.finish, grid, dim3(256), fargs, 0, b->stream));
+  return TK_OK;
+}
+
+int check_errors(tk_batch *b) {
+  int e = 0;
+  TK_BHIP(b, hipMemcpyAsync(&e, b->err_dev.p, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  TK_BHIP(b, hipStreamSynchronize(b->stream));
+  if (e & tk::kErrSyncTimeout)
+    return bfail(b, TK_EHIP, "per-step reduction timed out (blocks not co-resident)");
+  if (e & tk::kErrNoJumpWeight) return bfail(b, TK_ENUMERIC, "jump with all ||L_l psi||^2 = 0");
+  if (e & tk::kErrTaylorOrder)
+    return bfail(b, TK_ENUMERIC, "time step too long for the polynomial propagator");
+  if (e & tk::kErrJumpLoop) return bfail(b, TK_ENUMERIC, "too many jumps inside one time step");
+  return TK_OK;
+}
+
+// Elapsed milliseconds of what `fn` enqueues on the batch stream.
+template <typename F>
+int timed(tk_batch *b, F fn, double *ms) {
+  TK_BHIP(b, hipEventRecord(b->ev0, b->stream));
+  int rc = fn();
+  if (rc) return rc;
+  TK_BHIP(b, hipEventRecord(b->ev1, b->stream));
+  TK_BHIP(b, hipEventSynchronize(b->ev1));
+  float f = 0.f;
+  TK_BHIP(b, hipEventElapsedTime(&f, b->ev0, b->ev1));
+  *ms = f;
+  return TK_OK;
+}
+
+// Allocations, instance table and work list (first iteration call).
+int finalize(tk_batch *b) {
+  const size_t n = b->mem.size();
+  if (n == 0) return bfail(b, TK_ESTATE, "batch has no instances");
+  b->kern = tk::batch_kernels(b->precision);
+  TK_BHIP(b, b->iter_dev.ensure(sizeof(uint64_t)));
+  TK_BHIP(b, b->J_hist_dev.ensure(n * tk::kBatchHistory * sizeof(double)));
+  TK_BHIP(b, b->err_dev.ensure(sizeof(int)));
+  TK_BHIP(b, b->rec_dev.ensure(sizeof(tk_jump)));
+  TK_BHIP(b, b->rec_count_dev.ensure(sizeof(unsigned long long)));
+  TK_BHIP(b, hipMemset(b->err_dev.p, 0, sizeof(int)));
+  TK_BHIP(b, hipMemset(b->rec_count_dev.p, 0, sizeof(unsigned long long)));
+  b->inst.assign(n, tk::BatchInstance{});
+  b->traj_steps = 0;
+  std::vector<std::pair<double, int2>> items;
+  for (size_t i = 0; i < n; ++i) {
+    Member &m = *b->mem[i];
+    tk_ctx *c = m.c;
+    const tk::Variant &v = *c->var;
+    const size_t vec = static_cast<size_t>(v.R) * tk::kWave * cplx_bytes(b->precision);
+    const int ncx = v.NC > 0 ? v.NC : 1;
+    TK_BHIP(b, c->chi.ensure(static_cast<size_t>(c->nt) * m.M * c->d * cplx_bytes(b->precision)));
+    TK_BHIP(b, c->tau.ensure(static_cast<size_t>(2) * m.M * sizeof(double)));
+    TK_BHIP(b, c->u_new_dev.ensure(static_cast<size_t>(tk::kMaxCtrl) * c->nt * sizeof(double)));
+    TK_BHIP(b, hipMemset(c->u_new_dev.p, 0, static_cast<size_t>(tk::kMaxCtrl) * c->nt * sizeof(double)));
+    TK_BHIP(b, m.psi.ensure(static_cast<size_t>(m.M) * vec));
+    TK_BHIP(b, m.meta.ensure(static_cast<size_t>(m.M) * sizeof(tk::TrajMeta)));
+    TK_BHIP(b, m.tslots.ensure(static_cast<size_t>(c->nt) * m.M * ncx * sizeof(uint64_t)));
+    m.variant = shape_index(c->var);
+    m.kbuf_fw = plan_kbuf(c, c->u, 1);
+    m.kbuf_bw = plan_kbuf(c, c->u, 0);
+    // relative cost of one trajectory-step: gathers per Taylor term times terms
+    m.step_cost = static_cast<double>(m.kbuf_fw) * v.R * (v.WS + v.NC);
+    tk::BatchInstance &I = b->inst[i];
+    I.fw = base_args(c, m.M, m.seed, 0, false);
+    I.bw = base_args(c, m.M, m.seed, 0, true);
+    for (tk::PassArgs *a : {&I.fw, &I.bw}) {
+      a->instance = m.id;
+      a->rec = b->rec_dev.as<tk_jump>();
+      a->rec_cap = 0;
+      a->rec_count = b->rec_count_dev.as<unsigned long long>();
+      a->err = b->err_dev.as<int>();
+      a->chi = c->chi.p;
+      a->spin_limit = 1ll << 22;
+    }
+    I.fw.kbuf = m.kbuf_fw;
+    I.bw.kbuf = m.kbuf_bw;
+    I.fw.psiT = nullptr;
+    I.fw.tau_out = c->tau.as<double>();
+    I.fw.u_old = c->u_dev.as<double>();
+    I.fw.u_new = c->u_new_dev.as<double>();
+    I.fw.S = c->S_dev.as<double>();
+    I.fw.lam = c->lam_dev.as<double>();
+    I.bw.tau_in = c->tau.as<double>();
+    I.variant = m.variant;
+    I.ncx = ncx;
+    I.psi = m.psi.p;
+    I.meta = m.meta.as<tk::TrajMeta>();
+    I.tslots = m.tslots.as<unsigned long long>();
+    for (int k = 0; k < m.M; ++k)
+      items.push_back({c->nt * m.step_cost, int2{static_cast<int>(i), k}});
+    b->traj_steps += 2ll * m.M * c->nt;
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const auto &x, const auto &y) { return x.first > y.first; });
+  std::vector<int2> it(items.size());
+  for (size_t q = 0; q < items.size(); ++q) it[q] = items[q].second;
+  TK_BHIP(b, b->items_dev.ensure(it.size() * sizeof(int2)));
+  TK_BHIP(b, hipMemcpy(b->items_dev.p, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice));
+  int rc = plan_pass(b, tk::kWavesPerBlock);
+  if (rc == TK_EUNSUPPORTED) rc = plan_pass(b, 1);
+  if (rc) return rc == TK_EUNSUPPORTED ? bfail(b, rc, "pass term vectors do not fit in LDS") : rc;
+  const double sync_cost = 0.0;
+  rc = plan_krotov(b, tk::kWavesPerBlock, 1.0, sync_cost);
+  if (rc == TK_EUNSUPPORTED) rc = plan_krotov(b, 1, 1.0, sync_cost);
+  if (rc) return rc == TK_EUNSUPPORTED ? bfail(b, rc, "instances do not fit one co-resident grid") : rc;
+  b->ready = true;
+  return TK_OK;
+}
+
+// Autotuner: times the costate pass for each waves-per-block choice and the
+// Krotov pass for each (waves per block, share of the co-resident blocks,
+// weight of the per-step exchange in the block split); keeps the fastest.  The
+// passes are deterministic and independent of the tile shape, so the repeated
+// runs leave the same results as one run.
+int autotune(tk_batch *b) {
+  double best = 1e300;
+  int best_wpb = 0;
+  for (int wpb : {4, 2, 1}) {
+    if (plan_pass(b, wpb)) continue;
+    double ms = 0.0;
+    int rc = timed(b, [&] { return launch_pass(b, 1); }, &ms);
+    if (rc) return rc;
+    if (ms < best) {
+      best = ms;
+      best_wpb = wpb;
+    }
+  }
+  if (!best_wpb) return bfail(b, TK_EUNSUPPORTED, "no batched pass shape fits");
+  int rc = plan_pass(b, best_wpb);
+  if (rc) return rc;
+  b->tuned_pass_ms = best;
+  double kbest = 1e300;
+  int kw = 0;
+  double kf = 0.0, ks = 0.0;
+  double unit = 0.0;  // step_cost -> sync weight scale: the cheapest instance's step
+  for (const auto &m : b->mem) unit = unit == 0.0 ? m->step_cost : std::min(unit, m->step_cost);
+  for (int wpb : {4, 2, 1})
+    for (double frac : {1.0, 0.5})
+      for (double sync : {0.0, 2.0 * unit}) {
+        if (plan_krotov(b, wpb, frac, sync)) continue;
+        double ms = 0.0;
+        rc = timed(b, [&] { return launch_krotov(b); }, &ms);
+        if (rc) return rc;
+        if ((rc = check_errors(b))) return rc;
+        if (ms < kbest) {
+          kbest = ms;
+          kw = wpb;
+          kf = frac;
+          ks = sync;
+        }
+      }
+  if (!kw) return bfail(b, TK_EUNSUPPORTED, "no batched Krotov shape fits");
+  if ((rc = plan_krotov(b, kw, kf, ks))) return rc;
+  b->tuned_krotov_ms = kbest;
+  b->tuned = true;
+  return TK_OK;
+}
+
+int build_graph(tk_batch *b) {
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  TK_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  int rc = launch_pass(b, 1);
+  if (!rc) rc = launch_krotov(b);
+  if (!rc) rc = launch_tail(b, 1);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return bhip(b, e, "hipStreamEndCapture");
+  b->graph = g;
+  TK_BHIP(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  return TK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tk_batch_create(tk_batch **out, int device, int precision) {
+  if (!out) return TK_EINVAL;
+  *out = nullptr;
+  if (precision != TK_FP64 && precision != TK_FP32) return TK_EINVAL;
+  tk_ctx *probe = nullptr;
+  int rc = tk_create(&probe, device, precision);  // device checks (gfx950)
+  if (rc) return rc;
+  tk_destroy(probe);
+  tk_batch *b = new (std::nothrow) tk_batch();
+  if (!b) return TK_ENOMEM;
+  b->device = device;
+  b->precision = precision;
+  hipDeviceProp_t prop;
+  if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&prop, device) != hipSuccess ||
+      hipStreamCreate(&b->stream) != hipSuccess || hipEventCreate(&b->ev0) != hipSuccess ||
+      hipEventCreate(&b->ev1) != hipSuccess) {
+    tk_batch_destroy(b);
+    return TK_EHIP;
+  }
+  b->n_cu = prop.multiProcessorCount;
+  *out = b;
+  return TK_OK;
+}
+
+void tk_batch_destroy(tk_batch *b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+const char *tk_batch_last_error(const tk_batch *b) { return b ? b->err.c_str() : "no batch"; }
+
+int tk_batch_add(tk_batch *b, uint32_t instance_id, int64_t d, const tk_csr *H0, int32_t n_ctrl,
+                 const tk_csr *H_ctrl, int32_t n_jump, const tk_csr *L_jump, const double *psi0,
+                 const double *psi_tgt, int32_t nt, double T, const double *u, const double *S,
+                 const double *lambda, int32_t M, uint64_t seed, int32_t *index_out) {
+  if (!b) return TK_EINVAL;
+  if (b->ready) return bfail(b, TK_ESTATE, "instances cannot be added after the first iteration");
+  if (M < 1) return bfail(b, TK_EINVAL, "M must be >= 1");
+  for (const auto &m : b->mem)
+    if (m->id == instance_id) return bfail(b, TK_EINVAL, "duplicate instance id");
+  auto m = std::make_unique<Member>();
+  int rc = tk_create(&m->c, b->device, b->precision);
+  if (rc) return bfail(b, rc, "context creation failed");
+  if ((rc = tk_set_system(m->c, d, H0, n_ctrl, H_ctrl, n_jump, L_jump)) ||
+      (rc = tk_set_states(m->c, psi0, psi_tgt)) ||
+      (rc = tk_set_pulses(m->c, nt, T, u, S, lambda)))
+    return bfail(b, rc, std::string("instance: ") + tk_last_error(m->c));
+  if (shape_index(m->c->var) < 0 || shape_index(m->c->var) > 3)
+    return bfail(b, TK_EUNSUPPORTED, "kernel shape not available in the batched kernels");
+  m->id = instance_id;
+  m->M = M;
+  m->seed = seed;
+  if (index_out) *index_out = static_cast<int32_t>(b->mem.size());
+  b->mem.push_back(std::move(m));
+  return TK_OK;
+}
+
+int tk_batch_krotov_iterate(tk_batch *b, uint64_t first_iteration, int32_t n_iter,
+                            double *J_T_out) {
+  if (!b) return TK_EINVAL;
+  TK_BHIP(b, hipSetDevice(b->device));
+  if (!J_T_out) return bfail(b, TK_EINVAL, "J_T_out is NULL");
+  const int n_out = n_iter + (first_iteration == 0 ? 1 : 0);
+  if (n_iter < 0 || n_out > tk::kBatchHistory)
+    return bfail(b, TK_EINVAL, "n_iter out of range (at most 63 per call)");
+  int rc;
+  if (!b->ready && (rc = finalize(b))) return rc;
+  if (first_iteration != 0 && first_iteration != b->next_iter)
+    return bfail(b, TK_ESTATE, "first_iteration does not continue the last call");
+  if (first_iteration == 0) {
+    // guess pass: iteration 0 of every instance
+    const uint64_t zero = 0;
+    TK_BHIP(b, hipMemcpy(b->iter_dev.p, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    if ((rc = launch_pass(b, 0))) return rc;
+    if ((rc = launch_tail(b, 0))) return rc;
+    if ((rc = check_errors(b))) return rc;
+  }
+  const uint64_t first = first_iteration == 0 ? 1 : first_iteration;
+  for (int32_t q = 0; q < n_iter; ++q) {
+    double ms = 0.0;
+    if (!b->tuned) {
+      // the first iteration runs step by step while the autotuner picks tiles
+      if ((rc = launch_pass(b, 1))) return rc;
+      if ((rc = autotune(b))) return rc;
+      if ((rc = launch_tail(b, 1))) return rc;
+      if ((rc = build_graph(b))) return rc;
+    } else {
+      rc = timed(b, [&]() -> int {
+        TK_BHIP(b, hipGraphLaunch(b->exec, b->stream));
+        return TK_OK;
+      }, &ms);
+      if (rc) return rc;
+      b->last_iter_ms = ms;
+    }
+  }
+  if ((rc = check_errors(b))) return rc;
+  b->next_iter = first + n_iter;
+  std::vector<double> hist(b->mem.size() * tk::kBatchHistory);
+  TK_BHIP(b, hipMemcpy(hist.data(), b->J_hist_dev.p, hist.size() * sizeof(double),
+                       hipMemcpyDeviceToHost));
+  const uint64_t it0 = first_iteration == 0 ? 0 : first_iteration;
+  for (size_t i = 0; i < b->mem.size(); ++i)
+    for (int q = 0; q < n_out; ++q)
+      J_T_out[i * n_out + q] = hist[i * tk::kBatchHistory + (it0 + q) % tk::kBatchHistory];
+  return TK_OK;
+}
+
+int tk_batch_get_pulses(tk_batch *b, int32_t index, double *u_out) {
+  if (!b) return TK_EINVAL;
+  if (index < 0 || index >= static_cast<int32_t>(b->mem.size()))
+    return bfail(b, TK_EINVAL, "instance index out of range");
+  if (!u_out) return bfail(b, TK_EINVAL, "u_out is NULL");
+  tk_ctx *c = b->mem[index]->c;
+  TK_BHIP(b, hipSetDevice(b->device));
+  TK_BHIP(b, hipStreamSynchronize(b->stream));
+  TK_BHIP(b, hipMemcpy(u_out, c->u_dev.p, static_cast<size_t>(c->n_ctrl) * c->nt * sizeof(double),
+                       hipMemcpyDeviceToHost));
+  return TK_OK;
+}
+
+int tk_batch_get_info(const tk_batch *b, tk_batch_info *out) {
+  if (!b || !out) return TK_EINVAL;
+  out->n_instances = static_cast<int32_t>(b->mem.size());
+  out->pass_waves_per_block = b->plan.pass_wpb;
+  out->pass_blocks = b->plan.pass_blocks;
+  out->krotov_waves_per_block = b->plan.kro_wpb;
+  out->krotov_blocks = b->plan.kro_blocks;
+  out->autotuned = b->tuned ? 1 : 0;
+  out->last_iteration_ms = b->last_iter_ms;
+  out->tuned_pass_ms = b->tuned_pass_ms;
+  out->tuned_krotov_ms = b->tuned_krotov_ms;
+  out->traj_steps_per_iteration = b->traj_steps;
+  return TK_OK;
+}
+
+}  // extern "C"

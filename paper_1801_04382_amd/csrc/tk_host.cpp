@@ -13,27 +13,16 @@
 #include <tuple>
 #include <vector>
 
+#include "tk_host_internal.h"
 #include "tk_internal.h"
 
-namespace {
+using namespace tkh;
 
-using cd = std::complex<double>;
+namespace {
 
 // ---------------------------------------------------------------------------
 // host sparse matrices
 // ---------------------------------------------------------------------------
-struct Csr {
-  int64_t n = 0;
-  std::vector<int64_t> ptr;
-  std::vector<int32_t> idx;
-  std::vector<cd> val;
-  int64_t nnz() const { return static_cast<int64_t>(idx.size()); }
-  int max_row() const {
-    int64_t w = 0;
-    for (int64_t r = 0; r < n; ++r) w = std::max(w, ptr[r + 1] - ptr[r]);
-    return static_cast<int>(w);
-  }
-};
 
 // dense-row accumulation helper (d is small enough for per-row scatter)
 struct RowAcc {
@@ -175,35 +164,6 @@ double max_abs(const Csr &a) {
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf &) = delete;
-  DevBuf &operator=(const DevBuf &) = delete;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  hipError_t ensure(size_t n) {
-    if (n <= bytes && p) return hipSuccess;
-    release();
-    if (n == 0) n = 8;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return e;
-    }
-    bytes = n;
-    return hipSuccess;
-  }
-  template <typename T>
-  T *as() const {
-    return static_cast<T *>(p);
-  }
-};
 
 struct Ell {  // packed per-lane slices of one operator group
   std::vector<int32_t> col;
@@ -212,50 +172,8 @@ struct Ell {  // packed per-lane slices of one operator group
 
 }  // namespace
 
-struct tk_ctx {
-  int device = 0;
-  int precision = TK_FP64;
-  hipStream_t stream = nullptr;
-  std::string err;
-  int n_cu = 0;
 
-  bool has_system = false, has_states = false, has_pulses = false;
-  int64_t d = 0;
-  int n_ctrl = 0, n_jump = 0;
-  const tk::Variant *var = nullptr;
-  int wc = 1, wl = 1;
-  double b0 = 0.0;
-  double bc[tk::kMaxCtrl] = {};
-  int64_t nnz_heff = 0;
-  std::vector<Csr> H_ctrl_host;
-
-  DevBuf f_scol, f_sval, f_ccol, f_cval, b_scol, b_sval, b_ccol, b_cval, lcol, lval;
-  DevBuf ldcol, ldval;  // L_l^+ (pathwise gradient)
-  int wld = 1;
-  DevBuf psi0_bulk, tgt_bulk, tgt64;
-
-  int nt = 0;
-  double T = 0.0;
-  std::vector<double> u, S, lam;
-  DevBuf u_dev, u_new_dev, S_dev, lam_dev;
-
-  DevBuf chi, tau, psiT, slots, rec, rec_count, err_dev, jt_dev;
-  DevBuf path_off, path_step, path_t, path_op, ckpt, stash, gk, dJdu;
-  int chi_M = -1;
-  int tau_M = -1;
-  uint64_t tau_seed = 0;
-  int64_t tau_iter = -1;
-
-  bool timing = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  tk_kernel_timing tstat[TK_KERNEL_COUNT] = {};
-  int last_wpb = 0, last_tw = 0, last_blocks = 0;
-  bool cooperative = true;  // launch the Krotov pass with hipLaunchCooperativeKernel
-
-  size_t bulk_cplx() const { return precision == TK_FP64 ? 16 : 8; }
-};
-
-namespace {
+namespace tkh {
 
 int fail(tk_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -267,11 +185,10 @@ int hip_fail(tk_ctx *c, hipError_t e, const char *what) {
               std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define TK_HIP(ctx, call)                               \
-  do {                                                  \
-    hipError_t e_ = (call);                             \
-    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
-  } while (0)
+}  // namespace tkh
+
+namespace {
+
 
 int read_csr(tk_ctx *c, const tk_csr *m, int64_t d, const char *name, Csr &out) {
   if (!m) return fail(c, TK_EINVAL, std::string(name) + " is NULL");
@@ -383,11 +300,19 @@ void pack_ctrl(const std::vector<Csr> &H, int wc, int NC, int R, int n_bank_grou
   }
 }
 
+}  // namespace
+
+namespace tkh {
+
 int upload(tk_ctx *c, DevBuf &buf, const void *src, size_t bytes) {
   TK_HIP(c, buf.ensure(bytes));
   if (bytes) TK_HIP(c, hipMemcpy(buf.p, src, bytes, hipMemcpyHostToDevice));
   return TK_OK;
 }
+
+}  // namespace tkh
+
+namespace {
 
 int upload_ell(tk_ctx *c, const Ell &e, DevBuf &col, DevBuf &val) {
   int rc = upload(c, col, e.col.data(), e.col.size() * sizeof(int32_t));
@@ -427,6 +352,10 @@ void plan_step_host(const tk_ctx *c, const std::vector<double> &u, int j, int *n
   *K = taylor_order_host(x / *n_sub, step_tol(c), tk::kMaxTaylor);
 }
 
+}  // namespace
+
+namespace tkh {
+
 // Term vectors a pass needs: the largest order over its steps, plus one for
 // the zeroth term and `margin` for pulses that grow during a Krotov pass.
 int plan_kbuf(const tk_ctx *c, const std::vector<double> &u, int margin) {
@@ -449,12 +378,20 @@ double pass_flops(const tk_ctx *c, const std::vector<double> &u, int M) {
   return f * M;
 }
 
+}  // namespace tkh
+
+namespace {
+
 // Waves per block for a plain pass: as many as fit the LDS (at most 4).
 int pass_waves(const tk_ctx *c, int kbuf) {
   for (int w = tk::kWavesPerBlock; w >= 1; w /= 2)
     if (tk::block_lds_bytes(*c->var, w, kbuf, 0) <= tk::kLdsBytes) return w;
   return 0;
 }
+
+}  // namespace
+
+namespace tkh {
 
 tk::PassArgs base_args(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, bool backward) {
   tk::PassArgs a;
@@ -500,6 +437,10 @@ tk::PassArgs base_args(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, bool
   a.spin_limit = 1ll << 22;
   return a;
 }
+
+}  // namespace tkh
+
+namespace {
 
 int prepare_pass(tk_ctx *c, int M, int64_t cap) {
   if (!c->has_system) return fail(c, TK_ESTATE, "no system set");

@@ -107,6 +107,35 @@ struct PassArgs {
   double *gk;               // [n_ctrl][nt][M] per-trajectory gradient terms
 };
 
+// One optimisation instance of a batch: its pass arguments and the buffers of
+// the batched Krotov pass.
+struct BatchInstance {
+  PassArgs fw;        // forward passes (guess and sequential update)
+  PassArgs bw;        // costate pass (adjoint operator, starts from the target)
+  int variant;        // index of the kernel shape in the precision's table
+  int block0;         // first block of the batched Krotov launch serving it
+  int nblocks;        // blocks serving it
+  int ncx;            // shares per trajectory and step: the shape's NC (at least 1)
+  void *psi;          // [M][64 R] states between steps (bulk)
+  TrajMeta *meta;     // [M] MCWF clocks between steps
+  unsigned long long *tslots;  // [nt][M][NCX] per-trajectory partials s_ik (FP64 bits)
+};
+
+// Arguments of the batched kernels.
+struct BatchArgs {
+  const BatchInstance *inst;
+  int n_inst;
+  int wave_lds;          // LDS bytes per wave of the batched plain passes
+  const int2 *items;     // (instance, trajectory) work of the plain passes
+  int n_items;
+  const int *block_inst; // [blocks] instance of each block of the Krotov launch
+  uint64_t *iteration;   // iteration of the passes being run (device counter)
+  double *J_hist;        // [n_inst][kBatchHistory] J_T by iteration
+  int *err;
+  long long spin_limit;
+};
+constexpr int kBatchHistory = 64;  // J_T values kept per instance (ring by iteration)
+
 // One compiled kernel variant: bulk precision, rows per lane R, static slots
 // per row WS, control slots per row NC.
 struct Variant {
@@ -130,6 +159,14 @@ const void *functional_kernel();
 // reduces the per-trajectory terms: one 64-thread block per pulse value.
 const void *grad_kernel(int precision, int R, int WS, int NC);
 const void *grad_reduce_kernel();
+
+// Batched kernels of a precision (defined in tk_batch.hip).  The shape of an
+// instance is selected inside the kernels by BatchInstance::variant, the index
+// of (R, WS, NC) in variants() among those of the same precision.
+struct BatchKernels {
+  const void *pass_fw, *pass_bw, *krotov, *fill, *functional, *finish;
+};
+BatchKernels batch_kernels(int precision);
 
 // LDS bytes of one block of the gradient kernel with `waves` waves.
 size_t grad_lds_bytes(const Variant &v, int waves, int kbuf);

@@ -59,82 +59,9 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_pass(PassArgs a) {
   LaneOp<real, R, WS, NC> op;
   const Terms<real, R> T = block_setup<real, R, WS, NC>(a, smem_raw, wib, lane,
                                                          terms_bytes<real, R>(a.kbuf), op);
-  const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
-  cx<real> *chi = static_cast<cx<real> *>(a.chi);
   const int nwaves = gridDim.x * wpb;
-  for (int k = blockIdx.x * wpb + wib; k < a.M; k += nwaves) {
-    cx<real> psi[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) psi[m] = start[lane + kWave * m];
-    const Stream rng = make_stream(a, k, DIR);
-    TrajMeta st;
-    st.nrm2 = norm2(psi);
-    st.ordinal = 0;
-    st.r = rng.threshold(0);
-    double tau_re = 0.0, tau_im = 0.0;
-    if (DIR == 1) {
-      tau_re = a.tau_in[2 * k];
-      tau_im = a.tau_in[2 * k + 1];
-    }
-    constexpr int NCX = NC > 0 ? NC : 1;
-    double un[NCX];  // pulses of the next step, loaded one step ahead (rows padded)
-    {
-      const int j0 = DIR == 0 ? 0 : a.nt - 1;
-#pragma unroll
-      for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + j0];
-    }
-    for (int jj = 0; jj < a.nt; ++jj) {
-      const int j = DIR == 0 ? jj : a.nt - 1 - jj;
-      double uj[NCX];
-#pragma unroll
-      for (int i = 0; i < NCX; ++i) uj[i] = un[i];
-      if (jj + 1 < a.nt) {
-        const int jn = DIR == 0 ? j + 1 : j - 1;
-#pragma unroll
-        for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + jn];
-      }
-      op.set_pulses(uj, a.wc);
-      const StepPlan p = plan_step(a, uj);
-      advance_step<real, R, WS, NC, DIR>(op, a, T, psi, st, rng, j, p, k, lane);
-      if (DIR == 1) {
-        // chi_k(t_j) = tau_k chi_hat_k(t_j)
-        const double inv = 1.0 / sqrt(st.nrm2);
-        const size_t base = (static_cast<size_t>(j) * a.M + k) * a.d;
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-          const int row = lane + kWave * m;
-          if (row < a.d) {
-            const double px = psi[m].x * inv, py = psi[m].y * inv;
-            chi[base + row] = cx<real>{static_cast<real>(tau_re * px - tau_im * py),
-                                       static_cast<real>(tau_re * py + tau_im * px)};
-          }
-        }
-      }
-    }
-    if (DIR == 0) {
-      const double inv = 1.0 / sqrt(st.nrm2);
-      double tr = 0.0, ti = 0.0;
-      cx<real> *psiT = static_cast<cx<real> *>(a.psiT);
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int row = lane + kWave * m;
-        const double px = psi[m].x * inv, py = psi[m].y * inv;
-        // tau_k = <tgt|psi_hat> = sum conj(tgt) psi_hat
-        const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
-        tr = fma(gx, px, fma(gy, py, tr));
-        ti = fma(gx, py, fma(-gy, px, ti));
-        if (psiT != nullptr && row < a.d)
-          psiT[static_cast<size_t>(k) * a.d + row] =
-              cx<real>{static_cast<real>(px), static_cast<real>(py)};
-      }
-      tr = wave_sum(tr);
-      ti = wave_sum(ti);
-      if (lane == 0 && a.tau_out != nullptr) {
-        a.tau_out[2 * k] = tr;
-        a.tau_out[2 * k + 1] = ti;
-      }
-    }
-  }
+  for (int k = blockIdx.x * wpb + wib; k < a.M; k += nwaves)
+    pass_trajectory<real, R, WS, NC, DIR>(op, a, T, k, make_stream(a, k, DIR), lane);
 }
 
 // ---- slot initialisation for the Krotov pass ---------------------------------
@@ -145,39 +72,6 @@ __global__ void k_fill_slots(unsigned long long *slots, long long n, int nblk, i
        i += stride) {
     const int b = static_cast<int>((i / ncx) % kMaxBlocks);
     slots[i] = b < nblk ? kSlotEmpty : 0ull;
-  }
-}
-
-// Per-lane share of Im <chi|H_i|psi_hat> for every control slot c, added to pc.
-// v holds the (unnormalised) state, inv = 1/||psi||.
-template <typename real, int R, int WS, int NC>
-__device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC> &op,
-                                             const cx<real> *v, const cx<real> (&ch)[R],
-                                             double inv, double *pc) {
-#pragma unroll
-  for (int m = 0; m < R; ++m) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const cx<real> q = op.cval_at(c, m);
-      const cx<real> b = v[op.ccol[c][m]];
-      const double hx = static_cast<double>(q.x) * b.x - static_cast<double>(q.y) * b.y;
-      const double hy = static_cast<double>(q.x) * b.y + static_cast<double>(q.y) * b.x;
-      // Im(conj(chi) h) = chi.x h.y - chi.y h.x
-      pc[c] = fma(inv * static_cast<double>(ch[m].x), hy, pc[c]);
-      pc[c] = fma(-inv * static_cast<double>(ch[m].y), hx, pc[c]);
-    }
-  }
-}
-
-template <typename real, int R>
-__device__ __forceinline__ void load_costate(const PassArgs &a, int j, int k, int lane,
-                                             cx<real> (&ch)[R]) {
-  const cx<real> *chi = static_cast<const cx<real> *>(a.chi);
-  const size_t base = (static_cast<size_t>(j) * a.M + k) * a.d;
-#pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int row = lane + kWave * m;
-    ch[m] = row < a.d ? chi[base + row] : cx<real>{0, 0};
   }
 }
 

@@ -68,6 +68,15 @@ class tk_kernel_timing(ctypes.Structure):
                 ("traj_steps", ctypes.c_int64)]
 
 
+class tk_batch_info(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_int32), ("pass_waves_per_block", ctypes.c_int32),
+                ("pass_blocks", ctypes.c_int32), ("krotov_waves_per_block", ctypes.c_int32),
+                ("krotov_blocks", ctypes.c_int32), ("autotuned", ctypes.c_int32),
+                ("last_iteration_ms", ctypes.c_double), ("tuned_pass_ms", ctypes.c_double),
+                ("tuned_krotov_ms", ctypes.c_double),
+                ("traj_steps_per_iteration", ctypes.c_int64)]
+
+
 JUMP_DTYPE = np.dtype([("instance", np.int32), ("traj", np.int32), ("step", np.int32),
                        ("op", np.int32), ("ordinal", np.int32), ("direction", np.int32),
                        ("iteration", np.int32), ("reserved", np.int32), ("t", np.float64)])
@@ -101,6 +110,16 @@ _SIGNATURES = {
                                          ctypes.c_int64, _P(ctypes.c_int64)]),
     "tk_grad_pathwise": (ctypes.c_int, [_ctx_p, ctypes.c_int32, _P(tk_jump), ctypes.c_int64,
                                         _dp, _dp, _dp]),
+    "tk_batch_create": (ctypes.c_int, [_P(_ctx_p), ctypes.c_int, ctypes.c_int]),
+    "tk_batch_destroy": (None, [_ctx_p]),
+    "tk_batch_last_error": (ctypes.c_char_p, [_ctx_p]),
+    "tk_batch_add": (ctypes.c_int, [_ctx_p, ctypes.c_uint32, ctypes.c_int64, _P(tk_csr),
+                                    ctypes.c_int32, _P(tk_csr), ctypes.c_int32, _P(tk_csr),
+                                    _dp, _dp, ctypes.c_int32, ctypes.c_double, _dp, _dp, _dp,
+                                    ctypes.c_int32, ctypes.c_uint64, _P(ctypes.c_int32)]),
+    "tk_batch_krotov_iterate": (ctypes.c_int, [_ctx_p, ctypes.c_uint64, ctypes.c_int32, _dp]),
+    "tk_batch_get_pulses": (ctypes.c_int, [_ctx_p, ctypes.c_int32, _dp]),
+    "tk_batch_get_info": (ctypes.c_int, [_ctx_p, _P(tk_batch_info)]),
     "tk_set_timing": (ctypes.c_int, [_ctx_p, ctypes.c_int]),
     "tk_get_timing": (ctypes.c_int, [_ctx_p, ctypes.c_int, _P(tk_kernel_timing)]),
     "tk_reset_timing": (ctypes.c_int, [_ctx_p]),
@@ -408,3 +427,108 @@ class Context:
 
     def launch_info(self):
         return tk_get_launch_info(self.h)
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+def _bcheck(b, code: int) -> int:
+    if code != TK_OK:
+        msg = _lib.tk_batch_last_error(b).decode() if b else ""
+        raise TkError(code, msg)
+    return code
+
+
+def tk_batch_create(device: int = 0, precision: int = TK_FP32) -> int:
+    h = _ctx_p()
+    code = _lib.tk_batch_create(ctypes.byref(h), device, precision)
+    if code != TK_OK:
+        raise TkError(code, "tk_batch_create failed")
+    return h.value
+
+
+def tk_batch_destroy(b: int) -> None:
+    _lib.tk_batch_destroy(b)
+
+
+def tk_batch_add(b: int, instance_id: int, H0, H_ctrl, L_jump, psi0, psi_tgt, u, T, S, lam,
+                 M: int, seed: int) -> int:
+    d = H0.shape[0]
+    h0 = _CsrHolder(H0, d)
+    hc = [_CsrHolder(h, d) for h in H_ctrl]
+    lj = [_CsrHolder(l, d) for l in L_jump]
+    hc_arr = (tk_csr * max(len(hc), 1))(*[h.c for h in hc])
+    lj_arr = (tk_csr * max(len(lj), 1))(*[h.c for h in lj])
+    p = _cplx(psi0, d)
+    t = _cplx(psi_tgt, d)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(len(hc), -1)
+    s = None if S is None else np.ascontiguousarray(S, dtype=np.float64).reshape(u.shape)
+    l_ = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+    idx = ctypes.c_int32(-1)
+    _bcheck(b, _lib.tk_batch_add(b, instance_id, d, ctypes.byref(h0.c), len(hc), hc_arr, len(lj),
+                                 lj_arr, _dptr(p), _dptr(t), u.shape[1], float(T), _dptr(u),
+                                 _dptr(s), _dptr(l_), M, seed, ctypes.byref(idx)))
+    return idx.value
+
+
+def tk_batch_krotov_iterate(b: int, n_inst: int, n_iter: int, first_iteration: int = 0):
+    n_out = n_iter + (1 if first_iteration == 0 else 0)
+    J = np.zeros((n_inst, max(n_out, 1)))
+    _bcheck(b, _lib.tk_batch_krotov_iterate(b, first_iteration, n_iter, _dptr(J)))
+    return J[:, :n_out]
+
+
+def tk_batch_get_pulses(b: int, index: int, n_ctrl: int, nt: int) -> np.ndarray:
+    out = np.zeros((n_ctrl, nt))
+    _bcheck(b, _lib.tk_batch_get_pulses(b, index, _dptr(out)))
+    return out
+
+
+def tk_batch_get_info(b: int) -> dict:
+    info = tk_batch_info()
+    _bcheck(b, _lib.tk_batch_get_info(b, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in tk_batch_info._fields_}
+
+
+class Batch:
+    """A batch of independent optimisation instances advanced together."""
+
+    def __init__(self, device: int = 0, precision: str = "fp32"):
+        self.h = tk_batch_create(device, {"fp64": TK_FP64, "fp32": TK_FP32}[precision])
+        self.shapes: List[Tuple[int, int]] = []
+
+    def close(self):
+        if self.h:
+            tk_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, w, instance_id: Optional[int] = None) -> int:
+        """Add a workloads.Workload (its instance field is the default id)."""
+        iid = w.instance if instance_id is None else instance_id
+        idx = tk_batch_add(self.h, iid, w.H0, w.H_ctrl, w.L_jump, w.psi0, w.psi_tgt, w.u0, w.T,
+                           w.S, w.lam, w.M, w.seed)
+        self.shapes.append((len(w.H_ctrl), w.nt))
+        return idx
+
+    def krotov_iterate(self, n_iter: int, first_iteration: int = 0) -> np.ndarray:
+        return tk_batch_krotov_iterate(self.h, len(self.shapes), n_iter, first_iteration)
+
+    def get_pulses(self, index: int) -> np.ndarray:
+        n_ctrl, nt = self.shapes[index]
+        return tk_batch_get_pulses(self.h, index, n_ctrl, nt)
+
+    def info(self) -> dict:
+        return tk_batch_get_info(self.h)
