@@ -83,6 +83,69 @@ def cpu_baseline(name: str, M_sub: int, nt: int) -> dict:
                       f"{el:.1f} s; host cores {cores}, BLAS threads {blas_threads}"}
 
 
+def bench_batched(n_inst: int, steps: int, nodes, check: int) -> dict:
+    """FP32 batched form: n_inst instances of the batching workload in one
+    launch; guess pass + one autotuned iteration untimed, then `steps` graph
+    iterations timed.  The first `check` instances are also optimised alone in
+    FP64 (same seeds and streams) for the J_T accuracy of the FP32 form."""
+    import numpy as np
+    from paper_1801_04382_amd import trajkrotov as tk
+    from workloads import batch_instances
+    ws = batch_instances(n_inst, seed=0, nodes=tuple(nodes))
+    with tk.Batch(precision="fp32") as b:
+        for w in ws:
+            b.add(w)
+        J0 = b.krotov_iterate(1)
+        t0 = time.perf_counter()
+        J = b.krotov_iterate(steps, first_iteration=2)
+        el = time.perf_counter() - t0
+        info = b.info()
+    J32 = np.concatenate([J0, J], axis=1)
+    dJ = []
+    for i in range(min(check, n_inst)):
+        with tk.Batch(precision="fp64") as b64:
+            b64.add(ws[i])
+            J64 = b64.krotov_iterate(1 + steps)
+        dJ.append(float(np.max(np.abs(J64[0] - J32[i]))))
+    ts = info["traj_steps_per_iteration"]
+    return {"workload": f"batch of {n_inst} instances, chain of {min(nodes)}-{max(nodes)} nodes, "
+                        "cavity at 2 levels, M in [64, 2048], nt in [500, 4000]",
+            "dims": sorted({int(w.dim) for w in ws}),
+            "traj_steps_per_iteration": ts, "iterations": steps,
+            "value": ts * steps / el, "unit": "trajectory-steps/s",
+            "krotov_iters_per_s": steps / el, "ms_per_iteration": 1e3 * el / steps,
+            "graph_iteration_ms": info["last_iteration_ms"],
+            "launch": {k: info[k] for k in ("pass_waves_per_block", "pass_blocks",
+                                             "krotov_waves_per_block", "krotov_blocks")},
+            "max_abs_dJ_fp32_vs_fp64": max(dJ) if dJ else None,
+            "dJ_checked_instances": len(dJ)}
+
+
+def bench_grad(workload: str, reps: int) -> dict:
+    """Pathwise gradient (jump record fixed) of the FP64 workload."""
+    from paper_1801_04382_amd import trajkrotov as tk
+    from workloads import config_workload
+    w = config_workload(workload)
+    with tk.Context(precision="fp64") as ctx:
+        ctx.load(w)
+        _, _, rec, n = ctx.propagate_forward(w.M, w.seed, 0, want_states=False, rec_cap=8 * w.M)
+        ctx.grad_pathwise(w.M, rec)
+        ctx.reset_timing()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.grad_pathwise(w.M, rec)
+        el = time.perf_counter() - t0
+        t = ctx.timing(tk.TK_KERNEL_GRAD)
+    avg = t["ms_total"] / t["launches"]
+    return {"workload": workload, "d": w.dim, "M": w.M, "nt": w.nt, "records": int(n),
+            "ms_per_gradient": 1e3 * el / reps, "kernel_ms": avg,
+            "value": w.M * w.nt * reps / el, "unit": "trajectory-steps/s (replay + reverse sweep)",
+            "roofline": {"bound": "alu", "achieved": t["flops"] / t["launches"] / (avg * 1e-3) / 1e12,
+                         "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                         "frac": t["flops"] / t["launches"] / (avg * 1e-3) / 1e12 / PEAK["fp64"]}}
+
+
 def copy_probe(mib: int, reps: int) -> int:
     """Device-to-device copies of known size: each reads and writes mib MiB."""
     import torch
@@ -109,6 +172,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched FP32 and gradient forms")
+    ap.add_argument("--batch-instances", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--batch-nodes", default="2,3")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
@@ -176,6 +244,14 @@ def main() -> int:
         "roofline": roofline,
     }
     ctx.close()
+    if not args.no_forms:
+        out["forms"] = {
+            "batched_fp32": bench_batched(args.batch_instances, args.batch_steps,
+                                          [int(x) for x in args.batch_nodes.split(",")], 2),
+            "grad_fp64": bench_grad(args.workload, 3),
+        }
+        out["forms"]["fp32_batched_vs_fp64_plain"] = (
+            out["forms"]["batched_fp32"]["value"] / out["value"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, w.nt)
     print(json.dumps(out), flush=True)

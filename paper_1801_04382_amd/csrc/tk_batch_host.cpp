@@ -353,8 +353,8 @@ int finalize(tk_batch *b) {
 }
 
 // Autotuner: times the costate pass for each waves-per-block choice and the
-// Krotov pass for each (waves per block, share of the co-resident blocks,
-// weight of the per-step exchange in the block split); keeps the fastest.  The
+// Krotov pass for each (waves per block, weight of the per-step exchange in
+// the block split); keeps the fastest.  The
 // passes are deterministic and independent of the tile shape, so the repeated
 // runs leave the same results as one run.
 int autotune(tk_batch *b) {
@@ -376,12 +376,12 @@ int autotune(tk_batch *b) {
   b->tuned_pass_ms = best;
   double kbest = 1e300;
   int kw = 0;
-  double kf = 0.0, ks = 0.0;
+  double ks = 0.0;
   double unit = 0.0;  // step_cost -> sync weight scale: the cheapest instance's step
   for (const auto &m : b->mem) unit = unit == 0.0 ? m->step_cost : std::min(unit, m->step_cost);
+  const double frac = 1.0;
   for (int wpb : {4, 2, 1})
-    for (double frac : {1.0, 0.5})
-      for (double sync : {0.0, 2.0 * unit}) {
+    for (double sync : {0.0, 2.0 * unit}) {
         if (plan_krotov(b, wpb, frac, sync)) continue;
         double ms = 0.0;
         rc = timed(b, [&] { return launch_krotov(b); }, &ms);
@@ -390,12 +390,11 @@ int autotune(tk_batch *b) {
         if (ms < kbest) {
           kbest = ms;
           kw = wpb;
-          kf = frac;
           ks = sync;
         }
-      }
+    }
   if (!kw) return bfail(b, TK_EUNSUPPORTED, "no batched Krotov shape fits");
-  if ((rc = plan_krotov(b, kw, kf, ks))) return rc;
+  if ((rc = plan_krotov(b, kw, frac, ks))) return rc;
   b->tuned_krotov_ms = kbest;
   b->tuned = true;
   return TK_OK;
