@@ -34,7 +34,10 @@ from typing import Dict, Iterable, List, Sequence, Tuple
 import numpy as np
 import scipy.linalg
 
-from .mcwf import Jump, System, norm2, propagator
+import scipy.sparse
+import scipy.sparse.linalg
+
+from .mcwf import Jump, System, apply_propagator, norm2, step_operator
 
 Path = List[Tuple[int, float, int]]  # (step, time, operator) in time order
 
@@ -73,12 +76,12 @@ def replay_states(system: System, psi0, u: np.ndarray, T: float, paths: Sequence
     """Final unnormalised states phi_k(T) of the replayed trajectories, [M, d]."""
     nt = u.shape[1]
     dt = T / nt
-    H = [system.effective_hamiltonian(u[:, j]) for j in range(nt)]
+    H = [step_operator(system.effective_hamiltonian(u[:, j])) for j in range(nt)]
     out = []
     for path in paths:
         phi = np.array(psi0, dtype=np.complex128)
         for j, tau, l in _pieces(path, nt, dt):
-            phi = propagator(H[j], tau, 0) @ phi
+            phi = apply_propagator(H[j], tau, 0, phi)
             if l is not None:
                 phi = system.L_jump[l] @ phi
                 phi = phi / np.sqrt(norm2(phi))
@@ -94,14 +97,20 @@ def replay_functional(system: System, psi0, psi_tgt, u, T, paths) -> Tuple[float
     return float(1.0 - np.mean(np.abs(tau) ** 2)), tau
 
 
-def propagator_derivative(H_eff: np.ndarray, H_i: np.ndarray, tau: float) -> np.ndarray:
-    """d exp(-i (H_eff + u H_i) tau) / du at u = 0, by Van Loan's block exponential."""
+def propagator_derivative(H_eff, H_i: np.ndarray, tau: float, x: np.ndarray) -> np.ndarray:
+    """(d exp(-i (H_eff + u H_i) tau) / du at u = 0) x, by Van Loan's block
+    exponential: the top half of exp(tau [[-iH, -iH_i], [0, -iH]]) [0; x]."""
     d = H_eff.shape[0]
-    blk = np.zeros((2 * d, 2 * d), dtype=np.complex128)
-    blk[:d, :d] = -1j * tau * H_eff
-    blk[d:, d:] = -1j * tau * H_eff
-    blk[:d, d:] = -1j * tau * H_i
-    return scipy.linalg.expm(blk)[:d, d:]
+    if not scipy.sparse.issparse(H_eff):
+        blk = np.zeros((2 * d, 2 * d), dtype=np.complex128)
+        blk[:d, :d] = -1j * tau * H_eff
+        blk[d:, d:] = -1j * tau * H_eff
+        blk[:d, d:] = -1j * tau * H_i
+        return scipy.linalg.expm(blk)[:d, d:] @ x
+    A = -1j * tau * H_eff
+    blk = scipy.sparse.bmat([[A, -1j * tau * scipy.sparse.csr_matrix(H_i)], [None, A]]).tocsr()
+    z = np.concatenate([np.zeros(d, dtype=np.complex128), x])
+    return scipy.sparse.linalg.expm_multiply(blk, z)[:d]
 
 
 def gradient_adjoint(system: System, psi0, psi_tgt, u: np.ndarray, T: float,
@@ -111,7 +120,7 @@ def gradient_adjoint(system: System, psi0, psi_tgt, u: np.ndarray, T: float,
     dt = T / nt
     M = len(paths)
     n_ctrl = len(system.H_ctrl)
-    H = [system.effective_hamiltonian(u[:, j]) for j in range(nt)]
+    H = [step_operator(system.effective_hamiltonian(u[:, j])) for j in range(nt)]
     tgt = np.asarray(psi_tgt, dtype=np.complex128)
     grad = np.zeros((n_ctrl, nt))
     for path in paths:
@@ -121,7 +130,7 @@ def gradient_adjoint(system: System, psi0, psi_tgt, u: np.ndarray, T: float,
         phi = np.array(psi0, dtype=np.complex128)
         for j, tau, l in pieces:
             starts.append(phi)
-            phi = propagator(H[j], tau, 0) @ phi
+            phi = apply_propagator(H[j], tau, 0, phi)
             c = None
             if l is not None:
                 phi = system.L_jump[l] @ phi
@@ -137,9 +146,9 @@ def gradient_adjoint(system: System, psi0, psi_tgt, u: np.ndarray, T: float,
             if l is not None:  # adjoint of the (constant-scaled) jump map
                 lam = c * (system.L_jump[l].conj().T @ lam)
             for i, Hi in enumerate(system.H_ctrl):
-                D = propagator_derivative(H[j], Hi, tau)
-                grad[i, j] += 2.0 * np.real(np.vdot(lam, D @ start))
-            lam = propagator(H[j], tau, 0).conj().T @ lam
+                grad[i, j] += 2.0 * np.real(np.vdot(lam, propagator_derivative(H[j], Hi, tau, start)))
+            # adjoint of the piece: exp(-i H tau)^+ = exp(+i H^+ tau)
+            lam = apply_propagator(H[j], tau, 1, lam)
     return -grad / M
 
 

@@ -36,6 +36,8 @@ from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 import scipy.linalg
+import scipy.sparse
+import scipy.sparse.linalg
 
 from .philox import TrajectoryStream
 
@@ -77,6 +79,28 @@ def propagator(H_eff: np.ndarray, tau: float, direction: int) -> np.ndarray:
     return scipy.linalg.expm(1j * tau * H_eff.conj().T)
 
 
+# Above this dimension the propagator is never formed: its action on states
+# comes from scipy's expm_multiply (Al-Mohy & Higham's truncated Taylor series
+# with norm-based scaling), which is the same exp(-i H_eff tau) applied to a
+# vector without the d x d matrix.
+DENSE_MAX_DIM = 256
+
+
+def step_operator(H_eff: np.ndarray):
+    """H_eff as the propagator routines take it: dense up to DENSE_MAX_DIM, else sparse."""
+    if H_eff.shape[0] <= DENSE_MAX_DIM:
+        return H_eff
+    return scipy.sparse.csr_matrix(H_eff)
+
+
+def apply_propagator(H_op, tau: float, direction: int, psi: np.ndarray) -> np.ndarray:
+    """U(tau) psi: exp(-i H_eff tau) psi forward, exp(+i H_eff^+ tau) psi backward."""
+    if not scipy.sparse.issparse(H_op):
+        return propagator(H_op, tau, direction) @ psi
+    A = -1j * tau * H_op if direction == 0 else 1j * tau * H_op.conj().T.tocsr()
+    return scipy.sparse.linalg.expm_multiply(A, psi)
+
+
 def norm2(psi: np.ndarray) -> float:
     return float(np.vdot(psi, psi).real)
 
@@ -93,8 +117,7 @@ class Jump:
     t: float
 
 
-def jump_time(H_eff: np.ndarray, psi: np.ndarray, tau_rem: float, r: float,
-              direction: int) -> float:
+def jump_time(H_eff, psi: np.ndarray, tau_rem: float, r: float, direction: int) -> float:
     """First tau in (0, tau_rem] with ||U(tau) psi||^2 < r, by bisection.
 
     The norm is non-increasing in tau (d/dtau ||psi||^2 = -sum_l ||L_l psi||^2),
@@ -107,7 +130,7 @@ def jump_time(H_eff: np.ndarray, psi: np.ndarray, tau_rem: float, r: float,
         mid = 0.5 * (lo + hi)
         if mid <= lo or mid >= hi:
             return hi
-        if norm2(propagator(H_eff, mid, direction) @ psi) < r:
+        if norm2(apply_propagator(H_eff, mid, direction, psi)) < r:
             hi = mid
         else:
             lo = mid
@@ -159,21 +182,23 @@ class Ensemble:
         propagation (t_{j-1} forward, t_j backward); recorded jump times are
         t_start + elapsed forward and t_start - elapsed backward.
         """
-        H_eff = self.sys.effective_hamiltonian(u_j)
-        U = propagator(H_eff, dt, self.direction)
+        H_eff = step_operator(self.sys.effective_hamiltonian(u_j))
+        dense = not scipy.sparse.issparse(H_eff)
+        U = propagator(H_eff, dt, self.direction) if dense else None
         sign = 1.0 if self.direction == 0 else -1.0
         for k in range(self.M):
             psi = self.psi[k]
             tau_rem = dt
             U_rem = U
             while True:
-                phi = U_rem @ psi
+                phi = U_rem @ psi if dense else apply_propagator(H_eff, tau_rem,
+                                                                  self.direction, psi)
                 if norm2(phi) >= self.r[k]:
                     self.psi[k] = phi
                     break
                 # MCWF step 3: the norm reaches r inside this step
                 tau = jump_time(H_eff, psi, tau_rem, self.r[k], self.direction)
-                psi = propagator(H_eff, tau, self.direction) @ psi
+                psi = apply_propagator(H_eff, tau, self.direction, psi)
                 n = int(self.ordinal[k])
                 stream = self.streams[k]
                 # MCWF step 4: instantaneous jump with operator l
@@ -187,7 +212,7 @@ class Ensemble:
                 self.ordinal[k] = n + 1
                 self.r[k] = stream.threshold(n + 1)
                 tau_rem = tau_rem - tau
-                U_rem = propagator(H_eff, tau_rem, self.direction)
+                U_rem = propagator(H_eff, tau_rem, self.direction) if dense else None
 
 
 def forward_pass(system: System, psi0: np.ndarray, u: np.ndarray, T: float, M: int,
