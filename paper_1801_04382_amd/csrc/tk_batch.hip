@@ -39,25 +39,26 @@ namespace {
 // ---- plain passes ------------------------------------------------------------
 template <typename real, int R, int WS, int NC, int DIR>
 __device__ void batch_pass_item(const PassArgs &a, int k, uint64_t it, unsigned char *wave_lds,
-                                int lane) {
+                                const Team<1> &tm) {
+  const int lane = tm.lane;
   constexpr int NCX = NC > 0 ? NC : 1;
   cx<real> *cval_lds = reinterpret_cast<cx<real> *>(wave_lds);
   const cx<real> *cval_g = static_cast<const cx<real> *>(a.cval);
   wave_sync();  // the previous item's reads of this wave's LDS are done
   for (int i = lane; i < NCX * R * kWave; i += kWave) cval_lds[i] = cval_g[i];
-  Terms<real, R> T;
+  Terms<real, R, 1> T;
   T.base = cval_lds + NCX * R * kWave;
   if (lane < a.kbuf) T[lane][R * kWave] = cx<real>{0, 0};
   wave_sync();
-  LaneOp<real, R, WS, NC> op;
+  LaneOp<real, R, WS, NC, 1> op;
   op.load(a.scol, a.sval, a.ccol, cval_lds, lane);
-  pass_trajectory<real, R, WS, NC, DIR>(op, a, T, k, make_stream(a, k, DIR, it), lane);
+  pass_trajectory<real, R, WS, NC, 1, DIR>(op, a, T, k, make_stream(a, k, DIR, it), tm);
 }
 
 template <typename real, int DIR>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_pass(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int lane = threadIdx.x & (kWave - 1);
+  const Team<1> tm = make_team<1>(nullptr);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int wpb = blockDim.x / kWave;
   unsigned char *wl = smem_raw + static_cast<size_t>(wib) * b.wave_lds;
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_pass(BatchArgs 
     switch (I.variant) {
 #define TK_CASE(idx, R, WS, NC) \
   case idx:                     \
-    batch_pass_item<real, R, WS, NC, DIR>(a, k, it, wl, lane); \
+    batch_pass_item<real, R, WS, NC, DIR>(a, k, it, wl, tm); \
     break;
       TK_BATCH_SHAPES(TK_CASE)
 #undef TK_CASE
@@ -153,12 +154,13 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
   constexpr int NCX = NC > 0 ? NC : 1;
   constexpr int kRows = R * kWave;
   const PassArgs &a = I.fw;
-  const int lane = threadIdx.x & (kWave - 1);
+  const Team<1> tm = make_team<1>(nullptr);
+  const int lane = tm.lane;
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int wpb = blockDim.x / kWave;
-  LaneOp<real, R, WS, NC> op;
-  const Terms<real, R> T =
-      block_setup<real, R, WS, NC>(a, smem, wib, lane, terms_bytes<real, R>(a.kbuf), op);
+  LaneOp<real, R, WS, NC, 1> op;
+  const Terms<real, R, 1> T =
+      block_setup<real, R, WS, NC, 1>(a, smem, wib, tm, terms_bytes<real, R, 1>(a.kbuf), op);
   const int nw = I.nblocks * wpb;
   const int w = lb * wpb + wib;
   cx<real> *psi_g = static_cast<cx<real> *>(I.psi);
@@ -175,7 +177,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
       p[m] = start[lane + kWave * m];
       psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m] = p[m];
     }
-    const double n = norm2(p);
+    const double n = norm2(p, tm);
     if (lane == 0) {
       TrajMeta st;
       st.nrm2 = n;
@@ -185,14 +187,14 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
       meta_g[k] = st;
     }
     cx<real> ch[R];
-    load_costate<real, R>(a, 0, k, lane, ch);
+    load_costate<real, R, 1>(a, 0, k, tm, ch);
     double pc[NCX];
 #pragma unroll
     for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
     wave_sync();
-    store_lds(v, p, lane);
+    store_lds(v, p, tm);
     wave_sync();
-    krotov_share<real, R, WS, NC>(op, v, ch, 1.0 / sqrt(n), pc);
+    krotov_share<real, R, WS, NC, 1>(op, v, ch, 1.0 / sqrt(n), pc);
     publish_share<NC>(a, I.tslots, k, pc, lane);
   }
 
@@ -240,13 +242,13 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     const StepPlan p = plan_step(a, uj);
     for (int k = w; k < a.M; k += nw) {
       cx<real> ch[R];
-      if (j + 1 < a.nt) load_costate<real, R>(a, j + 1, k, lane, ch);
+      if (j + 1 < a.nt) load_costate<real, R, 1>(a, j + 1, k, tm, ch);
       cx<real> psi[R];
 #pragma unroll
       for (int m = 0; m < R; ++m) psi[m] = psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m];
       TrajMeta st = meta_g[k];
       const Stream rng = make_stream(a, k, 0, it);
-      advance_step<real, R, WS, NC, 0>(op, a, T, psi, st, rng, j, p, k, lane);
+      advance_step<real, R, WS, NC, 1, 0>(op, a, T, psi, st, rng, j, p, k, tm);
 #pragma unroll
       for (int m = 0; m < R; ++m) psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m] = psi[m];
       if (lane == 0) meta_g[k] = st;
@@ -255,9 +257,9 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
 #pragma unroll
         for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
         wave_sync();
-        store_lds(v, psi, lane);
+        store_lds(v, psi, tm);
         wave_sync();
-        krotov_share<real, R, WS, NC>(op, v, ch, 1.0 / sqrt(st.nrm2), pc);
+        krotov_share<real, R, WS, NC, 1>(op, v, ch, 1.0 / sqrt(st.nrm2), pc);
         publish_share<NC>(a, I.tslots + static_cast<size_t>(j + 1) * row_len, k, pc, lane);
       }
       wave_sync();

@@ -483,8 +483,9 @@ int tk_batch_add(tk_batch *b, uint32_t instance_id, int64_t d, const tk_csr *H0,
       (rc = tk_set_states(m->c, psi0, psi_tgt)) ||
       (rc = tk_set_pulses(m->c, nt, T, u, S, lambda)))
     return bfail(b, rc, std::string("instance: ") + tk_last_error(m->c));
-  if (shape_index(m->c->var) < 0 || shape_index(m->c->var) > 3)
-    return bfail(b, TK_EUNSUPPORTED, "kernel shape not available in the batched kernels");
+  if (m->c->var->G != 1 || shape_index(m->c->var) < 0 || shape_index(m->c->var) > 3)
+    return bfail(b, TK_EUNSUPPORTED,
+                 "kernel shape not available in the batched kernels (one-wave shapes, d <= 256)");
   m->id = instance_id;
   m->M = M;
   m->seed = seed;

@@ -48,6 +48,52 @@ __device__ __forceinline__ double wave_sum(double x) {
   return (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
 }
 
+// The lanes that advance one trajectory together: G wavefronts (G = 1: one
+// wavefront; G > 1: the G waves of a block, which then holds just this team).
+// Row r of a state belongs to team lane r mod 64G as its slot m = r / 64G.
+// sync() orders LDS traffic among the team; sum() is the team-wide FP64 sum
+// in a fixed order (each wave's DPP tree, then the waves in index order, via a
+// double-buffered LDS array), so every lane of the team holds the same bits.
+template <int G>
+struct Team {
+  static constexpr int kLanes = kWave * G;
+  int gl;            // lane within the team
+  int lane;          // lane within the wave
+  int g;             // wave within the team
+  double *red;       // LDS [2][G] (G > 1)
+  mutable int par;   // half of red the next sum writes
+  __device__ __forceinline__ void sync() const {
+    if (G == 1)
+      wave_sync();
+    else
+      __syncthreads();
+  }
+  __device__ __forceinline__ double sum(double x) const {
+    x = wave_sum(x);
+    if (G == 1) return x;
+    double *r = red + par * G;
+    if (lane == 0) r[g] = x;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) s += r[q];
+    par ^= 1;
+    return s;
+  }
+  __device__ __forceinline__ bool leader() const { return gl == 0; }
+};
+
+template <int G>
+__device__ __forceinline__ Team<G> make_team(double *red) {
+  Team<G> t;
+  t.gl = threadIdx.x % Team<G>::kLanes;
+  t.lane = threadIdx.x & (kWave - 1);
+  t.g = __builtin_amdgcn_readfirstlane(t.gl / kWave);
+  t.red = red;
+  t.par = 0;
+  return t;
+}
+
 // ---- Philox4x64-10 (Salmon et al., SC'11) ---------------------------------
 __device__ __forceinline__ void philox4x64(uint64_t c0, uint64_t c1, uint64_t c2,
                                            uint64_t c3, uint64_t k0, uint64_t k1,
@@ -118,25 +164,27 @@ __device__ __forceinline__ void cfma(cx<real> &y, const cx<real> &a, const cx<re
 }
 
 // ---- per-lane operator slice ------------------------------------------------
-template <typename real, int R, int WS, int NC>
+template <typename real, int R, int WS, int NC, int G>
 struct LaneOp {
+  static constexpr int kL = kWave * G;  // lanes of the team
   static constexpr int NCX = NC > 0 ? NC : 1;
   int scol[WS][R];
   cx<real> sval[WS][R];
   int ccol[NCX][R];
   cx<real> cv[NCX][R];   // control matrix elements scaled by the current pulses
-  const cx<real> *cval;  // unscaled control elements of this lane in LDS, [c][m][lane]
+  const cx<real> *cval;  // unscaled control elements of this lane, [c][m][team lane]
 
   // static slots (scol_g, sval_g) and control columns (ccol_g) from global
-  // memory; the unscaled control values stay in LDS (cval_lds)
+  // memory; the unscaled control values stay where cval_src points (LDS or
+  // global memory); gl is the lane within the team
   __device__ void load(const int *scol_g, const void *sval_g, const int *ccol_g,
-                       const cx<real> *cval_lds, int lane) {
+                       const cx<real> *cval_src, int gl) {
     const cx<real> *sv = static_cast<const cx<real> *>(sval_g);
 #pragma unroll
     for (int s = 0; s < WS; ++s)
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const int idx = (s * R + m) * kWave + lane;
+        const int idx = (s * R + m) * kL + gl;
         scol[s][m] = scol_g[idx];
         sval[s][m] = sv[idx];
       }
@@ -144,15 +192,15 @@ struct LaneOp {
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        ccol[c][m] = ccol_g[(c * R + m) * kWave + lane];
+        ccol[c][m] = ccol_g[(c * R + m) * kL + gl];
         cv[c][m] = cx<real>{0, 0};
       }
-    cval = cval_lds + lane;
+    cval = cval_src + gl;
   }
 
   // unscaled control element of slot c, row slot m
   __device__ __forceinline__ cx<real> cval_at(int c, int m) const {
-    return cval[(c * R + m) * kWave];
+    return cval[(c * R + m) * kL];
   }
 
   // cv = u_{c / wc} * cval for the pulse values uj[0 .. NCX) (zero past n_ctrl)
@@ -194,8 +242,8 @@ struct LaneOp {
   }
 };
 
-template <typename real, int R>
-__device__ __forceinline__ double norm2(const cx<real> (&p)[R]) {
+template <typename real, int R, int G>
+__device__ __forceinline__ double norm2(const cx<real> (&p)[R], const Team<G> &tm) {
   double s = 0.0;
 #pragma unroll
   for (int m = 0; m < R; ++m) {
@@ -203,26 +251,27 @@ __device__ __forceinline__ double norm2(const cx<real> (&p)[R]) {
     s = fma(x, x, s);
     s = fma(y, y, s);
   }
-  return wave_sum(s);
+  return tm.sum(s);
 }
 
-template <typename real, int R>
-__device__ __forceinline__ void store_lds(cx<real> *v, const cx<real> (&p)[R], int lane) {
+// the lane's rows of a team vector (LDS or global memory)
+template <typename real, int R, int G>
+__device__ __forceinline__ void store_lds(cx<real> *v, const cx<real> (&p)[R], const Team<G> &tm) {
 #pragma unroll
-  for (int m = 0; m < R; ++m) v[lane + kWave * m] = p[m];
+  for (int m = 0; m < R; ++m) v[tm.gl + Team<G>::kLanes * m] = p[m];
 }
 
-template <typename real, int R>
-__device__ __forceinline__ void load_lds(const cx<real> *v, cx<real> (&p)[R], int lane) {
+template <typename real, int R, int G>
+__device__ __forceinline__ void load_lds(const cx<real> *v, cx<real> (&p)[R], const Team<G> &tm) {
 #pragma unroll
-  for (int m = 0; m < R; ++m) p[m] = v[lane + kWave * m];
+  for (int m = 0; m < R; ++m) p[m] = v[tm.gl + Team<G>::kLanes * m];
 }
 
-// Per-wave LDS view: term vectors T_0 .. T_{kbuf-1}, each 64 R + 1 elements
-// (element 64 R is the zero read by padding slots).
-template <typename real, int R>
+// Per-team LDS view: term vectors T_0 .. T_{kbuf-1}, each 64 G R + 1
+// elements (element 64 G R is the zero read by padding slots).
+template <typename real, int R, int G>
 struct Terms {
-  static constexpr int kLen = R * kWave + 1;
+  static constexpr int kLen = R * kWave * G + 1;
   cx<real> *base;
   __device__ cx<real> *operator[](int n) const { return base + n * kLen; }
 };
@@ -242,19 +291,19 @@ __device__ inline int taylor_order(double x, double tol, int kmax) {
 // or +1 (backward); t_n is also left in T[n] for dense output.  The small
 // increment sum_{n>=1} t_n is accumulated on its own and added to t_0 once, so
 // the state is rounded once per substep rather than once per term.
-template <typename real, int R, int WS, int NC, int SGN>
-__device__ void taylor(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
-                       const Terms<real, R> &T, const cx<real> (&in)[R], cx<real> (&out)[R],
-                       double tau, int K, int lane) {
+template <typename real, int R, int WS, int NC, int G, int SGN>
+__device__ void taylor(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                       const Terms<real, R, G> &T, const cx<real> (&in)[R], cx<real> (&out)[R],
+                       double tau, int K, const Team<G> &tm) {
   cx<real> t[R], inc[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     t[m] = in[m];
     inc[m] = cx<real>{0, 0};
   }
-  store_lds(T[0], t, lane);
+  store_lds(T[0], t, tm);
   for (int n = 1; n <= K; ++n) {
-    wave_sync();
+    tm.sync();
     cx<real> y[R];
     op.apply(T[n - 1], y);
     const real c = static_cast<real>(tau * a.inv_n[n]);
@@ -267,22 +316,22 @@ __device__ void taylor(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
       inc[m].x += t[m].x;
       inc[m].y += t[m].y;
     }
-    store_lds(T[n], t, lane);
+    store_lds(T[n], t, tm);
   }
 #pragma unroll
   for (int m = 0; m < R; ++m) out[m] = cx<real>{in[m].x + inc[m].x, in[m].y + inc[m].y};
 }
 
 // p(s) = sum_n s^n t_n and dp/ds from the stored terms (own rows only; Horner)
-template <typename real, int R>
-__device__ __forceinline__ void dense_output(const Terms<real, R> &T, int K, real s,
-                                             cx<real> (&p)[R], cx<real> (&dp)[R], int lane) {
-  load_lds(T[K], p, lane);
+template <typename real, int R, int G>
+__device__ __forceinline__ void dense_output(const Terms<real, R, G> &T, int K, real s,
+                                             cx<real> (&p)[R], cx<real> (&dp)[R], const Team<G> &tm) {
+  load_lds(T[K], p, tm);
 #pragma unroll
   for (int m = 0; m < R; ++m) dp[m] = cx<real>{0, 0};
   for (int n = K - 1; n >= 0; --n) {
     cx<real> tn[R];
-    load_lds(T[n], tn, lane);
+    load_lds(T[n], tn, tm);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       dp[m] = cx<real>{fma(dp[m].x, s, p[m].x), fma(dp[m].y, s, p[m].y)};
@@ -293,34 +342,34 @@ __device__ __forceinline__ void dense_output(const Terms<real, R> &T, int K, rea
 
 // y = L_l p for operator l of a group packed [l][w][m][lane] with wl slots per
 // row (slices read from global memory; p in LDS v)
-template <typename real, int R>
+template <typename real, int R, int G>
 __device__ void apply_packed(const int *lcol, const void *lval, int wl, int l,
-                             const cx<real> *v, cx<real> (&y)[R], int lane) {
+                             const cx<real> *v, cx<real> (&y)[R], const Team<G> &tm) {
   const cx<real> *lv = static_cast<const cx<real> *>(lval);
 #pragma unroll
   for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
   for (int w = 0; w < wl; ++w)
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int idx = ((l * wl + w) * R + m) * kWave + lane;
+      const int idx = ((l * wl + w) * R + m) * Team<G>::kLanes + tm.gl;
       cfma(y[m], lv[idx], v[lcol[idx]]);
     }
 }
 
 // y = L_l p for the jump operators of the pass
-template <typename real, int R>
+template <typename real, int R, int G>
 __device__ __forceinline__ void apply_jump(const PassArgs &a, int l, const cx<real> *v,
-                                           cx<real> (&y)[R], int lane) {
-  apply_packed<real, R>(a.lcol, a.lval, a.wl, l, v, y, lane);
+                                           cx<real> (&y)[R], const Team<G> &tm) {
+  apply_packed<real, R, G>(a.lcol, a.lval, a.wl, l, v, y, tm);
 }
 
 // Advance one trajectory across one substep of length h starting at time t0
 // (MCWF with precise jump times).  DIR 0: forward, exp(-i H_eff tau), times
 // t0 + elapsed; DIR 1: backward, exp(+i H_eff^+ tau), times t0 - elapsed.
-template <typename real, int R, int WS, int NC, int DIR>
-__device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
-                        const Terms<real, R> &T, cx<real> (&psi)[R], TrajMeta &st,
-                        const Stream &rng, int j, double t0, double h, int K, int k, int lane) {
+template <typename real, int R, int WS, int NC, int G, int DIR>
+__device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                        const Terms<real, R, G> &T, cx<real> (&psi)[R], TrajMeta &st,
+                        const Stream &rng, int j, double t0, double h, int K, int k, const Team<G> &tm) {
   constexpr int SGN = DIR == 0 ? -1 : 1;
   double tau_rem = h;
   double n_s = st.nrm2;
@@ -330,8 +379,8 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
   constexpr double eps_real = sizeof(real) == 8 ? 0x1.0p-52 : 0x1.0p-23;
   for (int guard = 0;; ++guard) {
     cx<real> out[R];
-    taylor<real, R, WS, NC, SGN>(op, a, T, ps, out, tau_rem, K, lane);
-    const double n_end = norm2(out);
+    taylor<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, K, tm);
+    const double n_end = norm2(out, tm);
     if (!(n_end < st.r)) {
 #pragma unroll
       for (int m = 0; m < R; ++m) psi[m] = out[m];
@@ -339,7 +388,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
       return;
     }
     if (guard >= 64) {  // pathological: give up on this step, keep the state
-      if (lane == 0) atomicOr(a.err, kErrJumpLoop);
+      if (tm.leader()) atomicOr(a.err, kErrJumpLoop);
 #pragma unroll
       for (int m = 0; m < R; ++m) psi[m] = out[m];
       st.nrm2 = n_end;
@@ -353,15 +402,15 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
     if (!(s > lo && s < hi)) s = 0.5;
     cx<real> pt[R], dp[R];
     for (int it = 0; it < 64; ++it) {
-      dense_output<real, R>(T, K, static_cast<real>(s), pt, dp, lane);
-      const double f = norm2(pt) - st.r;
+      dense_output<real, R, G>(T, K, static_cast<real>(s), pt, dp, tm);
+      const double f = norm2(pt, tm) - st.r;
       double g = 0.0;  // Re <p|dp/ds>
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         g = fma(static_cast<double>(pt[m].x), static_cast<double>(dp[m].x), g);
         g = fma(static_cast<double>(pt[m].y), static_cast<double>(dp[m].y), g);
       }
-      const double fp = 2.0 * wave_sum(g);
+      const double fp = 2.0 * tm.sum(g);
       if (f >= 0.0)
         lo = s;
       else
@@ -371,31 +420,31 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
       if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
       if (fabs(sn - s) <= 2.0 * eps_real) {
         s = sn;
-        dense_output<real, R>(T, K, static_cast<real>(s), pt, dp, lane);
+        dense_output<real, R, G>(T, K, static_cast<real>(s), pt, dp, tm);
         break;
       }
       s = sn;
     }
     const double tau = s * tau_rem;
     // ---- jump (MCWF step 4) ----
-    store_lds(T[0], pt, lane);
-    wave_sync();
+    store_lds(T[0], pt, tm);
+    tm.sync();
     // weights ||L_l p||^2; pass 1 sums them, pass 2 walks the cumulative sum
     double total = 0.0;
     for (int l = 0; l < a.n_jump; ++l) {
       cx<real> y[R];
-      apply_jump<real, R>(a, l, T[0], y, lane);
-      total += norm2(y);
+      apply_jump<real, R, G>(a, l, T[0], y, tm);
+      total += norm2(y, tm);
     }
     double thr_unused, x;
     rng.block(static_cast<uint64_t>(st.ordinal), thr_unused, x);
     if (!(total > 0.0)) {
-      if (lane == 0) atomicOr(a.err, kErrNoJumpWeight);
+      if (tm.leader()) atomicOr(a.err, kErrNoJumpWeight);
 #pragma unroll
       for (int m = 0; m < R; ++m) psi[m] = pt[m];
-      st.nrm2 = norm2(pt);
+      st.nrm2 = norm2(pt, tm);
       st.r = 0.0;
-      wave_sync();
+      tm.sync();
       return;
     }
     const double target = x * total;
@@ -403,8 +452,8 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
     int lsel = -1;
     cx<real> y[R];
     for (int l = 0; l < a.n_jump; ++l) {
-      apply_jump<real, R>(a, l, T[0], y, lane);
-      wsel = norm2(y);
+      apply_jump<real, R, G>(a, l, T[0], y, tm);
+      wsel = norm2(y, tm);
       acc += wsel;
       if (target < acc) {
         lsel = l;
@@ -413,15 +462,15 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
     }
     if (lsel < 0) {  // rounding left target >= total: take the last operator
       lsel = a.n_jump - 1;
-      apply_jump<real, R>(a, lsel, T[0], y, lane);
-      wsel = norm2(y);
+      apply_jump<real, R, G>(a, lsel, T[0], y, tm);
+      wsel = norm2(y, tm);
     }
-    wave_sync();
+    tm.sync();
     const real inv = static_cast<real>(1.0 / sqrt(wsel));
 #pragma unroll
     for (int m = 0; m < R; ++m) ps[m] = cx<real>{y[m].x * inv, y[m].y * inv};
     const double elapsed = (h - tau_rem) + tau;
-    if (lane == 0) {
+    if (tm.leader()) {
       const unsigned long long slot = atomicAdd(a.rec_count, 1ull);
       if (static_cast<long long>(slot) < a.rec_cap) {
         tk_jump r;
@@ -439,7 +488,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
     }
     st.ordinal += 1;
     st.r = rng.threshold(static_cast<uint64_t>(st.ordinal));
-    n_s = norm2(ps);
+    n_s = norm2(ps, tm);
     tau_rem = tau_rem - tau;
   }
 }
@@ -475,57 +524,67 @@ __device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&
 }
 
 // Advance across the whole step j (its substeps).
-template <typename real, int R, int WS, int NC, int DIR>
-__device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC> &op,
-                                             const PassArgs &a, const Terms<real, R> &T,
+template <typename real, int R, int WS, int NC, int G, int DIR>
+__device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC, G> &op,
+                                             const PassArgs &a, const Terms<real, R, G> &T,
                                              cx<real> (&psi)[R], TrajMeta &st,
                                              const Stream &rng, int j, const StepPlan &p,
-                                             int k, int lane) {
+                                             int k, const Team<G> &tm) {
   for (int s = 0; s < p.n_sub; ++s) {
     const double t0 = DIR == 0 ? static_cast<double>(j) * a.dt + s * p.h
                                : static_cast<double>(j + 1) * a.dt - s * p.h;
-    advance<real, R, WS, NC, DIR>(op, a, T, psi, st, rng, j, t0, p.h, p.K, k, lane);
+    advance<real, R, WS, NC, G, DIR>(op, a, T, psi, st, rng, j, t0, p.h, p.K, k, tm);
   }
 }
 
-// Block prologue shared by the kernels: copy the unscaled control slots to LDS,
-// zero the trailing element of this wave's term vectors, load the lane's
-// operator slice.  Returns the wave's term vectors.
-template <typename real, int R, int WS, int NC>
-__device__ __forceinline__ Terms<real, R> block_setup(const PassArgs &a, unsigned char *smem,
-                                                      int wib, int lane, size_t wave_bytes,
-                                                      LaneOp<real, R, WS, NC> &op) {
+// Block prologue shared by the kernels: copy the unscaled control slots to LDS
+// (one copy per block of one-wave teams; a G-wave team reads them from global
+// memory, where they are few and cached, to leave its LDS to the term
+// vectors), zero the trailing element of this team's term vectors, load the
+// lane's operator slice.  `team` is the team's index in the block and
+// team_bytes its share of LDS.  Returns the team's term vectors.
+template <typename real, int R, int WS, int NC, int G>
+__device__ __forceinline__ Terms<real, R, G> block_setup(const PassArgs &a, unsigned char *smem,
+                                                         int team, const Team<G> &tm,
+                                                         size_t team_bytes,
+                                                         LaneOp<real, R, WS, NC, G> &op) {
   constexpr int NCX = NC > 0 ? NC : 1;
-  cx<real> *cval_lds = reinterpret_cast<cx<real> *>(smem);
+  constexpr int kL = Team<G>::kLanes;
   const cx<real> *cval_g = static_cast<const cx<real> *>(a.cval);
-  for (int i = threadIdx.x; i < NCX * R * kWave; i += blockDim.x) cval_lds[i] = cval_g[i];
-  Terms<real, R> T;
-  T.base = reinterpret_cast<cx<real> *>(smem + sizeof(cx<real>) * NCX * R * kWave +
-                                        static_cast<size_t>(wib) * wave_bytes);
-  if (lane < a.kbuf) T[lane][R * kWave] = cx<real>{0, 0};
+  const cx<real> *cval_src = cval_g;
+  size_t cval_bytes = 0;
+  if (G == 1) {
+    cx<real> *cval_lds = reinterpret_cast<cx<real> *>(smem);
+    for (int i = threadIdx.x; i < NCX * R * kL; i += blockDim.x) cval_lds[i] = cval_g[i];
+    cval_src = cval_lds;
+    cval_bytes = sizeof(cx<real>) * NCX * R * kL;
+  }
+  Terms<real, R, G> T;
+  T.base = reinterpret_cast<cx<real> *>(smem + cval_bytes + static_cast<size_t>(team) * team_bytes);
+  if (tm.gl < a.kbuf) T[tm.gl][R * kL] = cx<real>{0, 0};
   __syncthreads();
-  op.load(a.scol, a.sval, a.ccol, cval_lds, lane);
+  op.load(a.scol, a.sval, a.ccol, cval_src, tm.gl);
   return T;
 }
 
-template <typename real, int R>
+template <typename real, int R, int G>
 __device__ __forceinline__ size_t terms_bytes(int kbuf) {
-  return static_cast<size_t>(kbuf) * Terms<real, R>::kLen * sizeof(cx<real>);
+  return static_cast<size_t>(kbuf) * Terms<real, R, G>::kLen * sizeof(cx<real>);
 }
 
 // One trajectory of a plain pass over all nt steps: DIR 0 forward from
 // psi_start (final normalised state and tau_k = <tgt|psi_hat_k(T)>), DIR 1
 // backward from the target, storing chi_k(t_j) = tau_k chi_hat_k(t_j).
-template <typename real, int R, int WS, int NC, int DIR>
-__device__ void pass_trajectory(LaneOp<real, R, WS, NC> &op, const PassArgs &a,
-                                const Terms<real, R> &T, int k, const Stream &rng, int lane) {
+template <typename real, int R, int WS, int NC, int G, int DIR>
+__device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                                const Terms<real, R, G> &T, int k, const Stream &rng, const Team<G> &tm) {
   const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
   cx<real> *chi = static_cast<cx<real> *>(a.chi);
   cx<real> psi[R];
 #pragma unroll
-  for (int m = 0; m < R; ++m) psi[m] = start[lane + kWave * m];
+  for (int m = 0; m < R; ++m) psi[m] = start[tm.gl + Team<G>::kLanes * m];
   TrajMeta st;
-  st.nrm2 = norm2(psi);
+  st.nrm2 = norm2(psi, tm);
   st.ordinal = 0;
   st.r = rng.threshold(0);
   double tau_re = 0.0, tau_im = 0.0;
@@ -552,14 +611,14 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC> &op, const PassArgs &a,
     }
     op.set_pulses(uj, a.wc);
     const StepPlan p = plan_step(a, uj);
-    advance_step<real, R, WS, NC, DIR>(op, a, T, psi, st, rng, j, p, k, lane);
+    advance_step<real, R, WS, NC, G, DIR>(op, a, T, psi, st, rng, j, p, k, tm);
     if (DIR == 1) {
       // chi_k(t_j) = tau_k chi_hat_k(t_j)
       const double inv = 1.0 / sqrt(st.nrm2);
       const size_t base = (static_cast<size_t>(j) * a.M + k) * a.d;
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const int row = lane + kWave * m;
+        const int row = tm.gl + Team<G>::kLanes * m;
         if (row < a.d) {
           const double px = psi[m].x * inv, py = psi[m].y * inv;
           chi[base + row] = cx<real>{static_cast<real>(tau_re * px - tau_im * py),
@@ -574,7 +633,7 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC> &op, const PassArgs &a,
     cx<real> *psiT = static_cast<cx<real> *>(a.psiT);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int row = lane + kWave * m;
+      const int row = tm.gl + Team<G>::kLanes * m;
       const double px = psi[m].x * inv, py = psi[m].y * inv;
       // tau_k = <tgt|psi_hat> = sum conj(tgt) psi_hat
       const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
@@ -584,9 +643,9 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC> &op, const PassArgs &a,
         psiT[static_cast<size_t>(k) * a.d + row] =
             cx<real>{static_cast<real>(px), static_cast<real>(py)};
     }
-    tr = wave_sum(tr);
-    ti = wave_sum(ti);
-    if (lane == 0 && a.tau_out != nullptr) {
+    tr = tm.sum(tr);
+    ti = tm.sum(ti);
+    if (tm.leader() && a.tau_out != nullptr) {
       a.tau_out[2 * k] = tr;
       a.tau_out[2 * k + 1] = ti;
     }
@@ -595,8 +654,8 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC> &op, const PassArgs &a,
 
 // Per-lane share of Im <chi|H_i|psi_hat> for every control slot c, added to pc.
 // v holds the (unnormalised) state, inv = 1/||psi||.
-template <typename real, int R, int WS, int NC>
-__device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC> &op,
+template <typename real, int R, int WS, int NC, int G>
+__device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC, G> &op,
                                              const cx<real> *v, const cx<real> (&ch)[R],
                                              double inv, double *pc) {
 #pragma unroll
@@ -614,14 +673,14 @@ __device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC> &op,
   }
 }
 
-template <typename real, int R>
-__device__ __forceinline__ void load_costate(const PassArgs &a, int j, int k, int lane,
+template <typename real, int R, int G>
+__device__ __forceinline__ void load_costate(const PassArgs &a, int j, int k, const Team<G> &tm,
                                              cx<real> (&ch)[R]) {
   const cx<real> *chi = static_cast<const cx<real> *>(a.chi);
   const size_t base = (static_cast<size_t>(j) * a.M + k) * a.d;
 #pragma unroll
   for (int m = 0; m < R; ++m) {
-    const int row = lane + kWave * m;
+    const int row = tm.gl + Team<G>::kLanes * m;
     ch[m] = row < a.d ? chi[base + row] : cx<real>{0, 0};
   }
 }

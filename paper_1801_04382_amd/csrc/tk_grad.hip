@@ -32,17 +32,17 @@
 namespace tk {
 namespace {
 
-// the lane's rows of a state to / from a 64 R-element vector in global memory
-template <typename real, int R>
-__device__ __forceinline__ void put_rows(cx<real> *v, const cx<real> (&p)[R], int lane) {
+// the lane's rows of a state to / from a 64 G R-element vector in global memory
+template <typename real, int R, int G>
+__device__ __forceinline__ void put_rows(cx<real> *v, const cx<real> (&p)[R], const Team<G> &tm) {
 #pragma unroll
-  for (int m = 0; m < R; ++m) v[lane + kWave * m] = p[m];
+  for (int m = 0; m < R; ++m) v[tm.gl + Team<G>::kLanes * m] = p[m];
 }
 
-template <typename real, int R>
-__device__ __forceinline__ void get_rows(const cx<real> *v, cx<real> (&p)[R], int lane) {
+template <typename real, int R, int G>
+__device__ __forceinline__ void get_rows(const cx<real> *v, cx<real> (&p)[R], const Team<G> &tm) {
 #pragma unroll
-  for (int m = 0; m < R; ++m) p[m] = v[lane + kWave * m];
+  for (int m = 0; m < R; ++m) p[m] = v[tm.gl + Team<G>::kLanes * m];
 }
 
 template <typename real, int R>
@@ -52,33 +52,33 @@ __device__ __forceinline__ void copy_state(const cx<real> (&in)[R], cx<real> (&o
 }
 
 // psi <- exp(-i H_eff tau) psi in n = ceil(tau / h) equal substeps of order K
-template <typename real, int R, int WS, int NC>
-__device__ void propagate_piece(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
-                                const Terms<real, R> &T, cx<real> (&psi)[R], double tau,
-                                const StepPlan &p, int lane) {
+template <typename real, int R, int WS, int NC, int G>
+__device__ void propagate_piece(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                                const Terms<real, R, G> &T, cx<real> (&psi)[R], double tau,
+                                const StepPlan &p, const Team<G> &tm) {
   if (!(tau > 0.0)) return;
   const int n = max(1, static_cast<int>(ceil(tau / p.h)));
   const double hs = tau / n;
   for (int s = 0; s < n; ++s) {
     cx<real> out[R];
-    wave_sync();
-    taylor<real, R, WS, NC, -1>(op, a, T, psi, out, hs, p.K, lane);
+    tm.sync();
+    taylor<real, R, WS, NC, G, -1>(op, a, T, psi, out, hs, p.K, tm);
     copy_state(out, psi);
   }
 }
 
 // psi <- L_l psi / ||L_l psi|| (the forward jump map); returns ||L_l psi||^2
-template <typename real, int R>
-__device__ double jump_map(const PassArgs &a, const Terms<real, R> &T, int l, cx<real> (&psi)[R],
-                           int lane) {
-  wave_sync();
-  store_lds(T[0], psi, lane);
-  wave_sync();
+template <typename real, int R, int G>
+__device__ double jump_map(const PassArgs &a, const Terms<real, R, G> &T, int l, cx<real> (&psi)[R],
+                           const Team<G> &tm) {
+  tm.sync();
+  store_lds(T[0], psi, tm);
+  tm.sync();
   cx<real> y[R];
-  apply_jump<real, R>(a, l, T[0], y, lane);
-  const double w = norm2(y);
+  apply_jump<real, R, G>(a, l, T[0], y, tm);
+  const double w = norm2(y, tm);
   if (!(w > 0.0)) {
-    if (lane == 0) atomicOr(a.err, kErrNoJumpWeight);
+    if (tm.leader()) atomicOr(a.err, kErrNoJumpWeight);
     copy_state(y, psi);
     return w;
   }
@@ -99,14 +99,14 @@ __device__ __forceinline__ double piece_start(const PassArgs &a, int j, int qs, 
 }
 
 // Replay of step j: pieces between the recorded jumps [qs, qs + nj).
-template <typename real, int R, int WS, int NC>
-__device__ void replay_step(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
-                            const Terms<real, R> &T, cx<real> (&psi)[R], int j, int qs, int nj,
-                            const StepPlan &p, int lane) {
+template <typename real, int R, int WS, int NC, int G>
+__device__ void replay_step(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                            const Terms<real, R, G> &T, cx<real> (&psi)[R], int j, int qs, int nj,
+                            const StepPlan &p, const Team<G> &tm) {
   for (int q = 0; q <= nj; ++q) {
     const double tau = fmax(piece_end(a, j, qs, q, nj) - piece_start(a, j, qs, q), 0.0);
-    propagate_piece<real, R, WS, NC>(op, a, T, psi, tau, p, lane);
-    if (q < nj) jump_map<real, R>(a, T, a.path_op[qs + q], psi, lane);
+    propagate_piece<real, R, WS, NC, G>(op, a, T, psi, tau, p, tm);
+    if (q < nj) jump_map<real, R, G>(a, T, a.path_op[qs + q], psi, tm);
   }
 }
 
@@ -115,10 +115,10 @@ __device__ void replay_step(const LaneOp<real, R, WS, NC> &op, const PassArgs &a
 // X = sum x_n, Y_i = sum y_{i,n} for the controls i < n_ctrl.  Term vectors are
 // double-buffered in LDS: buffer b holds x in T[b (1 + NCX)] and y_i in
 // T[b (1 + NCX) + 1 + i].
-template <typename real, int R, int WS, int NC>
-__device__ void taylor_aug(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
-                           const Terms<real, R> &T, const cx<real> (&x0)[R], cx<real> (&X)[R],
-                           cx<real> (&Y)[NC > 0 ? NC : 1][R], double tau, int K, int lane) {
+template <typename real, int R, int WS, int NC, int G>
+__device__ void taylor_aug(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                           const Terms<real, R, G> &T, const cx<real> (&x0)[R], cx<real> (&X)[R],
+                           cx<real> (&Y)[NC > 0 ? NC : 1][R], double tau, int K, const Team<G> &tm) {
   constexpr int NCX = NC > 0 ? NC : 1;
   const int nctl = a.n_ctrl;
   cx<real> incX[R];
@@ -128,14 +128,14 @@ __device__ void taylor_aug(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
   for (int i = 0; i < NCX; ++i)
 #pragma unroll
     for (int m = 0; m < R; ++m) Y[i][m] = cx<real>{0, 0};
-  wave_sync();
-  store_lds(T[0], x0, lane);
+  tm.sync();
+  store_lds(T[0], x0, tm);
 #pragma unroll
   for (int i = 0; i < NCX; ++i)
-    if (i < nctl) store_lds(T[1 + i], Y[i], lane);
+    if (i < nctl) store_lds(T[1 + i], Y[i], tm);
   int cur = 0;
   for (int n = 1; n <= K; ++n) {
-    wave_sync();
+    tm.sync();
     const cx<real> *xv = T[cur * (1 + NCX)];
     // gathers of x_{n-1}: H x and the unscaled H_i x from the same loads
     cx<real> b[WS + NCX][R];
@@ -196,58 +196,54 @@ __device__ void taylor_aug(const LaneOp<real, R, WS, NC> &op, const PassArgs &a,
         }
       }
     }
-    store_lds(T[nxt * (1 + NCX)], t, lane);
+    store_lds(T[nxt * (1 + NCX)], t, tm);
 #pragma unroll
     for (int i = 0; i < NCX; ++i)
-      if (i < nctl) store_lds(T[nxt * (1 + NCX) + 1 + i], ty[i], lane);
+      if (i < nctl) store_lds(T[nxt * (1 + NCX) + 1 + i], ty[i], tm);
     cur = nxt;
   }
 #pragma unroll
   for (int m = 0; m < R; ++m) X[m] = cx<real>{x0[m].x + incX[m].x, x0[m].y + incX[m].y};
 }
 
-template <typename real, int R, int WS, int NC>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
+template <typename real, int R, int WS, int NC, int G>
+__global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_grad(
+    PassArgs a) {
   extern __shared__ unsigned char smem_raw[];
+  __shared__ double team_red[2 * G];
   constexpr int NCX = NC > 0 ? NC : 1;
-  constexpr int kLen = Terms<real, R>::kLen;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int wpb = blockDim.x / kWave;
+  constexpr int kL = Team<G>::kLanes;
+  constexpr int kLen = Terms<real, R, G>::kLen;
+  const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / kL);
+  const int tpb = blockDim.x / kL;
+  const Team<G> tm = make_team<G>(team_red);
   const int nbuf = max(a.kbuf, 2 * (1 + NCX));
-  // LDS: forward and adjoint control values, then per wave nbuf term vectors
-  cx<real> *cval_f = reinterpret_cast<cx<real> *>(smem_raw);
-  cx<real> *cval_b = cval_f + NCX * R * kWave;
-  const cx<real> *cf_g = static_cast<const cx<real> *>(a.cval);
-  const cx<real> *cb_g = static_cast<const cx<real> *>(a.a_cval);
-  for (int i = threadIdx.x; i < NCX * R * kWave; i += blockDim.x) {
-    cval_f[i] = cf_g[i];
-    cval_b[i] = cb_g[i];
-  }
-  Terms<real, R> T;
-  T.base = cval_b + NCX * R * kWave + static_cast<size_t>(wib) * nbuf * kLen;
-  if (lane < nbuf) T[lane][R * kWave] = cx<real>{0, 0};
+  // LDS: per team nbuf term vectors; the unscaled control values of both
+  // operators are read from global memory (they are small and cached)
+  Terms<real, R, G> T;
+  T.base = reinterpret_cast<cx<real> *>(smem_raw) + static_cast<size_t>(team) * nbuf * kLen;
+  if (tm.gl < nbuf) T[tm.gl][R * kL] = cx<real>{0, 0};
   __syncthreads();
-  LaneOp<real, R, WS, NC> opf, opb;
-  opf.load(a.scol, a.sval, a.ccol, cval_f, lane);
-  opb.load(a.a_scol, a.a_sval, a.a_ccol, cval_b, lane);
+  LaneOp<real, R, WS, NC, G> opf, opb;
+  opf.load(a.scol, a.sval, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
+  opb.load(a.a_scol, a.a_sval, a.a_ccol, static_cast<const cx<real> *>(a.a_cval), tm.gl);
 
   const int nseg = (a.nt + kGradCheckpoint - 1) / kGradCheckpoint;
-  const int wave = blockIdx.x * wpb + wib;
-  const int nwaves = gridDim.x * wpb;
+  const int wave = blockIdx.x * tpb + team;  // global team index
+  const int nwaves = gridDim.x * tpb;
   const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
   cx<real> *stash = static_cast<cx<real> *>(a.stash) +
-                    static_cast<size_t>(wave) * kGradCheckpoint * R * kWave;
+                    static_cast<size_t>(wave) * kGradCheckpoint * R * kL;
 
   for (int k = wave; k < a.M; k += nwaves) {
-    cx<real> *ck = static_cast<cx<real> *>(a.ckpt) + static_cast<size_t>(k) * nseg * R * kWave;
+    cx<real> *ck = static_cast<cx<real> *>(a.ckpt) + static_cast<size_t>(k) * nseg * R * kL;
     const int q_first = a.path_off[k], q_last = a.path_off[k + 1];
     // ---- 1. forward replay with checkpoints ----
     cx<real> psi[R];
-    get_rows(start, psi, lane);
+    get_rows(start, psi, tm);
     int q = q_first;
     for (int j = 0; j < a.nt; ++j) {
-      if (j % kGradCheckpoint == 0) put_rows(ck + (j / kGradCheckpoint) * R * kWave, psi, lane);
+      if (j % kGradCheckpoint == 0) put_rows(ck + (j / kGradCheckpoint) * R * kL, psi, tm);
       int nj = 0;
       while (q + nj < q_last && a.path_step[q + nj] == j) ++nj;
       double uj[NCX];
@@ -255,24 +251,24 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
       for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
       opf.set_pulses(uj, a.wc);
       const StepPlan p = plan_step(a, uj);
-      replay_step<real, R, WS, NC>(opf, a, T, psi, j, q, nj, p, lane);
+      replay_step<real, R, WS, NC, G>(opf, a, T, psi, j, q, nj, p, tm);
       q += nj;
     }
     // ---- functional and adjoint seed ----
-    const double nrm2 = norm2(psi);
+    const double nrm2 = norm2(psi, tm);
     const double inv = 1.0 / sqrt(nrm2);
     double tr = 0.0, ti = 0.0;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int row = lane + kWave * m;
+      const int row = tm.gl + kL * m;
       const double px = psi[m].x * inv, py = psi[m].y * inv;
       const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
       tr = fma(gx, px, fma(gy, py, tr));
       ti = fma(gx, py, fma(-gy, px, ti));
     }
-    tr = wave_sum(tr);
-    ti = wave_sum(ti);
-    if (lane == 0) {
+    tr = tm.sum(tr);
+    ti = tm.sum(ti);
+    if (tm.leader()) {
       a.tau_out[2 * k] = tr;
       a.tau_out[2 * k + 1] = ti;
     }
@@ -280,7 +276,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
     cx<real> lam[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int row = lane + kWave * m;
+      const int row = tm.gl + kL * m;
       const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
       const double px = psi[m].x * inv, py = psi[m].y * inv;
       lam[m] = cx<real>{static_cast<real>((tr * gx - ti * gy - f * px) * inv),
@@ -292,11 +288,11 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
       const int j0 = sg * kGradCheckpoint;
       const int j1 = min(a.nt, j0 + kGradCheckpoint);
       // recompute the segment's step-start states
-      get_rows(ck + sg * R * kWave, psi, lane);
+      get_rows(ck + sg * R * kL, psi, tm);
       int qr = q_first;
       while (qr < q_last && a.path_step[qr] < j0) ++qr;
       for (int j = j0; j < j1; ++j) {
-        put_rows(stash + (j - j0) * R * kWave, psi, lane);
+        put_rows(stash + (j - j0) * R * kL, psi, tm);
         if (j + 1 == j1) break;  // the last step's end state is not needed
         int nj = 0;
         while (qr + nj < q_last && a.path_step[qr + nj] == j) ++nj;
@@ -305,7 +301,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
         for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
         opf.set_pulses(uj, a.wc);
         const StepPlan p = plan_step(a, uj);
-        replay_step<real, R, WS, NC>(opf, a, T, psi, j, qr, nj, p, lane);
+        replay_step<real, R, WS, NC, G>(opf, a, T, psi, j, qr, nj, p, tm);
         qr += nj;
       }
       for (int j = j1 - 1; j >= j0; --j) {
@@ -323,7 +319,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
         for (int i = 0; i < NCX; ++i) bnd += fabs(uj[i]) * a.bc[i];
         int Kaug = taylor_order((bnd + a.bc_max) * p.h, a.tol, a.kmax);
         if (Kaug < 0) {
-          if (lane == 0) atomicOr(a.err, kErrTaylorOrder);
+          if (tm.leader()) atomicOr(a.err, kErrTaylorOrder);
           Kaug = a.kmax;
         }
         double gl[NCX];  // lane partials of Re <lambda|Y_i> over the step's units
@@ -333,25 +329,25 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
           const double tau = fmax(piece_end(a, j, qs, pc, nj) - piece_start(a, j, qs, pc), 0.0);
           // state at the start of piece pc
           cx<real> ps[R];
-          get_rows(stash + (j - j0) * R * kWave, ps, lane);
+          get_rows(stash + (j - j0) * R * kL, ps, tm);
           for (int qq = 0; qq < pc; ++qq) {
             const double tq = fmax(piece_end(a, j, qs, qq, nj) - piece_start(a, j, qs, qq), 0.0);
-            propagate_piece<real, R, WS, NC>(opf, a, T, ps, tq, p, lane);
-            jump_map<real, R>(a, T, a.path_op[qs + qq], ps, lane);
+            propagate_piece<real, R, WS, NC, G>(opf, a, T, ps, tq, p, tm);
+            jump_map<real, R, G>(a, T, a.path_op[qs + qq], ps, tm);
           }
           if (!(tau > 0.0)) {
             // zero-length piece: only the jump that ends it (if any) acts
             if (pc < nj) {
               cx<real> y[R];
-              wave_sync();
-              store_lds(T[0], ps, lane);
-              wave_sync();
-              apply_jump<real, R>(a, a.path_op[qs + pc], T[0], y, lane);
-              const double c = 1.0 / sqrt(norm2(y));
-              wave_sync();
-              store_lds(T[0], lam, lane);
-              wave_sync();
-              apply_packed<real, R>(a.ldcol, a.ldval, a.wld, a.path_op[qs + pc], T[0], y, lane);
+              tm.sync();
+              store_lds(T[0], ps, tm);
+              tm.sync();
+              apply_jump<real, R, G>(a, a.path_op[qs + pc], T[0], y, tm);
+              const double c = 1.0 / sqrt(norm2(y, tm));
+              tm.sync();
+              store_lds(T[0], lam, tm);
+              tm.sync();
+              apply_packed<real, R, G>(a.ldcol, a.ldval, a.wld, a.path_op[qs + pc], T[0], y, tm);
 #pragma unroll
               for (int m = 0; m < R; ++m)
                 lam[m] = cx<real>{static_cast<real>(c * y[m].x), static_cast<real>(c * y[m].y)};
@@ -366,24 +362,24 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
             copy_state(ps, xs);
             for (int ss = 0; ss < s; ++ss) {
               cx<real> out[R];
-              wave_sync();
-              taylor<real, R, WS, NC, -1>(opf, a, T, xs, out, hs, p.K, lane);
+              tm.sync();
+              taylor<real, R, WS, NC, G, -1>(opf, a, T, xs, out, hs, p.K, tm);
               copy_state(out, xs);
             }
             cx<real> X[R], Y[NCX][R];
-            taylor_aug<real, R, WS, NC>(opf, a, T, xs, X, Y, hs, Kaug, lane);
+            taylor_aug<real, R, WS, NC, G>(opf, a, T, xs, X, Y, hs, Kaug, tm);
             if (s == n - 1 && pc < nj) {
               // adjoint of the jump map that ends the piece: lambda <- c L^+ lambda
               cx<real> y[R];
-              wave_sync();
-              store_lds(T[0], X, lane);
-              wave_sync();
-              apply_jump<real, R>(a, a.path_op[qs + pc], T[0], y, lane);
-              const double c = 1.0 / sqrt(norm2(y));
-              wave_sync();
-              store_lds(T[0], lam, lane);
-              wave_sync();
-              apply_packed<real, R>(a.ldcol, a.ldval, a.wld, a.path_op[qs + pc], T[0], y, lane);
+              tm.sync();
+              store_lds(T[0], X, tm);
+              tm.sync();
+              apply_jump<real, R, G>(a, a.path_op[qs + pc], T[0], y, tm);
+              const double c = 1.0 / sqrt(norm2(y, tm));
+              tm.sync();
+              store_lds(T[0], lam, tm);
+              tm.sync();
+              apply_packed<real, R, G>(a.ldcol, a.ldval, a.wld, a.path_op[qs + pc], T[0], y, tm);
 #pragma unroll
               for (int m = 0; m < R; ++m)
                 lam[m] = cx<real>{static_cast<real>(c * y[m].x), static_cast<real>(c * y[m].y)};
@@ -397,16 +393,16 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_grad(PassArgs a) {
               }
             // lambda <- exp(+i H^+ hs) lambda
             cx<real> out[R];
-            wave_sync();
-            taylor<real, R, WS, NC, 1>(opb, a, T, lam, out, hs, p.K, lane);
+            tm.sync();
+            taylor<real, R, WS, NC, G, 1>(opb, a, T, lam, out, hs, p.K, tm);
             copy_state(out, lam);
           }
         }
 #pragma unroll
         for (int i = 0; i < NCX; ++i) {
           if (i < a.n_ctrl) {
-            const double g = wave_sum(gl[i]);
-            if (lane == 0) a.gk[(static_cast<size_t>(i) * a.nt + j) * a.M + k] = g;
+            const double g = tm.sum(gl[i]);
+            if (tm.leader()) a.gk[(static_cast<size_t>(i) * a.nt + j) * a.M + k] = g;
           }
         }
         qe = qs;
@@ -427,29 +423,33 @@ __global__ __launch_bounds__(kWave) void k_grad_reduce(const double *gk, int M, 
 
 }  // namespace
 
-const void *grad_kernel(int precision, int R, int WS, int NC) {
-#define TK_GRAD_CASE(real, r, ws, nc)                                                     \
-  if (precision == (sizeof(real) == 8 ? TK_FP64 : TK_FP32) && R == r && WS == ws && NC == nc) \
-    return reinterpret_cast<const void *>(&k_grad<real, r, ws, nc>);
-  TK_GRAD_CASE(double, 1, 4, 2)
-  TK_GRAD_CASE(double, 2, 4, 2)
-  TK_GRAD_CASE(double, 4, 6, 3)
-  TK_GRAD_CASE(double, 4, 8, 4)
-  TK_GRAD_CASE(float, 1, 4, 2)
-  TK_GRAD_CASE(float, 2, 4, 2)
-  TK_GRAD_CASE(float, 4, 6, 3)
-  TK_GRAD_CASE(float, 4, 8, 4)
+const void *grad_kernel(int precision, int R, int WS, int NC, int G) {
+#define TK_GRAD_CASE(real, r, ws, nc, g)                                                   \
+  if (precision == (sizeof(real) == 8 ? TK_FP64 : TK_FP32) && R == r && WS == ws && NC == nc && \
+      G == g)                                                                               \
+    return reinterpret_cast<const void *>(&k_grad<real, r, ws, nc, g>);
+  TK_GRAD_CASE(double, 1, 4, 2, 1)
+  TK_GRAD_CASE(double, 2, 4, 2, 1)
+  TK_GRAD_CASE(double, 4, 6, 3, 1)
+  TK_GRAD_CASE(double, 4, 8, 4, 1)
+  TK_GRAD_CASE(double, 1, 4, 2, 2)
+  TK_GRAD_CASE(float, 1, 4, 2, 1)
+  TK_GRAD_CASE(float, 2, 4, 2, 1)
+  TK_GRAD_CASE(float, 4, 6, 3, 1)
+  TK_GRAD_CASE(float, 4, 8, 4, 1)
+  TK_GRAD_CASE(float, 1, 4, 2, 2)
+  TK_GRAD_CASE(float, 3, 9, 4, 8)
 #undef TK_GRAD_CASE
   return nullptr;
 }
 
 const void *grad_reduce_kernel() { return reinterpret_cast<const void *>(&k_grad_reduce); }
 
-size_t grad_lds_bytes(const Variant &v, int waves, int kbuf) {
+size_t grad_lds_bytes(const Variant &v, int teams, int kbuf) {
   const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
   const size_t ncx = v.NC > 0 ? v.NC : 1;
   const size_t nbuf = std::max<size_t>(kbuf, 2 * (1 + ncx));
-  return 2 * ncx * v.R * kWave * cplx + static_cast<size_t>(waves) * nbuf * (v.R * kWave + 1) * cplx;
+  return static_cast<size_t>(teams) * nbuf * (static_cast<size_t>(v.R) * kWave * v.G + 1) * cplx;
 }
 
 }  // namespace tk

@@ -236,9 +236,8 @@ bool hermitian(const Csr &h) {
 // gathered elements over the LDS bank groups (element c lies in group
 // c mod n_bank_groups), which keeps the gathers of one instruction from
 // colliding in the same banks.
-void pack_group(const Csr *a, int W, int first, int R, int n_bank_groups, int32_t dummy,
-                std::vector<int32_t> &col, std::vector<double> &val) {
-  const int lanes = tk::kWave;
+void pack_group(const Csr *a, int W, int first, int R, int lanes, int n_bank_groups,
+                int32_t dummy, std::vector<int32_t> &col, std::vector<double> &val) {
   std::vector<std::vector<std::pair<int32_t, cd>>> left(static_cast<size_t>(R) * lanes);
   for (int m = 0; m < R; ++m)
     for (int lane = 0; lane < lanes; ++lane) {
@@ -277,26 +276,31 @@ void pack_group(const Csr *a, int W, int first, int R, int n_bank_groups, int32_
       }
 }
 
-// Operators ops[g], each in W slots: layout [g][w][m][lane].
-void pack(const std::vector<const Csr *> &ops, int W, int R, int n_bank_groups, Ell &out) {
-  const size_t n = ops.size() * static_cast<size_t>(W) * R * tk::kWave;
+// Operators ops[g], each in W slots: layout [g][w][m][lane], `lanes` lanes
+// (64 G) per row slot m.
+void pack(const std::vector<const Csr *> &ops, int W, int R, int lanes, int n_bank_groups,
+          Ell &out) {
+  const size_t n = ops.size() * static_cast<size_t>(W) * R * lanes;
   out.col.assign(n, 0);
   out.val.assign(2 * n, 0.0);
-  const int32_t dummy = R * tk::kWave;
+  const int32_t dummy = R * lanes;
   for (size_t g = 0; g < ops.size(); ++g)
-    pack_group(ops[g], W, static_cast<int>(g) * W, R, n_bank_groups, dummy, out.col, out.val);
+    pack_group(ops[g], W, static_cast<int>(g) * W, R, lanes, n_bank_groups, dummy, out.col,
+               out.val);
 }
 
 // Control operators: slots c = i * wc .. i * wc + wc - 1 hold H_i; slots past
 // n_ctrl * wc are padding.
-void pack_ctrl(const std::vector<Csr> &H, int wc, int NC, int R, int n_bank_groups, Ell &out) {
-  const size_t n = static_cast<size_t>(NC) * R * tk::kWave;
+void pack_ctrl(const std::vector<Csr> &H, int wc, int NC, int R, int lanes, int n_bank_groups,
+               Ell &out) {
+  const size_t n = static_cast<size_t>(NC) * R * lanes;
   out.col.assign(n, 0);
   out.val.assign(2 * n, 0.0);
-  const int32_t dummy = R * tk::kWave;
+  const int32_t dummy = R * lanes;
   for (int i = 0; i * wc < NC; ++i) {
     const Csr *a = i < static_cast<int>(H.size()) ? &H[i] : nullptr;
-    pack_group(a, std::min(wc, NC - i * wc), i * wc, R, n_bank_groups, dummy, out.col, out.val);
+    pack_group(a, std::min(wc, NC - i * wc), i * wc, R, lanes, n_bank_groups, dummy, out.col,
+               out.val);
   }
 }
 
@@ -383,7 +387,10 @@ double pass_flops(const tk_ctx *c, const std::vector<double> &u, int M) {
 namespace {
 
 // Waves per block for a plain pass: as many as fit the LDS (at most 4).
+// Teams per block for a plain pass: one G-wave team (G > 1), else as many
+// one-wave teams as fit the LDS (at most 4).
 int pass_waves(const tk_ctx *c, int kbuf) {
+  if (c->var->G > 1) return tk::block_lds_bytes(*c->var, 1, kbuf, 0) <= tk::kLdsBytes ? 1 : 0;
   for (int w = tk::kWavesPerBlock; w >= 1; w /= 2)
     if (tk::block_lds_bytes(*c->var, w, kbuf, 0) <= tk::kLdsBytes) return w;
   return 0;
@@ -533,7 +540,7 @@ int run_forward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap
                                 static_cast<int>(lds)));
   void *args[] = {&a};
   TimedLaunch tl(c, TK_KERNEL_FORWARD);
-  TK_HIP(c, hipLaunchKernel(c->var->k_forward, dim3(blocks), dim3(tk::kWave * wpb), args, lds,
+  TK_HIP(c, hipLaunchKernel(c->var->k_forward, dim3(blocks), dim3(tk::kWave * c->var->G * wpb), args, lds,
                             c->stream));
   int rc = tl.finish(static_cast<int64_t>(M) * c->nt, pass_flops(c, c->u, M),
                      static_cast<double>(M) * c->d * c->bulk_cplx());
@@ -561,7 +568,7 @@ int run_backward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t ca
                                 static_cast<int>(lds)));
   void *args[] = {&a};
   TimedLaunch tl(c, TK_KERNEL_BACKWARD);
-  TK_HIP(c, hipLaunchKernel(c->var->k_backward, dim3(blocks), dim3(tk::kWave * wpb), args, lds,
+  TK_HIP(c, hipLaunchKernel(c->var->k_backward, dim3(blocks), dim3(tk::kWave * c->var->G * wpb), args, lds,
                             c->stream));
   int rc = tl.finish(static_cast<int64_t>(M) * c->nt, pass_flops(c, c->u, M),
                      static_cast<double>(chi_bytes));
@@ -578,14 +585,14 @@ int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap)
   int tw = 0, wpb = 0, blocks = 0;
   size_t lds = 0;
   for (int t = 1; t <= 64 && !tw; ++t)
-    for (int w = tk::kWavesPerBlock; w >= 1; w /= 2) {
+    for (int w = c->var->G > 1 ? 1 : tk::kWavesPerBlock; w >= 1; w /= 2) {
       const int b = (M + w * t - 1) / (w * t);
       const size_t l = tk::block_lds_bytes(*c->var, w, kbuf, t);
       if (b > tk::kMaxBlocks || l > tk::kLdsBytes) continue;
       TK_HIP(c, hipFuncSetAttribute(c->var->k_krotov, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     static_cast<int>(l)));
       int occ = 0;
-      TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, c->var->k_krotov, tk::kWave * w,
+      TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, c->var->k_krotov, tk::kWave * c->var->G * w,
                                                               l));
       if (occ > 0 && static_cast<int64_t>(occ) * c->n_cu >= b) {
         tw = t;
@@ -627,9 +634,9 @@ int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap)
   TimedLaunch tl(c, TK_KERNEL_KROTOV);
   if (c->cooperative) {
     TK_HIP(c, hipLaunchCooperativeKernel(c->var->k_krotov, dim3(blocks),
-                                         dim3(tk::kWave * wpb), args, lds, c->stream));
+                                         dim3(tk::kWave * c->var->G * wpb), args, lds, c->stream));
   } else {  // occupancy was checked above; a stalled grid ends at the spin limit
-    TK_HIP(c, hipLaunchKernel(c->var->k_krotov, dim3(blocks), dim3(tk::kWave * wpb), args, lds,
+    TK_HIP(c, hipLaunchKernel(c->var->k_krotov, dim3(blocks), dim3(tk::kWave * c->var->G * wpb), args, lds,
                               c->stream));
   }
   // new pulses become the current ones
@@ -709,12 +716,12 @@ int run_grad(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec) {
   if (!kern) return fail(c, TK_EUNSUPPORTED, "no gradient kernel for this variant");
   tk::PassArgs a = base_args(c, M, 0, 0, false);
   int wpb = 0;
-  for (int w = tk::kWavesPerBlock; w >= 1 && !wpb; w /= 2)
+  for (int w = c->var->G > 1 ? 1 : tk::kWavesPerBlock; w >= 1 && !wpb; w /= 2)
     if (tk::grad_lds_bytes(*c->var, w, a.kbuf) <= tk::kLdsBytes) wpb = w;
   if (!wpb) return fail(c, TK_EUNSUPPORTED, "the gradient's term vectors do not fit in LDS");
   const int blocks = (M + wpb - 1) / wpb;
   const size_t lds = tk::grad_lds_bytes(*c->var, wpb, a.kbuf);
-  const size_t vec = static_cast<size_t>(c->var->R) * tk::kWave * c->bulk_cplx();
+  const size_t vec = static_cast<size_t>(c->var->R) * tk::kWave * c->var->G * c->bulk_cplx();
   const int nseg = (c->nt + tk::kGradCheckpoint - 1) / tk::kGradCheckpoint;
   TK_HIP(c, c->ckpt.ensure(static_cast<size_t>(M) * nseg * vec));
   TK_HIP(c, c->stash.ensure(static_cast<size_t>(blocks) * wpb * tk::kGradCheckpoint * vec));
@@ -742,7 +749,8 @@ int run_grad(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec) {
                                 static_cast<int>(lds)));
   void *args[] = {&a};
   TimedLaunch tl(c, TK_KERNEL_GRAD);
-  TK_HIP(c, hipLaunchKernel(kern, dim3(blocks), dim3(tk::kWave * wpb), args, lds, c->stream));
+  TK_HIP(c, hipLaunchKernel(kern, dim3(blocks), dim3(tk::kWave * c->var->G * wpb), args, lds,
+                            c->stream));
   // replay, recompute and adjoint sweeps (3 plain passes) plus the augmented
   // series (1 + n_ctrl chains); bytes: checkpoints and the stash, written and
   // read once, and the per-trajectory terms
@@ -864,21 +872,29 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
     wld = std::max(wld, ljd[l].max_row());
   }
   const int nc = n_ctrl * wc;
-  const int r_need = static_cast<int>((d + tk::kWave - 1) / tk::kWave);
-
+  // the compiled variant with the fewest rows 64 G R >= d (then one-wave teams,
+  // then the narrowest slots); TK_VARIANT=<name> picks one by name instead
+  const char *want = std::getenv("TK_VARIANT");
   int nv = 0;
   const tk::Variant *vs = tk::variants(&nv);
   const tk::Variant *best = nullptr;
+  auto key = [](const tk::Variant &v) { return std::make_tuple(v.R * v.G, v.G, v.WS, v.NC); };
   for (int k = 0; k < nv; ++k) {
     const tk::Variant &v = vs[k];
-    if (v.precision != c->precision || v.R < r_need || v.WS < ws || v.NC < nc) continue;
-    if (!best || std::make_tuple(v.R, v.WS, v.NC) < std::make_tuple(best->R, best->WS, best->NC))
-      best = &v;
+    if (v.precision != c->precision || static_cast<int64_t>(v.R) * tk::kWave * v.G < d ||
+        v.WS < ws || v.NC < nc)
+      continue;
+    if (want && *want) {
+      if (std::strcmp(want, v.name) == 0) best = &v;
+      continue;
+    }
+    if (!best || key(v) < key(*best)) best = &v;
   }
   if (!best)
     return fail(c, TK_EUNSUPPORTED,
                 "no compiled kernel variant for d=" + std::to_string(d) + " static width " +
-                    std::to_string(ws) + " control slots " + std::to_string(nc));
+                    std::to_string(ws) + " control slots " + std::to_string(nc) +
+                    (want && *want ? std::string(" named ") + want : std::string()));
   c->var = best;
   c->d = d;
   c->n_ctrl = n_ctrl;
@@ -889,26 +905,27 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   c->H_ctrl_host = hc;
 
   const int R = best->R;
+  const int lanes = tk::kWave * best->G;
   // LDS bank groups of one complex element (32 banks of 4 bytes)
   const int nbg = c->precision == TK_FP64 ? 8 : 16;
   Ell e;
-  pack({&A}, best->WS, R, nbg, e);
+  pack({&A}, best->WS, R, lanes, nbg, e);
   if ((rc = upload_ell(c, e, c->f_scol, c->f_sval))) return rc;
-  pack({&Ad}, best->WS, R, nbg, e);
+  pack({&Ad}, best->WS, R, lanes, nbg, e);
   if ((rc = upload_ell(c, e, c->b_scol, c->b_sval))) return rc;
-  pack_ctrl(hc, wc, best->NC, R, nbg, e);
+  pack_ctrl(hc, wc, best->NC, R, lanes, nbg, e);
   if ((rc = upload_ell(c, e, c->f_ccol, c->f_cval))) return rc;
-  pack_ctrl(hcd, wc, best->NC, R, nbg, e);
+  pack_ctrl(hcd, wc, best->NC, R, lanes, nbg, e);
   if ((rc = upload_ell(c, e, c->b_ccol, c->b_cval))) return rc;
   std::vector<const Csr *> lp;
   for (int l = 0; l < n_jump; ++l) lp.push_back(&lj[l]);
   if (lp.empty()) lp.push_back(nullptr);
-  pack(lp, wl, R, nbg, e);
+  pack(lp, wl, R, lanes, nbg, e);
   if ((rc = upload_ell(c, e, c->lcol, c->lval))) return rc;
   std::vector<const Csr *> ldp;
   for (int l = 0; l < n_jump; ++l) ldp.push_back(&ljd[l]);
   if (ldp.empty()) ldp.push_back(nullptr);
-  pack(ldp, wld, R, nbg, e);
+  pack(ldp, wld, R, lanes, nbg, e);
   if ((rc = upload_ell(c, e, c->ldcol, c->ldval))) return rc;
 
   c->b0 = norm2_estimate(A);
@@ -933,7 +950,7 @@ int tk_set_states(tk_ctx *c, const double *psi0, const double *psi_tgt) {
   if (!psi0 || !psi_tgt) return fail(c, TK_EINVAL, "state pointer is NULL");
   TK_HIP(c, hipSetDevice(c->device));
   const int64_t d = c->d;
-  const int64_t dpad = static_cast<int64_t>(c->var->R) * tk::kWave;
+  const int64_t dpad = static_cast<int64_t>(c->var->R) * tk::kWave * c->var->G;
   double n0 = 0.0, nt = 0.0;
   for (int64_t i = 0; i < 2 * d; ++i) {
     if (!std::isfinite(psi0[i]) || !std::isfinite(psi_tgt[i]))

@@ -137,11 +137,12 @@ struct BatchArgs {
 constexpr int kBatchHistory = 64;  // J_T values kept per instance (ring by iteration)
 
 // One compiled kernel variant: bulk precision, rows per lane R, static slots
-// per row WS, control slots per row NC.
+// per row WS, control slots per row NC, waves per trajectory G (a team; rows
+// 64 G R).
 struct Variant {
   const char *name;
   int precision;  // TK_FP64 / TK_FP32
-  int R, WS, NC;
+  int R, WS, NC, G;
   const void *k_forward;
   const void *k_backward;
   const void *k_krotov;
@@ -157,7 +158,7 @@ const void *functional_kernel();
 
 // Gradient kernel of a variant (defined in tk_grad.hip), and the kernel that
 // reduces the per-trajectory terms: one 64-thread block per pulse value.
-const void *grad_kernel(int precision, int R, int WS, int NC);
+const void *grad_kernel(int precision, int R, int WS, int NC, int G);
 const void *grad_reduce_kernel();
 
 // Batched kernels of a precision (defined in tk_batch.hip).  The shape of an
@@ -168,12 +169,13 @@ struct BatchKernels {
 };
 BatchKernels batch_kernels(int precision);
 
-// LDS bytes of one block of the gradient kernel with `waves` waves.
-size_t grad_lds_bytes(const Variant &v, int waves, int kbuf);
+// LDS bytes of one block of the gradient kernel with `teams` teams.
+size_t grad_lds_bytes(const Variant &v, int teams, int kbuf);
 
-// LDS bytes of one block of `waves` waves: the block's copy of the control
-// slots, then per wave `kbuf` term vectors of 64 R + 1 elements and, for the
-// Krotov pass, `traj_per_wave` state vectors and their bookkeeping.
-size_t block_lds_bytes(const Variant &v, int waves, int kbuf, int traj_per_wave);
+// LDS bytes of one block of `teams` teams (G waves each): the block's copy of
+// the control slots (one-wave teams only), then per team `kbuf` term vectors of 64 G R + 1 elements
+// and, for the Krotov pass, `traj_per_wave` state vectors and their
+// bookkeeping.
+size_t block_lds_bytes(const Variant &v, int teams, int kbuf, int traj_per_wave);
 
 }  // namespace tk

@@ -50,18 +50,22 @@ namespace {
 
 
 // ---- plain forward / backward passes --------------------------------------
-template <typename real, int R, int WS, int NC, int DIR>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) void k_pass(PassArgs a) {
+// Blocks hold kWavesPerBlock one-wave teams (G = 1) or one G-wave team.
+template <typename real, int R, int WS, int NC, int G, int DIR>
+__global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_pass(
+    PassArgs a) {
   extern __shared__ unsigned char smem_raw[];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const int wpb = blockDim.x / kWave;
-  LaneOp<real, R, WS, NC> op;
-  const Terms<real, R> T = block_setup<real, R, WS, NC>(a, smem_raw, wib, lane,
-                                                         terms_bytes<real, R>(a.kbuf), op);
-  const int nwaves = gridDim.x * wpb;
-  for (int k = blockIdx.x * wpb + wib; k < a.M; k += nwaves)
-    pass_trajectory<real, R, WS, NC, DIR>(op, a, T, k, make_stream(a, k, DIR), lane);
+  __shared__ double team_red[2 * G];
+  constexpr int kL = Team<G>::kLanes;
+  const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / kL);
+  const int tpb = blockDim.x / kL;
+  const Team<G> tm = make_team<G>(team_red);
+  LaneOp<real, R, WS, NC, G> op;
+  const Terms<real, R, G> T = block_setup<real, R, WS, NC, G>(
+      a, smem_raw, team, tm, terms_bytes<real, R, G>(a.kbuf), op);
+  const int nteams = gridDim.x * tpb;
+  for (int k = blockIdx.x * tpb + team; k < a.M; k += nteams)
+    pass_trajectory<real, R, WS, NC, G, DIR>(op, a, T, k, make_stream(a, k, DIR), tm);
 }
 
 // ---- slot initialisation for the Krotov pass ---------------------------------
@@ -88,26 +92,32 @@ __device__ __forceinline__ void poll_slots(const unsigned long long *row, int la
 }
 
 // ---- sequential Krotov forward pass (cooperative launch) ---------------------
-template <typename real, int R, int WS, int NC>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
+template <typename real, int R, int WS, int NC, int G>
+__global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_krotov(
+    PassArgs a) {
   extern __shared__ unsigned char smem_raw[];
   constexpr int NCX = NC > 0 ? NC : 1;
+  constexpr int kL = Team<G>::kLanes;
   __shared__ double wpart[kWavesPerBlock][NCX];
   __shared__ double s_upd[NCX];
   __shared__ int s_abort;
+  __shared__ double team_red[2 * G];
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const int wpb = blockDim.x / kWave;
+  const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / kL);
+  const int tpb = blockDim.x / kL;  // teams per block
+  const Team<G> tm = make_team<G>(team_red);
   const int Tw = a.traj_per_wave;
-  const int wave = blockIdx.x * wpb + wib;
-  // LDS per wave: term vectors, then Tw state vectors, then Tw bookkeeping
-  const size_t tb = terms_bytes<real, R>(a.kbuf);
-  const size_t wave_bytes = tb + static_cast<size_t>(Tw) * R * kWave * sizeof(cx<real>) +
+  const int tglob = blockIdx.x * tpb + team;
+  // LDS per team: term vectors, then Tw state vectors, then Tw bookkeeping
+  const size_t tb = terms_bytes<real, R, G>(a.kbuf);
+  const size_t team_bytes = tb + static_cast<size_t>(Tw) * R * kL * sizeof(cx<real>) +
                             static_cast<size_t>(Tw) * sizeof(TrajMeta);
-  LaneOp<real, R, WS, NC> op;
-  const Terms<real, R> T = block_setup<real, R, WS, NC>(a, smem_raw, wib, lane, wave_bytes, op);
+  LaneOp<real, R, WS, NC, G> op;
+  const Terms<real, R, G> T =
+      block_setup<real, R, WS, NC, G>(a, smem_raw, team, tm, team_bytes, op);
   cx<real> *states = reinterpret_cast<cx<real> *>(reinterpret_cast<unsigned char *>(T.base) + tb);
-  TrajMeta *meta = reinterpret_cast<TrajMeta *>(states + static_cast<size_t>(Tw) * R * kWave);
+  TrajMeta *meta = reinterpret_cast<TrajMeta *>(states + static_cast<size_t>(Tw) * R * kL);
   cx<real> *v = T[0];  // scratch vector for the update's gathers
   const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
   if (threadIdx.x == 0) s_abort = 0;
@@ -117,13 +127,13 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
 #pragma unroll
   for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
   for (int t = 0; t < Tw; ++t) {
-    const int k = wave * Tw + t;
+    const int k = tglob * Tw + t;
     cx<real> p[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) p[m] = start[lane + kWave * m];
-    store_lds(states + t * R * kWave, p, lane);
-    const double n = norm2(p);
-    if (lane == 0) {
+    for (int m = 0; m < R; ++m) p[m] = start[tm.gl + kL * m];
+    store_lds(states + t * R * kL, p, tm);
+    const double n = norm2(p, tm);
+    if (tm.leader()) {
       TrajMeta st;
       st.nrm2 = n;
       st.ordinal = 0;
@@ -133,11 +143,11 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
     }
     if (k < a.M) {
       cx<real> ch[R];
-      load_costate<real, R>(a, 0, k, lane, ch);
-      store_lds(v, p, lane);
-      wave_sync();
-      krotov_share<real, R, WS, NC>(op, v, ch, 1.0 / sqrt(n), pc);
-      wave_sync();
+      load_costate<real, R, G>(a, 0, k, tm, ch);
+      store_lds(v, p, tm);
+      tm.sync();
+      krotov_share<real, R, WS, NC, G>(op, v, ch, 1.0 / sqrt(n), pc);
+      tm.sync();
     }
   }
 
@@ -155,14 +165,14 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
     // ---- reduce the partial of t_j: waves -> block (fixed order) -> publish ----
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double s = wave_sum(pc[c]);
-      if (lane == 0) wpart[wib][c] = s;
+      const double s = tm.sum(pc[c]);
+      if (tm.leader()) wpart[team][c] = s;
     }
     __syncthreads();
     if (threadIdx.x < NCX) {  // control i's block partial (zero for padding controls)
       const int i = threadIdx.x;
       double s = 0.0;
-      for (int w = 0; w < wpb; ++w)
+      for (int w = 0; w < tpb; ++w)
         for (int c = i * a.wc; c < (i + 1) * a.wc && c < NC; ++c) s += wpart[w][c];
       __hip_atomic_store(&a.slots[(static_cast<size_t>(j) * kMaxBlocks + blockIdx.x) * NCX + i],
                          __double_as_longlong(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -247,38 +257,38 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
 #pragma unroll
     for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
     for (int t = 0; t < Tw; ++t) {
-      const int k = wave * Tw + t;
+      const int k = tglob * Tw + t;
       if (k >= a.M) break;
-      cx<real> *sv = states + t * R * kWave;
+      cx<real> *sv = states + t * R * kL;
       cx<real> ch[R];
-      if (j + 1 < a.nt) load_costate<real, R>(a, j + 1, k, lane, ch);
+      if (j + 1 < a.nt) load_costate<real, R, G>(a, j + 1, k, tm, ch);
       cx<real> psi[R];
-      load_lds(sv, psi, lane);
+      load_lds(sv, psi, tm);
       TrajMeta st = meta[t];
       const Stream rng = make_stream(a, k, 0);
-      advance_step<real, R, WS, NC, 0>(op, a, T, psi, st, rng, j, p, k, lane);
-      wave_sync();
-      store_lds(sv, psi, lane);
-      if (lane == 0) meta[t] = st;
+      advance_step<real, R, WS, NC, G, 0>(op, a, T, psi, st, rng, j, p, k, tm);
+      tm.sync();
+      store_lds(sv, psi, tm);
+      if (tm.leader()) meta[t] = st;
       if (j + 1 < a.nt) {
-        store_lds(v, psi, lane);
-        wave_sync();
-        krotov_share<real, R, WS, NC>(op, v, ch, 1.0 / sqrt(st.nrm2), pc);
+        store_lds(v, psi, tm);
+        tm.sync();
+        krotov_share<real, R, WS, NC, G>(op, v, ch, 1.0 / sqrt(st.nrm2), pc);
       }
-      wave_sync();
+      tm.sync();
     }
   }
   // ---- functional: tau_k = <tgt|psi_hat_k(T)> and the final states ----------
   cx<real> *psiT = static_cast<cx<real> *>(a.psiT);
   for (int t = 0; t < Tw; ++t) {
-    const int k = wave * Tw + t;
+    const int k = tglob * Tw + t;
     if (k >= a.M) break;
-    const cx<real> *sv = states + t * R * kWave;
+    const cx<real> *sv = states + t * R * kL;
     const double inv = 1.0 / sqrt(meta[t].nrm2);
     double tr = 0.0, ti = 0.0;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int row = lane + kWave * m;
+      const int row = tm.gl + kL * m;
       const cx<real> q = sv[row];
       const double px = q.x * inv, py = q.y * inv;
       const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
@@ -288,9 +298,9 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_krotov(PassArgs a) {
         psiT[static_cast<size_t>(k) * a.d + row] =
             cx<real>{static_cast<real>(px), static_cast<real>(py)};
     }
-    tr = wave_sum(tr);
-    ti = wave_sum(ti);
-    if (lane == 0 && a.tau_out != nullptr) {
+    tr = tm.sum(tr);
+    ti = tm.sum(ti);
+    if (tm.leader() && a.tau_out != nullptr) {
       a.tau_out[2 * k] = tr;
       a.tau_out[2 * k + 1] = ti;
     }
@@ -312,7 +322,7 @@ __global__ __launch_bounds__(256) void k_functional(const double *tau, int M, do
   if (threadIdx.x == 0) *J = 1.0 - part[0] / static_cast<double>(M);
 }
 
-template <typename real, int R, int WS, int NC>
+template <typename real, int R, int WS, int NC, int G>
 Variant make_variant(const char *name) {
   Variant v;
   v.name = name;
@@ -320,11 +330,12 @@ Variant make_variant(const char *name) {
   v.R = R;
   v.WS = WS;
   v.NC = NC;
-  v.k_forward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, 0>);
-  v.k_backward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, 1>);
-  v.k_krotov = reinterpret_cast<const void *>(&k_krotov<real, R, WS, NC>);
+  v.G = G;
+  v.k_forward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, G, 0>);
+  v.k_backward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, G, 1>);
+  v.k_krotov = reinterpret_cast<const void *>(&k_krotov<real, R, WS, NC, G>);
   v.k_fill = reinterpret_cast<const void *>(&k_fill_slots);
-  v.k_grad = grad_kernel(v.precision, R, WS, NC);
+  v.k_grad = grad_kernel(v.precision, R, WS, NC, G);
   return v;
 }
 
@@ -332,14 +343,17 @@ Variant make_variant(const char *name) {
 
 const Variant *variants(int *count) {
   static const Variant table[] = {
-      make_variant<double, 1, 4, 2>("fp64 R=1 WS=4 NC=2"),
-      make_variant<double, 2, 4, 2>("fp64 R=2 WS=4 NC=2"),
-      make_variant<double, 4, 6, 3>("fp64 R=4 WS=6 NC=3"),
-      make_variant<double, 4, 8, 4>("fp64 R=4 WS=8 NC=4"),
-      make_variant<float, 1, 4, 2>("fp32 R=1 WS=4 NC=2"),
-      make_variant<float, 2, 4, 2>("fp32 R=2 WS=4 NC=2"),
-      make_variant<float, 4, 6, 3>("fp32 R=4 WS=6 NC=3"),
-      make_variant<float, 4, 8, 4>("fp32 R=4 WS=8 NC=4"),
+      make_variant<double, 1, 4, 2, 1>("fp64 R=1 WS=4 NC=2"),
+      make_variant<double, 2, 4, 2, 1>("fp64 R=2 WS=4 NC=2"),
+      make_variant<double, 4, 6, 3, 1>("fp64 R=4 WS=6 NC=3"),
+      make_variant<double, 4, 8, 4, 1>("fp64 R=4 WS=8 NC=4"),
+      make_variant<double, 1, 4, 2, 2>("fp64 R=1 WS=4 NC=2 G=2"),
+      make_variant<float, 1, 4, 2, 1>("fp32 R=1 WS=4 NC=2"),
+      make_variant<float, 2, 4, 2, 1>("fp32 R=2 WS=4 NC=2"),
+      make_variant<float, 4, 6, 3, 1>("fp32 R=4 WS=6 NC=3"),
+      make_variant<float, 4, 8, 4, 1>("fp32 R=4 WS=8 NC=4"),
+      make_variant<float, 1, 4, 2, 2>("fp32 R=1 WS=4 NC=2 G=2"),
+      make_variant<float, 3, 9, 4, 8>("fp32 R=3 WS=9 NC=4 G=8"),
   };
   *count = static_cast<int>(sizeof(table) / sizeof(table[0]));
   return table;
@@ -347,13 +361,16 @@ const Variant *variants(int *count) {
 
 const void *functional_kernel() { return reinterpret_cast<const void *>(&k_functional); }
 
-size_t block_lds_bytes(const Variant &v, int waves, int kbuf, int traj_per_wave) {
+size_t block_lds_bytes(const Variant &v, int teams, int kbuf, int traj_per_wave) {
   const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
   const size_t ncx = v.NC > 0 ? v.NC : 1;
-  const size_t per_wave = static_cast<size_t>(kbuf) * (v.R * kWave + 1) * cplx +
-                          static_cast<size_t>(traj_per_wave) * v.R * kWave * cplx +
+  const size_t rows = static_cast<size_t>(v.R) * kWave * v.G;
+  const size_t per_team = static_cast<size_t>(kbuf) * (rows + 1) * cplx +
+                          static_cast<size_t>(traj_per_wave) * rows * cplx +
                           static_cast<size_t>(traj_per_wave) * sizeof(TrajMeta);
-  return ncx * v.R * kWave * cplx + static_cast<size_t>(waves) * per_wave;
+  // one-wave teams share a block copy of the control values; G-wave teams read them
+  // from global memory
+  return (v.G == 1 ? ncx * rows * cplx : 0) + static_cast<size_t>(teams) * per_team;
 }
 
 }  // namespace tk
