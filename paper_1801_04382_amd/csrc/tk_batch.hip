@@ -52,6 +52,7 @@ __device__ void batch_pass_item(const PassArgs &a, int k, uint64_t it, unsigned 
   wave_sync();
   LaneOp<real, R, WS, NC, 1> op;
   op.load(a.scol, a.sval, a.ccol, cval_lds, lane);
+  op.bind(T[0]);
   pass_trajectory<real, R, WS, NC, 1, DIR>(op, a, T, k, make_stream(a, k, DIR, it), tm);
 }
 

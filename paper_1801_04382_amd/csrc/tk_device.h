@@ -11,8 +11,10 @@
 namespace tk {
 namespace {
 
+// complex number of the bulk precision; aligned to its size so that one LDS
+// access moves a whole element
 template <typename real>
-struct cx {
+struct alignas(2 * sizeof(real)) cx {
   real x, y;
 };
 
@@ -173,6 +175,10 @@ struct LaneOp {
   int ccol[NCX][R];
   cx<real> cv[NCX][R];   // control matrix elements scaled by the current pulses
   const cx<real> *cval;  // unscaled control elements of this lane, [c][m][team lane]
+  // LDS addresses of the gathered elements within term vector 0 (see bind);
+  // term n lies n vector lengths further on, a constant offset
+  const cx<real> *sp[WS][R];
+  const cx<real> *cp[NCX][R];
 
   // static slots (scol_g, sval_g) and control columns (ccol_g) from global
   // memory; the unscaled control values stay where cval_src points (LDS or
@@ -196,6 +202,18 @@ struct LaneOp {
         cv[c][m] = cx<real>{0, 0};
       }
     cval = cval_src + gl;
+  }
+
+  // addresses of the lane's gathers in the term vector t0 (once per team)
+  __device__ void bind(const cx<real> *t0) {
+#pragma unroll
+    for (int s = 0; s < WS; ++s)
+#pragma unroll
+      for (int m = 0; m < R; ++m) sp[s][m] = t0 + scol[s][m];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int m = 0; m < R; ++m) cp[c][m] = t0 + ccol[c][m];
   }
 
   // unscaled control element of slot c, row slot m
@@ -322,6 +340,77 @@ __device__ void taylor(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
   for (int m = 0; m < R; ++m) out[m] = cx<real>{in[m].x + inc[m].x, in[m].y + inc[m].y};
 }
 
+// One term of the series from the term vector at the bound gather addresses
+// plus OFF elements: t = (s i tau / n) Op t_prev for the lane's rows.
+template <typename real, int R, int WS, int NC, int G, int SGN, int OFF>
+__device__ __forceinline__ void series_term(const LaneOp<real, R, WS, NC, G> &op, real cf,
+                                            cx<real> (&t)[R], cx<real> (&inc)[R]) {
+  cx<real> b[WS + NC][R];
+#pragma unroll
+  for (int s = 0; s < WS; ++s)
+#pragma unroll
+    for (int m = 0; m < R; ++m) b[s][m] = op.sp[s][m][OFF];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int m = 0; m < R; ++m) b[WS + c][m] = op.cp[c][m][OFF];
+  __builtin_amdgcn_sched_barrier(0);
+  cx<real> y[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+#pragma unroll
+  for (int s = 0; s < WS; ++s)
+#pragma unroll
+    for (int m = 0; m < R; ++m) cfma(y[m], op.sval[s][m], b[s][m]);
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int m = 0; m < R; ++m) cfma(y[m], op.cv[c][m], b[WS + c][m]);
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    if (SGN < 0)
+      t[m] = cx<real>{cf * y[m].y, -cf * y[m].x};
+    else
+      t[m] = cx<real>{-cf * y[m].y, cf * y[m].x};
+    inc[m].x += t[m].x;
+    inc[m].y += t[m].y;
+  }
+}
+
+// The same series without keeping the terms: they alternate between T[0]
+// and T[1], read through the addresses bound to T[0] (LaneOp::bind) plus a
+// constant, so the loop does no address arithmetic.  Steps that end in a jump
+// rebuild the stored terms with taylor() for the dense output.
+template <typename real, int R, int WS, int NC, int G, int SGN>
+__device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                                const Terms<real, R, G> &T, const cx<real> (&in)[R],
+                                cx<real> (&out)[R], double tau, int K, const Team<G> &tm) {
+  constexpr int kLen = Terms<real, R, G>::kLen;
+  constexpr int kL = Team<G>::kLanes;
+  cx<real> *own = T.base + tm.gl;
+  cx<real> t[R], inc[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    t[m] = in[m];
+    inc[m] = cx<real>{0, 0};
+    own[kL * m] = t[m];
+  }
+  for (int n = 1; n <= K; n += 2) {
+    tm.sync();
+    series_term<real, R, WS, NC, G, SGN, 0>(op, static_cast<real>(tau * a.inv_n[n]), t, inc);
+#pragma unroll
+    for (int m = 0; m < R; ++m) own[kLen + kL * m] = t[m];
+    if (n + 1 > K) break;
+    tm.sync();
+    series_term<real, R, WS, NC, G, SGN, kLen>(op, static_cast<real>(tau * a.inv_n[n + 1]), t,
+                                                inc);
+#pragma unroll
+    for (int m = 0; m < R; ++m) own[kL * m] = t[m];
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) out[m] = cx<real>{in[m].x + inc[m].x, in[m].y + inc[m].y};
+}
+
 // p(s) = sum_n s^n t_n and dp/ds from the stored terms (own rows only; Horner)
 template <typename real, int R, int G>
 __device__ __forceinline__ void dense_output(const Terms<real, R, G> &T, int K, real s,
@@ -379,7 +468,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
   constexpr double eps_real = sizeof(real) == 8 ? 0x1.0p-52 : 0x1.0p-23;
   for (int guard = 0;; ++guard) {
     cx<real> out[R];
-    taylor<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, K, tm);
+    taylor_pingpong<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, K, tm);
     const double n_end = norm2(out, tm);
     if (!(n_end < st.r)) {
 #pragma unroll
@@ -396,6 +485,12 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
       return;
     }
     // ---- jump time: root of f(s) = ||p(s)||^2 - r for s in (0, 1] (tau = s tau_rem) ----
+    {  // the series again, now keeping every term for the dense output
+      cx<real> again[R];
+      tm.sync();
+      taylor<real, R, WS, NC, G, SGN>(op, a, T, ps, again, tau_rem, K, tm);
+      tm.sync();
+    }
     double lo = 0.0, hi = 1.0;
     const double flo = n_s - st.r, fhi = n_end - st.r;
     double s = flo / (flo - fhi);
@@ -564,6 +659,7 @@ __device__ __forceinline__ Terms<real, R, G> block_setup(const PassArgs &a, unsi
   if (tm.gl < a.kbuf) T[tm.gl][R * kL] = cx<real>{0, 0};
   __syncthreads();
   op.load(a.scol, a.sval, a.ccol, cval_src, tm.gl);
+  op.bind(T[0]);
   return T;
 }
 

@@ -62,7 +62,7 @@ __device__ void propagate_piece(const LaneOp<real, R, WS, NC, G> &op, const Pass
   for (int s = 0; s < n; ++s) {
     cx<real> out[R];
     tm.sync();
-    taylor<real, R, WS, NC, G, -1>(op, a, T, psi, out, hs, p.K, tm);
+    taylor_pingpong<real, R, WS, NC, G, -1>(op, a, T, psi, out, hs, p.K, tm);
     copy_state(out, psi);
   }
 }
@@ -209,7 +209,7 @@ __device__ void taylor_aug(const LaneOp<real, R, WS, NC, G> &op, const PassArgs 
 template <typename real, int R, int WS, int NC, int G>
 __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_grad(
     PassArgs a) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double team_red[2 * G];
   constexpr int NCX = NC > 0 ? NC : 1;
   constexpr int kL = Team<G>::kLanes;
@@ -227,6 +227,8 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   LaneOp<real, R, WS, NC, G> opf, opb;
   opf.load(a.scol, a.sval, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
   opb.load(a.a_scol, a.a_sval, a.a_ccol, static_cast<const cx<real> *>(a.a_cval), tm.gl);
+  opf.bind(T[0]);
+  opb.bind(T[0]);
 
   const int nseg = (a.nt + kGradCheckpoint - 1) / kGradCheckpoint;
   const int wave = blockIdx.x * tpb + team;  // global team index
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
             for (int ss = 0; ss < s; ++ss) {
               cx<real> out[R];
               tm.sync();
-              taylor<real, R, WS, NC, G, -1>(opf, a, T, xs, out, hs, p.K, tm);
+              taylor_pingpong<real, R, WS, NC, G, -1>(opf, a, T, xs, out, hs, p.K, tm);
               copy_state(out, xs);
             }
             cx<real> X[R], Y[NCX][R];
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
             // lambda <- exp(+i H^+ hs) lambda
             cx<real> out[R];
             tm.sync();
-            taylor<real, R, WS, NC, G, 1>(opb, a, T, lam, out, hs, p.K, tm);
+            taylor_pingpong<real, R, WS, NC, G, 1>(opb, a, T, lam, out, hs, p.K, tm);
             copy_state(out, lam);
           }
         }

@@ -54,7 +54,7 @@ namespace {
 template <typename real, int R, int WS, int NC, int G, int DIR>
 __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_pass(
     PassArgs a) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double team_red[2 * G];
   constexpr int kL = Team<G>::kLanes;
   const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / kL);
@@ -95,7 +95,7 @@ __device__ __forceinline__ void poll_slots(const unsigned long long *row, int la
 template <typename real, int R, int WS, int NC, int G>
 __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_krotov(
     PassArgs a) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NCX = NC > 0 ? NC : 1;
   constexpr int kL = Team<G>::kLanes;
   __shared__ double wpart[kWavesPerBlock][NCX];
@@ -111,8 +111,9 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   const int tglob = blockIdx.x * tpb + team;
   // LDS per team: term vectors, then Tw state vectors, then Tw bookkeeping
   const size_t tb = terms_bytes<real, R, G>(a.kbuf);
-  const size_t team_bytes = tb + static_cast<size_t>(Tw) * R * kL * sizeof(cx<real>) +
-                            static_cast<size_t>(Tw) * sizeof(TrajMeta);
+  // (rounded to 16 bytes: every team's vectors keep the alignment of cx<real>)
+  const size_t team_bytes = (tb + static_cast<size_t>(Tw) * R * kL * sizeof(cx<real>) +
+                             static_cast<size_t>(Tw) * sizeof(TrajMeta) + 15) / 16 * 16;
   LaneOp<real, R, WS, NC, G> op;
   const Terms<real, R, G> T =
       block_setup<real, R, WS, NC, G>(a, smem_raw, team, tm, team_bytes, op);
@@ -365,9 +366,9 @@ size_t block_lds_bytes(const Variant &v, int teams, int kbuf, int traj_per_wave)
   const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
   const size_t ncx = v.NC > 0 ? v.NC : 1;
   const size_t rows = static_cast<size_t>(v.R) * kWave * v.G;
-  const size_t per_team = static_cast<size_t>(kbuf) * (rows + 1) * cplx +
-                          static_cast<size_t>(traj_per_wave) * rows * cplx +
-                          static_cast<size_t>(traj_per_wave) * sizeof(TrajMeta);
+  const size_t per_team = (static_cast<size_t>(kbuf) * (rows + 1) * cplx +
+                           static_cast<size_t>(traj_per_wave) * rows * cplx +
+                           static_cast<size_t>(traj_per_wave) * sizeof(TrajMeta) + 15) / 16 * 16;
   // one-wave teams share a block copy of the control values; G-wave teams read them
   // from global memory
   return (v.G == 1 ? ncx * rows * cplx : 0) + static_cast<size_t>(teams) * per_team;
