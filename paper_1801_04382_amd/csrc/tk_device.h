@@ -50,6 +50,20 @@ __device__ __forceinline__ double wave_sum(double x) {
   return (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
 }
 
+// Two wave sums at once (the DPP chains interleave); same order as wave_sum.
+__device__ __forceinline__ void wave_sum2(double &x, double &y) {
+  x += dpp_mov<0xB1>(x);
+  y += dpp_mov<0xB1>(y);
+  x += dpp_mov<0x4E>(x);
+  y += dpp_mov<0x4E>(y);
+  x += dpp_mov<0x141>(x);
+  y += dpp_mov<0x141>(y);
+  x += dpp_mov<0x140>(x);
+  y += dpp_mov<0x140>(y);
+  x = (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
+  y = (read_lane(y, 0) + read_lane(y, 16)) + (read_lane(y, 32) + read_lane(y, 48));
+}
+
 // The lanes that advance one trajectory together: G wavefronts (G = 1: one
 // wavefront; G > 1: the G waves of a block, which then holds just this team).
 // Row r of a state belongs to team lane r mod 64G as its slot m = r / 64G.
@@ -62,7 +76,7 @@ struct Team {
   int gl;            // lane within the team
   int lane;          // lane within the wave
   int g;             // wave within the team
-  double *red;       // LDS [2][G] (G > 1)
+  double *red;       // LDS [2][2 G] (G > 1)
   mutable int par;   // half of red the next sum writes
   __device__ __forceinline__ void sync() const {
     if (G == 1)
@@ -73,7 +87,7 @@ struct Team {
   __device__ __forceinline__ double sum(double x) const {
     x = wave_sum(x);
     if (G == 1) return x;
-    double *r = red + par * G;
+    double *r = red + par * 2 * G;
     if (lane == 0) r[g] = x;
     __syncthreads();
     double s = 0.0;
@@ -81,6 +95,26 @@ struct Team {
     for (int q = 0; q < G; ++q) s += r[q];
     par ^= 1;
     return s;
+  }
+  // two team sums with one exchange
+  __device__ __forceinline__ void sum2(double &x, double &y) const {
+    wave_sum2(x, y);
+    if (G == 1) return;
+    double *r = red + par * 2 * G;
+    if (lane == 0) {
+      r[g] = x;
+      r[G + g] = y;
+    }
+    __syncthreads();
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      sx += r[q];
+      sy += r[G + q];
+    }
+    par ^= 1;
+    x = sx;
+    y = sy;
   }
   __device__ __forceinline__ bool leader() const { return gl == 0; }
 };
@@ -455,12 +489,16 @@ __device__ __forceinline__ void apply_jump(const PassArgs &a, int l, const cx<re
 // Advance one trajectory across one substep of length h starting at time t0
 // (MCWF with precise jump times).  DIR 0: forward, exp(-i H_eff tau), times
 // t0 + elapsed; DIR 1: backward, exp(+i H_eff^+ tau), times t0 - elapsed.
+// K is the order for the whole substep and bnd a bound on ||H_eff||; what is
+// left of a substep after a jump takes the (lower) order its length needs.
 template <typename real, int R, int WS, int NC, int G, int DIR>
 __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                         const Terms<real, R, G> &T, cx<real> (&psi)[R], TrajMeta &st,
-                        const Stream &rng, int j, double t0, double h, int K, int k, const Team<G> &tm) {
+                        const Stream &rng, int j, double t0, double h, int K, double bnd, int k,
+                        const Team<G> &tm) {
   constexpr int SGN = DIR == 0 ? -1 : 1;
   double tau_rem = h;
+  int Kc = K;
   double n_s = st.nrm2;
   cx<real> ps[R];
 #pragma unroll
@@ -468,7 +506,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
   constexpr double eps_real = sizeof(real) == 8 ? 0x1.0p-52 : 0x1.0p-23;
   for (int guard = 0;; ++guard) {
     cx<real> out[R];
-    taylor_pingpong<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, K, tm);
+    taylor_pingpong<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, Kc, tm);
     const double n_end = norm2(out, tm);
     if (!(n_end < st.r)) {
 #pragma unroll
@@ -488,7 +526,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     {  // the series again, now keeping every term for the dense output
       cx<real> again[R];
       tm.sync();
-      taylor<real, R, WS, NC, G, SGN>(op, a, T, ps, again, tau_rem, K, tm);
+      taylor<real, R, WS, NC, G, SGN>(op, a, T, ps, again, tau_rem, Kc, tm);
       tm.sync();
     }
     double lo = 0.0, hi = 1.0;
@@ -497,15 +535,19 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     if (!(s > lo && s < hi)) s = 0.5;
     cx<real> pt[R], dp[R];
     for (int it = 0; it < 64; ++it) {
-      dense_output<real, R, G>(T, K, static_cast<real>(s), pt, dp, tm);
-      const double f = norm2(pt, tm) - st.r;
-      double g = 0.0;  // Re <p|dp/ds>
+      dense_output<real, R, G>(T, Kc, static_cast<real>(s), pt, dp, tm);
+      double f = 0.0, g = 0.0;  // ||p||^2 and Re <p|dp/ds>, reduced together
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        g = fma(static_cast<double>(pt[m].x), static_cast<double>(dp[m].x), g);
-        g = fma(static_cast<double>(pt[m].y), static_cast<double>(dp[m].y), g);
+        const double px = pt[m].x, py = pt[m].y;
+        f = fma(px, px, f);
+        f = fma(py, py, f);
+        g = fma(px, static_cast<double>(dp[m].x), g);
+        g = fma(py, static_cast<double>(dp[m].y), g);
       }
-      const double fp = 2.0 * tm.sum(g);
+      tm.sum2(f, g);
+      f -= st.r;
+      const double fp = 2.0 * g;
       if (f >= 0.0)
         lo = s;
       else
@@ -515,25 +557,52 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
       if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
       if (fabs(sn - s) <= 2.0 * eps_real) {
         s = sn;
-        dense_output<real, R, G>(T, K, static_cast<real>(s), pt, dp, tm);
+        dense_output<real, R, G>(T, Kc, static_cast<real>(s), pt, dp, tm);
         break;
       }
       s = sn;
     }
     const double tau = s * tau_rem;
     // ---- jump (MCWF step 4) ----
+    tm.sync();
     store_lds(T[0], pt, tm);
     tm.sync();
-    // weights ||L_l p||^2; pass 1 sums them, pass 2 walks the cumulative sum
-    double total = 0.0;
-    for (int l = 0; l < a.n_jump; ++l) {
-      cx<real> y[R];
-      apply_jump<real, R, G>(a, l, T[0], y, tm);
-      total += norm2(y, tm);
-    }
     double thr_unused, x;
     rng.block(static_cast<uint64_t>(st.ordinal), thr_unused, x);
-    if (!(total > 0.0)) {
+    int lsel = -1;
+    double wsel = 0.0;
+    cx<real> y[R];
+    if (a.n_jump == 1) {  // one operator: its weight only has to be non-zero
+      apply_jump<real, R, G>(a, 0, T[0], y, tm);
+      wsel = norm2(y, tm);
+      if (wsel > 0.0) lsel = 0;
+    } else {
+      // weights ||L_l p||^2; pass 1 sums them, pass 2 walks the cumulative sum
+      double total = 0.0;
+      for (int l = 0; l < a.n_jump; ++l) {
+        apply_jump<real, R, G>(a, l, T[0], y, tm);
+        total += norm2(y, tm);
+      }
+      if (total > 0.0) {
+        const double target = x * total;
+        double acc = 0.0;
+        for (int l = 0; l < a.n_jump; ++l) {
+          apply_jump<real, R, G>(a, l, T[0], y, tm);
+          wsel = norm2(y, tm);
+          acc += wsel;
+          if (target < acc) {
+            lsel = l;
+            break;
+          }
+        }
+        if (lsel < 0) {  // rounding left target >= total: take the last operator
+          lsel = a.n_jump - 1;
+          apply_jump<real, R, G>(a, lsel, T[0], y, tm);
+          wsel = norm2(y, tm);
+        }
+      }
+    }
+    if (lsel < 0) {
       if (tm.leader()) atomicOr(a.err, kErrNoJumpWeight);
 #pragma unroll
       for (int m = 0; m < R; ++m) psi[m] = pt[m];
@@ -541,24 +610,6 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
       st.r = 0.0;
       tm.sync();
       return;
-    }
-    const double target = x * total;
-    double acc = 0.0, wsel = 0.0;
-    int lsel = -1;
-    cx<real> y[R];
-    for (int l = 0; l < a.n_jump; ++l) {
-      apply_jump<real, R, G>(a, l, T[0], y, tm);
-      wsel = norm2(y, tm);
-      acc += wsel;
-      if (target < acc) {
-        lsel = l;
-        break;
-      }
-    }
-    if (lsel < 0) {  // rounding left target >= total: take the last operator
-      lsel = a.n_jump - 1;
-      apply_jump<real, R, G>(a, lsel, T[0], y, tm);
-      wsel = norm2(y, tm);
     }
     tm.sync();
     const real inv = static_cast<real>(1.0 / sqrt(wsel));
@@ -575,7 +626,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
         r.op = lsel;
         r.ordinal = st.ordinal;
         r.direction = DIR;
-        r.iteration = static_cast<int32_t>(a.iteration);
+        r.iteration = static_cast<int32_t>(rng.iteration);
         r.reserved = 0;
         r.t = DIR == 0 ? t0 + elapsed : t0 - elapsed;
         a.rec[slot] = r;
@@ -585,13 +636,16 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     st.r = rng.threshold(static_cast<uint64_t>(st.ordinal));
     n_s = norm2(ps, tm);
     tau_rem = tau_rem - tau;
+    const int Kr = taylor_order(bnd * tau_rem, a.tol, a.kmax);
+    if (Kr >= 1 && Kr < Kc) Kc = Kr;
   }
 }
 
 struct StepPlan {
-  int n_sub;  // substeps per step
-  int K;      // Taylor order of a substep
-  double h;   // substep length
+  int n_sub;   // substeps per step
+  int K;       // Taylor order of a substep
+  double h;    // substep length
+  double bnd;  // bound on ||H_eff|| of the step
 };
 
 // Substeps and polynomial order of step j from the norm bound of its H_eff:
@@ -604,15 +658,17 @@ __device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&
   for (int i = 0; i < N; ++i) b += fabs(uj[i]) * a.bc[i];
   const double x = b * a.dt;
   StepPlan p;
+  p.bnd = b;
+  const int kfit = a.kbuf - 1;  // largest order whose terms fit the LDS
   p.n_sub = x > kMaxStepNorm ? static_cast<int>(ceil(x / kMaxStepNorm)) : 1;
   p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
-  while ((p.K < 0 || p.K > a.kbuf - 1) && p.n_sub < kMaxSubsteps) {
+  while ((p.K < 0 || p.K > kfit) && p.n_sub < kMaxSubsteps) {
     p.n_sub += 1;
     p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
   }
-  if (p.K < 0 || p.K > a.kbuf - 1) {
+  if (p.K < 0 || p.K > kfit) {
     atomicOr(a.err, kErrTaylorOrder);
-    p.K = a.kbuf - 1;
+    p.K = kfit;
   }
   p.h = a.dt / static_cast<double>(p.n_sub);
   return p;
@@ -628,7 +684,7 @@ __device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC, G> &o
   for (int s = 0; s < p.n_sub; ++s) {
     const double t0 = DIR == 0 ? static_cast<double>(j) * a.dt + s * p.h
                                : static_cast<double>(j + 1) * a.dt - s * p.h;
-    advance<real, R, WS, NC, G, DIR>(op, a, T, psi, st, rng, j, t0, p.h, p.K, k, tm);
+    advance<real, R, WS, NC, G, DIR>(op, a, T, psi, st, rng, j, t0, p.h, p.K, p.bnd, k, tm);
   }
 }
 

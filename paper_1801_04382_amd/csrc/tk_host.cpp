@@ -361,7 +361,8 @@ void plan_step_host(const tk_ctx *c, const std::vector<double> &u, int j, int *n
 namespace tkh {
 
 // Term vectors a pass needs: the largest order over its steps, plus one for
-// the zeroth term and `margin` for pulses that grow during a Krotov pass.
+// the zeroth term (a step that ends in a jump keeps t_0 .. t_K) and `margin`
+// for pulses that grow during a Krotov pass.
 int plan_kbuf(const tk_ctx *c, const std::vector<double> &u, int margin) {
   int kmax = 1;
   for (int j = 0; j < c->nt; ++j) {
