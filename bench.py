@@ -116,7 +116,8 @@ def bench_batched(n_inst: int, steps: int, nodes, check: int) -> dict:
             "krotov_iters_per_s": steps / el, "ms_per_iteration": 1e3 * el / steps,
             "graph_iteration_ms": info["last_iteration_ms"],
             "launch": {k: info[k] for k in ("pass_waves_per_block", "pass_blocks",
-                                             "krotov_waves_per_block", "krotov_blocks")},
+                                             "krotov_waves_per_block", "krotov_blocks",
+                                             "tuned_pass_ms", "tuned_krotov_ms")},
             "max_abs_dJ_fp32_vs_fp64": max(dJ) if dJ else None,
             "dJ_checked_instances": len(dJ)}
 
@@ -144,6 +145,51 @@ def bench_grad(workload: str, reps: int) -> dict:
             "roofline": {"bound": "alu", "achieved": t["flops"] / t["launches"] / (avg * 1e-3) / 1e12,
                          "peak": PEAK["fp64"], "unit": "TFLOP/s",
                          "frac": t["flops"] / t["launches"] / (avg * 1e-3) / 1e12 / PEAK["fp64"]}}
+
+
+def bench_precision(workload: str) -> dict:
+    """Precision form: one guess pass + one Krotov iteration of the same workload
+    in FP32 and in FP64 (same seeds and streams); rates and the J_T difference."""
+    import numpy as np
+    from paper_1801_04382_amd import trajkrotov as tk
+    from workloads import config_workload
+    w = config_workload(workload)
+    out = {"workload": workload, "d": w.dim, "M": w.M, "nt": w.nt}
+    J = {}
+    for prec in ("fp32", "fp64"):
+        with tk.Context(precision=prec) as ctx:
+            ctx.load(w)
+            J0, _, _ = ctx.krotov_iterate(w.M, w.seed, 0, rec_cap=0)
+            t0 = time.perf_counter()
+            J1, _, _ = ctx.krotov_iterate(w.M, w.seed, 1, first_iteration=1, rec_cap=0)
+            el = time.perf_counter() - t0
+            J[prec] = np.concatenate([J0, J1])
+            out[prec] = {"ms_per_iteration": 1e3 * el,
+                         "value": 2.0 * w.M * w.nt / el, "unit": "trajectory-steps/s",
+                         "variant": ctx.launch_info()["variant"]}
+    out["fp32_over_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    out["max_abs_dJ_fp32_vs_fp64"] = float(np.max(np.abs(J["fp32"] - J["fp64"])))
+    return out
+
+
+def bench_grad_large(workload: str) -> dict:
+    """Pathwise gradient of the FP32 workload (d = 1296): records from one
+    forward pass, then one gradient."""
+    from paper_1801_04382_amd import trajkrotov as tk
+    from workloads import config_workload
+    w = config_workload(workload)
+    with tk.Context(precision="fp32") as ctx:
+        ctx.load(w)
+        _, _, rec, n = ctx.propagate_forward(w.M, w.seed, 0, want_states=False, rec_cap=8 * w.M)
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        ctx.grad_pathwise(w.M, rec)
+        el = time.perf_counter() - t0
+        t = ctx.timing(tk.TK_KERNEL_GRAD)
+        variant = ctx.launch_info()["variant"]
+    return {"workload": workload, "d": w.dim, "M": w.M, "nt": w.nt, "records": int(n),
+            "variant": variant, "s_per_gradient": el, "kernel_ms": t["ms_total"],
+            "value": w.M * w.nt / el, "unit": "trajectory-steps/s (replay + reverse sweep)"}
 
 
 def copy_probe(mib: int, reps: int) -> int:
@@ -249,6 +295,8 @@ def main() -> int:
             "batched_fp32": bench_batched(args.batch_instances, args.batch_steps,
                                           [int(x) for x in args.batch_nodes.split(",")], 2),
             "grad_fp64": bench_grad(args.workload, 3),
+            "precision_fp32_vs_fp64": bench_precision("chain3_fock2"),
+            "grad_fp32_d1296": bench_grad_large("chain4_fock2"),
         }
         out["forms"]["fp32_batched_vs_fp64_plain"] = (
             out["forms"]["batched_fp32"]["value"] / out["value"])

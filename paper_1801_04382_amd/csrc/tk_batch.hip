@@ -105,43 +105,63 @@ __device__ __forceinline__ void publish_share(const PassArgs &a, unsigned long l
   }
 }
 
+// Loads of the shares of trajectories lane + 64 (q0 + qq), qq < CH (0 past M).
+template <int NCX, int CH>
+__device__ __forceinline__ void load_shares(const unsigned long long *row, int M, int lane, int q0,
+                                            unsigned long long (&v)[CH][NCX]) {
+#pragma unroll
+  for (int qq = 0; qq < CH; ++qq) {
+    const int k = lane + kWave * (q0 + qq);
+#pragma unroll
+    for (int c = 0; c < NCX; ++c)
+      v[qq][c] = k < M ? __hip_atomic_load(&row[static_cast<size_t>(k) * NCX + c],
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : 0ull;
+  }
+}
+
 // Waits for the M shares of one step and sums them in a fixed order (lane l
-// takes k = l, l + 64, ... in increasing k; then the wave reduction).
-// Returns false if the spin limit is reached or another block gave up.
+// takes k = l, l + 64, ... in increasing k; then the wave reduction).  The
+// trajectories are read in groups of 64 CH; the loads of the next group are in
+// flight while the current one is checked, and a group with a share still
+// missing is read again until it is complete.  Returns false if the spin
+// limit is reached or another block gave up.
 template <int NCX>
 __device__ bool gather_shares(const unsigned long long *row, int M, int lane,
                               long long spin_limit, int *err, double (&acc)[NCX]) {
-  constexpr int CH = 4;  // 64-trajectory groups whose loads are in flight together
+  constexpr int CH = 4;
 #pragma unroll
   for (int c = 0; c < NCX; ++c) acc[c] = 0.0;
   long long spins = 0;
+  unsigned long long cur[CH][NCX], nxt[CH][NCX];
+  load_shares<NCX, CH>(row, M, lane, 0, cur);
   for (int q0 = 0; q0 * kWave < M; q0 += CH) {
-    unsigned long long v[CH][NCX];
+    const bool more = (q0 + CH) * kWave < M;
+    if (more) load_shares<NCX, CH>(row, M, lane, q0 + CH, nxt);
+    __builtin_amdgcn_sched_barrier(0);
     for (;;) {
-#pragma unroll
-      for (int qq = 0; qq < CH; ++qq) {
-        const int k = lane + kWave * (q0 + qq);
-#pragma unroll
-        for (int c = 0; c < NCX; ++c)
-          v[qq][c] = k < M ? __hip_atomic_load(&row[static_cast<size_t>(k) * NCX + c],
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                           : 0ull;
-      }
       int missing = 0;
 #pragma unroll
       for (int qq = 0; qq < CH; ++qq)
 #pragma unroll
-        for (int c = 0; c < NCX; ++c) missing |= v[qq][c] == kSlotEmpty;
+        for (int c = 0; c < NCX; ++c) missing |= cur[qq][c] == kSlotEmpty;
       if (!__any(missing)) break;
       if (++spins > spin_limit ||
           ((spins & 255) == 0 &&
            (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrSyncTimeout)))
         return false;
+      load_shares<NCX, CH>(row, M, lane, q0, cur);
     }
 #pragma unroll
     for (int qq = 0; qq < CH; ++qq)
 #pragma unroll
-      for (int c = 0; c < NCX; ++c) acc[c] += __longlong_as_double(static_cast<long long>(v[qq][c]));
+      for (int c = 0; c < NCX; ++c) acc[c] += __longlong_as_double(static_cast<long long>(cur[qq][c]));
+    if (more) {
+#pragma unroll
+      for (int qq = 0; qq < CH; ++qq)
+#pragma unroll
+        for (int c = 0; c < NCX; ++c) cur[qq][c] = nxt[qq][c];
+    }
   }
 #pragma unroll
   for (int c = 0; c < NCX; ++c) acc[c] = wave_sum(acc[c]);
@@ -241,13 +261,27 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     }
     op.set_pulses(uj, a.wc);
     const StepPlan p = plan_step(a, uj);
-    for (int k = w; k < a.M; k += nw) {
-      cx<real> ch[R];
-      if (j + 1 < a.nt) load_costate<real, R, 1>(a, j + 1, k, tm, ch);
-      cx<real> psi[R];
+    // the wave's trajectories in turn; the state, clock and costate of the next
+    // one are loaded while the current one advances
+    cx<real> psi[R], ch[R];
+    TrajMeta st;
+    if (w < a.M) {
 #pragma unroll
-      for (int m = 0; m < R; ++m) psi[m] = psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m];
-      TrajMeta st = meta_g[k];
+      for (int m = 0; m < R; ++m) psi[m] = psi_g[static_cast<size_t>(w) * kRows + lane + kWave * m];
+      st = meta_g[w];
+      if (j + 1 < a.nt) load_costate<real, R, 1>(a, j + 1, w, tm, ch);
+    }
+    for (int k = w; k < a.M; k += nw) {
+      const int kn = k + nw;
+      cx<real> psi_n[R], ch_n[R];
+      TrajMeta st_n;
+      if (kn < a.M) {
+#pragma unroll
+        for (int m = 0; m < R; ++m)
+          psi_n[m] = psi_g[static_cast<size_t>(kn) * kRows + lane + kWave * m];
+        st_n = meta_g[kn];
+        if (j + 1 < a.nt) load_costate<real, R, 1>(a, j + 1, kn, tm, ch_n);
+      }
       const Stream rng = make_stream(a, k, 0, it);
       advance_step<real, R, WS, NC, 1, 0>(op, a, T, psi, st, rng, j, p, k, tm);
 #pragma unroll
@@ -264,6 +298,14 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
         publish_share<NC>(a, I.tslots + static_cast<size_t>(j + 1) * row_len, k, pc, lane);
       }
       wave_sync();
+      if (kn < a.M) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          psi[m] = psi_n[m];
+          ch[m] = ch_n[m];
+        }
+        st = st_n;
+      }
     }
   }
   // ---- tau_k = <tgt|psi_hat_k(T)> ----
@@ -293,7 +335,10 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArg
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double s_upd[kMaxCtrl];
   __shared__ int s_abort;
-  if (threadIdx.x == 0) s_abort = 0;
+  if (threadIdx.x == 0) {
+    s_abort = 0;
+    atomicMin(b.t_begin, static_cast<unsigned long long>(wall_clock64()));
+  }
   const int i = __builtin_amdgcn_readfirstlane(b.block_inst[blockIdx.x]);
   const BatchInstance &I = b.inst[i];
   const int lb = blockIdx.x - I.block0;
@@ -308,6 +353,9 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArg
     default:
       break;
   }
+  // the instance's finishing time, for the autotuner's block split
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&b.t_end[i], static_cast<unsigned long long>(wall_clock64()));
 }
 
 // ---- bookkeeping kernels ------------------------------------------------------------
@@ -340,8 +388,8 @@ __global__ __launch_bounds__(256) void k_batch_functional(BatchArgs b) {
 }
 
 // End of an iteration: the updated pulses become the current ones (one block
-// per instance); block 0 advances the iteration counter after every block has
-// read it (the counter is read only by the next launches).
+// per instance); block 0 advances the iteration counter (read only by the next
+// launches).
 __global__ __launch_bounds__(256) void k_batch_finish(BatchArgs b, int copy_pulses) {
   const BatchInstance &I = b.inst[blockIdx.x];
   if (copy_pulses) {

@@ -61,6 +61,8 @@ struct tk_batch {
   LaunchPlan plan;
   bool tuned = false;
   DevBuf inst_dev, items_dev, block_inst_dev, iter_dev, J_hist_dev, err_dev, rec_dev, rec_count_dev;
+  DevBuf t_begin_dev, t_end_dev;  // launch start and per-instance finish (constant clock)
+  double clock_khz = 0.0;         // rate of that clock
   std::vector<tk::BatchInstance> inst;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -112,15 +114,18 @@ size_t pass_wave_lds(const tk_batch *b, const Member &m) {
 
 // Krotov blocks per instance: every instance gets one, then blocks go one at a
 // time to the instance with the longest estimated pass,
-//   nt (ceil(M / (blocks * wpb)) step_cost + sync_cost),
-// until `capacity` blocks are given out or the longest cannot gain.
-std::vector<int> split_blocks(const tk_batch *b, int capacity, int wpb, double sync_cost) {
+//   nt (ceil(M / (blocks * wpb)) cost + sync_cost),
+// until `capacity` blocks are given out or the longest cannot gain.  `cost` is
+// the time of one trajectory-step per instance (measured), or null for the
+// model m.step_cost.
+std::vector<int> split_blocks(const tk_batch *b, int capacity, int wpb, double sync_cost,
+                              const std::vector<double> *cost) {
   const size_t n = b->mem.size();
   std::vector<int> nb(n, 1);
   auto est = [&](size_t i) {
     const Member &m = *b->mem[i];
     const double tw = std::ceil(static_cast<double>(m.M) / (static_cast<double>(nb[i]) * wpb));
-    return m.c->nt * (tw * m.step_cost + sync_cost);
+    return m.c->nt * (tw * (cost ? (*cost)[i] : m.step_cost) + sync_cost);
   };
   int used = static_cast<int>(n);
   while (used < capacity) {
@@ -167,6 +172,8 @@ tk::BatchArgs batch_args(tk_batch *b) {
   a.block_inst = b->block_inst_dev.as<int>();
   a.iteration = b->iter_dev.as<uint64_t>();
   a.J_hist = b->J_hist_dev.as<double>();
+  a.t_begin = b->t_begin_dev.as<unsigned long long>();
+  a.t_end = b->t_end_dev.as<unsigned long long>();
   a.err = b->err_dev.as<int>();
   a.spin_limit = 1ll << 22;
   return a;
@@ -195,7 +202,8 @@ int plan_pass(tk_batch *b, int wpb) {
 }
 
 // Krotov plan with `wpb` waves per block and a fraction of the co-resident blocks.
-int plan_krotov(tk_batch *b, int wpb, double frac, double sync_cost) {
+int plan_krotov(tk_batch *b, int wpb, double frac, double sync_cost,
+                const std::vector<double> *cost = nullptr) {
   size_t lds = 0;
   for (const auto &m : b->mem)
     lds = std::max(lds, tk::block_lds_bytes(*m->c->var, wpb, m->kbuf_fw, 0));
@@ -209,7 +217,7 @@ int plan_krotov(tk_batch *b, int wpb, double frac, double sync_cost) {
   if (capacity < static_cast<int>(b->mem.size())) return TK_EUNSUPPORTED;
   b->plan.kro_wpb = wpb;
   b->plan.kro_lds = lds;
-  b->plan.nblocks = split_blocks(b, capacity, wpb, sync_cost);
+  b->plan.nblocks = split_blocks(b, capacity, wpb, sync_cost, cost);
   return upload_tables(b);
 }
 
@@ -282,6 +290,13 @@ int finalize(tk_batch *b) {
   TK_BHIP(b, b->err_dev.ensure(sizeof(int)));
   TK_BHIP(b, b->rec_dev.ensure(sizeof(tk_jump)));
   TK_BHIP(b, b->rec_count_dev.ensure(sizeof(unsigned long long)));
+  TK_BHIP(b, b->t_begin_dev.ensure(sizeof(unsigned long long)));
+  TK_BHIP(b, b->t_end_dev.ensure(n * sizeof(unsigned long long)));
+  {
+    int khz = 0;
+    TK_BHIP(b, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
+    b->clock_khz = khz;
+  }
   TK_BHIP(b, hipMemset(b->err_dev.p, 0, sizeof(int)));
   TK_BHIP(b, hipMemset(b->rec_count_dev.p, 0, sizeof(unsigned long long)));
   b->inst.assign(n, tk::BatchInstance{});
@@ -352,9 +367,32 @@ int finalize(tk_batch *b) {
   return TK_OK;
 }
 
-// Autotuner: times the costate pass for each waves-per-block choice and the
-// Krotov pass for each (waves per block, weight of the per-step exchange in
-// the block split); keeps the fastest.  The
+// One Krotov pass with the current plan: its duration (ms) and, per instance,
+// the time from the launch's first block start to the instance's last block end.
+int time_krotov(tk_batch *b, double *ms, std::vector<double> *inst_us) {
+  const size_t n = b->mem.size();
+  const unsigned long long never = ~0ull;
+  std::vector<unsigned long long> t_end(n, 0ull);
+  TK_BHIP(b, hipMemcpy(b->t_begin_dev.p, &never, sizeof(never), hipMemcpyHostToDevice));
+  TK_BHIP(b, hipMemcpy(b->t_end_dev.p, t_end.data(), n * sizeof(unsigned long long),
+                       hipMemcpyHostToDevice));
+  int rc = timed(b, [&] { return launch_krotov(b); }, ms);
+  if (rc) return rc;
+  if ((rc = check_errors(b))) return rc;
+  unsigned long long t0 = 0;
+  TK_BHIP(b, hipMemcpy(&t0, b->t_begin_dev.p, sizeof(t0), hipMemcpyDeviceToHost));
+  TK_BHIP(b, hipMemcpy(t_end.data(), b->t_end_dev.p, n * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost));
+  inst_us->assign(n, 0.0);
+  for (size_t i = 0; i < n; ++i)
+    (*inst_us)[i] = t_end[i] > t0 ? (t_end[i] - t0) * 1e3 / b->clock_khz : 0.0;
+  return TK_OK;
+}
+
+// Autotuner: times the costate pass for each waves-per-block choice, and the
+// Krotov pass for each waves-per-block choice with two block splits -- one from
+// the cost model, one from the per-instance times measured on the first run --
+// and keeps the fastest.  The
 // passes are deterministic and independent of the tile shape, so the repeated
 // runs leave the same results as one run.
 int autotune(tk_batch *b) {
@@ -374,27 +412,39 @@ int autotune(tk_batch *b) {
   int rc = plan_pass(b, best_wpb);
   if (rc) return rc;
   b->tuned_pass_ms = best;
+  // Krotov pass: for each waves-per-block choice, a split from the cost model,
+  // then a split from the per-trajectory-step times measured on that run
   double kbest = 1e300;
   int kw = 0;
-  double ks = 0.0;
-  double unit = 0.0;  // step_cost -> sync weight scale: the cheapest instance's step
+  std::vector<int> kblocks;
+  double unit = 0.0;  // the cheapest instance's modelled step: scale of the exchange weight
   for (const auto &m : b->mem) unit = unit == 0.0 ? m->step_cost : std::min(unit, m->step_cost);
-  const double frac = 1.0;
-  for (int wpb : {4, 2, 1})
-    for (double sync : {0.0, 2.0 * unit}) {
-        if (plan_krotov(b, wpb, frac, sync)) continue;
-        double ms = 0.0;
-        rc = timed(b, [&] { return launch_krotov(b); }, &ms);
-        if (rc) return rc;
-        if ((rc = check_errors(b))) return rc;
-        if (ms < kbest) {
-          kbest = ms;
-          kw = wpb;
-          ks = sync;
-        }
+  for (int wpb : {4, 2, 1}) {
+    std::vector<double> cost;
+    for (int round = 0; round < 2; ++round) {
+      if (plan_krotov(b, wpb, 1.0, round == 0 ? 2.0 * unit : 0.0, round == 0 ? nullptr : &cost))
+        break;
+      double ms = 0.0;
+      std::vector<double> inst_us;
+      if ((rc = time_krotov(b, &ms, &inst_us))) return rc;
+      if (ms < kbest) {
+        kbest = ms;
+        kw = wpb;
+        kblocks = b->plan.nblocks;
+      }
+      // measured time of one trajectory-step (with its share of the exchange)
+      cost.assign(b->mem.size(), 0.0);
+      for (size_t i = 0; i < b->mem.size(); ++i) {
+        const Member &m = *b->mem[i];
+        const double tw = std::ceil(static_cast<double>(m.M) / (b->plan.nblocks[i] * wpb));
+        cost[i] = inst_us[i] / (m.c->nt * tw);
+      }
     }
+  }
   if (!kw) return bfail(b, TK_EUNSUPPORTED, "no batched Krotov shape fits");
-  if ((rc = plan_krotov(b, kw, frac, ks))) return rc;
+  if ((rc = plan_krotov(b, kw, 1.0, 0.0))) return rc;  // sets wpb and LDS
+  b->plan.nblocks = kblocks;
+  if ((rc = upload_tables(b))) return rc;
   b->tuned_krotov_ms = kbest;
   b->tuned = true;
   return TK_OK;

@@ -131,6 +131,8 @@ struct BatchArgs {
   const int *block_inst; // [blocks] instance of each block of the Krotov launch
   uint64_t *iteration;   // iteration of the passes being run (device counter)
   double *J_hist;        // [n_inst][kBatchHistory] J_T by iteration
+  unsigned long long *t_begin;  // earliest block start of the Krotov launch (constant clock)
+  unsigned long long *t_end;    // [n_inst] latest block end of each instance
   int *err;
   long long spin_limit;
 };
