@@ -529,6 +529,7 @@ int tk_batch_add(tk_batch *b, uint32_t instance_id, int64_t d, const tk_csr *H0,
   auto m = std::make_unique<Member>();
   int rc = tk_create(&m->c, b->device, b->precision);
   if (rc) return bfail(b, rc, "context creation failed");
+  m->c->single_wave_only = true;  // the batched kernels run one-wave shapes
   if ((rc = tk_set_system(m->c, d, H0, n_ctrl, H_ctrl, n_jump, L_jump)) ||
       (rc = tk_set_states(m->c, psi0, psi_tgt)) ||
       (rc = tk_set_pulses(m->c, nt, T, u, S, lambda)))

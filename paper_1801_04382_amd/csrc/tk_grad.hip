@@ -435,11 +435,13 @@ const void *grad_kernel(int precision, int R, int WS, int NC, int G) {
   TK_GRAD_CASE(double, 4, 6, 3, 1)
   TK_GRAD_CASE(double, 4, 8, 4, 1)
   TK_GRAD_CASE(double, 1, 4, 2, 2)
+  TK_GRAD_CASE(double, 2, 6, 3, 2)
   TK_GRAD_CASE(float, 1, 4, 2, 1)
   TK_GRAD_CASE(float, 2, 4, 2, 1)
   TK_GRAD_CASE(float, 4, 6, 3, 1)
   TK_GRAD_CASE(float, 4, 8, 4, 1)
   TK_GRAD_CASE(float, 1, 4, 2, 2)
+  TK_GRAD_CASE(float, 2, 6, 3, 2)
   TK_GRAD_CASE(float, 3, 9, 4, 8)
 #undef TK_GRAD_CASE
   return nullptr;

@@ -873,17 +873,22 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
     wld = std::max(wld, ljd[l].max_row());
   }
   const int nc = n_ctrl * wc;
-  // the compiled variant with the fewest rows 64 G R >= d (then one-wave teams,
-  // then the narrowest slots); TK_VARIANT=<name> picks one by name instead
+  // the compiled variant with the fewest rows 64 G R >= d; among those, FP64
+  // shapes with 4 rows per lane come last (they spill registers), then one-wave
+  // teams, then the narrowest slots.  Batch members take one-wave shapes only.
+  // TK_VARIANT=<name> picks one by name instead.
   const char *want = std::getenv("TK_VARIANT");
   int nv = 0;
   const tk::Variant *vs = tk::variants(&nv);
   const tk::Variant *best = nullptr;
-  auto key = [](const tk::Variant &v) { return std::make_tuple(v.R * v.G, v.G, v.WS, v.NC); };
+  auto key = [](const tk::Variant &v) {
+    const int spills = v.precision == TK_FP64 && v.R >= 4 ? 1 : 0;
+    return std::make_tuple(v.R * v.G, spills, v.G, v.WS, v.NC);
+  };
   for (int k = 0; k < nv; ++k) {
     const tk::Variant &v = vs[k];
     if (v.precision != c->precision || static_cast<int64_t>(v.R) * tk::kWave * v.G < d ||
-        v.WS < ws || v.NC < nc)
+        v.WS < ws || v.NC < nc || (c->single_wave_only && v.G != 1))
       continue;
     if (want && *want) {
       if (std::strcmp(want, v.name) == 0) best = &v;

@@ -349,11 +349,13 @@ const Variant *variants(int *count) {
       make_variant<double, 4, 6, 3, 1>("fp64 R=4 WS=6 NC=3"),
       make_variant<double, 4, 8, 4, 1>("fp64 R=4 WS=8 NC=4"),
       make_variant<double, 1, 4, 2, 2>("fp64 R=1 WS=4 NC=2 G=2"),
+      make_variant<double, 2, 6, 3, 2>("fp64 R=2 WS=6 NC=3 G=2"),
       make_variant<float, 1, 4, 2, 1>("fp32 R=1 WS=4 NC=2"),
       make_variant<float, 2, 4, 2, 1>("fp32 R=2 WS=4 NC=2"),
       make_variant<float, 4, 6, 3, 1>("fp32 R=4 WS=6 NC=3"),
       make_variant<float, 4, 8, 4, 1>("fp32 R=4 WS=8 NC=4"),
       make_variant<float, 1, 4, 2, 2>("fp32 R=1 WS=4 NC=2 G=2"),
+      make_variant<float, 2, 6, 3, 2>("fp32 R=2 WS=6 NC=3 G=2"),
       make_variant<float, 3, 9, 4, 8>("fp32 R=3 WS=9 NC=4 G=8"),
   };
   *count = static_cast<int>(sizeof(table) / sizeof(table[0]));

@@ -89,3 +89,30 @@ def test_chain_of_four_nodes_fp32(tk):
     assert max_abs(J, ref.J_T) <= 1e-4
     assert abs(Jg - J_ref) <= 1e-5
     assert max_abs(g, g_ref) <= 1e-4 * np.max(np.abs(g_ref))
+
+
+def test_two_wave_shape_selected_for_d216_fp64(tk):
+    """d = 216 in FP64 selects the 2-wave, 2-rows-per-lane shape (the 4-rows
+    one spills registers): records, a Krotov iteration and the gradient against
+    the oracle at the FP64 bars."""
+    w = config_workload("chain3_fock2", M=2, nt=16, seed=2)
+    say("d=216 fp64", "M", w.M, "nt", w.nt)
+    sysd = oracle_system(w)
+    ref = okrotov.optimise(sysd, w.psi0, w.psi_tgt, w.u0, w.S, w.lam, w.T, w.M, w.seed, 1)
+    fw = ref.passes[0]
+    paths = paths_from_records(fw.records, w.M)
+    g_ref = gradient_adjoint(sysd, w.psi0, w.psi_tgt, w.u0, w.T, paths)
+    with tk.Context(precision="fp64") as ctx:
+        ctx.load(w)
+        assert ctx.launch_info()["variant"] == "fp64 R=2 WS=6 NC=3 G=2"
+        psiT, tau, rec, n = ctx.propagate_forward(w.M, w.seed, 0)
+        compare_records(gpu_records(rec), oracle_records(fw.records, 0), T_TOL)
+        assert max_abs(psiT, fw.psi_hat_T) <= TOL
+        _, _, g = ctx.grad_pathwise(w.M, to_tk_records(tk, fw.records))
+        ctx.load(w)
+        J, _, _ = ctx.krotov_iterate(w.M, w.seed, 1)
+        u = ctx.get_pulses()
+    say("  J gpu", J.tolist(), "oracle", ref.J_T, "records", n)
+    assert max_abs(J, ref.J_T) <= TOL
+    assert max_abs(u, ref.u[-1]) <= TOL
+    assert max_abs(g, g_ref) <= 1e-9 * max(np.max(np.abs(g_ref)), 1e-12)
