@@ -226,6 +226,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     uo[i] = a.u_old[static_cast<size_t>(i) * a.nt];
     sf[i] = a.S[static_cast<size_t>(i) * a.nt] * inv_lm[i];
   }
+  int khint = 1;  // order of the previous step (where the order search starts)
   for (int j = 0; j < a.nt; ++j) {
     __syncthreads();  // every wave has used the previous step's s_upd
     if (wib == 0) {
@@ -260,7 +261,8 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
       }
     }
     op.set_pulses(uj, a.wc);
-    const StepPlan p = plan_step(a, uj);
+    const StepPlan p = plan_step(a, uj, khint);
+    khint = p.K;
     // the wave's trajectories in turn; the state, clock and costate of the next
     // one are loaded while the current one advances
     cx<real> psi[R], ch[R];

@@ -67,6 +67,16 @@ __device__ __forceinline__ void wave_sum2(double &x, double &y) {
 // The lanes that advance one trajectory together: G wavefronts (G = 1: one
 // wavefront; G > 1: the G waves of a block, which then holds just this team).
 // Row r of a state belongs to team lane r mod 64G as its slot m = r / 64G.
+// Workgroup barrier that orders LDS traffic only: it waits for the wave's own
+// LDS operations, not for its global loads and stores still in flight (which
+// __syncthreads' release fence would wait for).  Every exchange between the
+// waves of a block in these kernels goes through LDS.
+__device__ __forceinline__ void block_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // sync() orders LDS traffic among the team; sum() is the team-wide FP64 sum
 // in a fixed order (each wave's DPP tree, then the waves in index order, via a
 // double-buffered LDS array), so every lane of the team holds the same bits.
@@ -82,14 +92,14 @@ struct Team {
     if (G == 1)
       wave_sync();
     else
-      __syncthreads();
+      block_sync_lds();
   }
   __device__ __forceinline__ double sum(double x) const {
     x = wave_sum(x);
     if (G == 1) return x;
     double *r = red + par * 2 * G;
     if (lane == 0) r[g] = x;
-    __syncthreads();
+    block_sync_lds();
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < G; ++q) s += r[q];
@@ -105,7 +115,7 @@ struct Team {
       r[g] = x;
       r[G + g] = y;
     }
-    __syncthreads();
+    block_sync_lds();
     double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -160,11 +170,23 @@ __device__ __forceinline__ double to_unit(uint64_t w) {
   return static_cast<double>(w >> 11) * 0x1.0p-53;
 }
 
+// A wave-uniform 64-bit value moved to scalar registers, so that arithmetic
+// on it runs on the scalar unit (Philox's 64-bit products are far cheaper
+// there than as quarter-rate vector multiplies).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Counter-based stream of one trajectory.  Every argument is uniform across
+// the team that advances the trajectory.
 struct Stream {
   uint64_t k0, k1, iteration, direction;
   __device__ void block(uint64_t ordinal, double &thr, double &choice) const {
     uint64_t w0, w1;
-    philox4x64(ordinal, iteration, direction, 0, k0, k1, w0, w1);
+    philox4x64(uniform64(ordinal), uniform64(iteration), uniform64(direction), 0, uniform64(k0),
+               uniform64(k1), w0, w1);
     thr = to_unit(w0);
     choice = to_unit(w1);
   }
@@ -328,15 +350,15 @@ struct Terms {
   __device__ cx<real> *operator[](int n) const { return base + n * kLen; }
 };
 
-// Smallest K with x^(K+1)/(K+1)! e^x <= tol (Taylor remainder bound), or -1.
-__device__ inline int taylor_order(double x, double tol, int kmax) {
-  const double ex = exp(x);
-  double t = x;
-  for (int K = 1; K <= kmax; ++K) {
-    t *= x / static_cast<double>(K + 1);
-    if (t * ex <= tol) return K;
-  }
-  return -1;
+// Smallest order K whose remainder bound x^(K+1)/(K+1)! e^x meets the step
+// tolerance, read from the launch's threshold table (x <= ord_x[K]), or -1
+// when kmax does not suffice.  The search starts at `hint` (the previous
+// step's order), so a step costs one or two comparisons.
+__device__ __forceinline__ int taylor_order(const PassArgs &a, double x, int hint) {
+  int K = hint < 1 ? 1 : (hint > a.kmax ? a.kmax : hint);
+  while (K < a.kmax && x > a.ord_x[K]) ++K;
+  while (K > 1 && x <= a.ord_x[K - 1]) --K;
+  return x <= a.ord_x[K] ? K : -1;
 }
 
 // out = sum_{n=0..K} t_n with t_n = (s i tau Op)^n / n! in, s = -1 (forward)
@@ -445,14 +467,29 @@ __device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const Pass
   for (int m = 0; m < R; ++m) out[m] = cx<real>{in[m].x + inc[m].x, in[m].y + inc[m].y};
 }
 
-// p(s) = sum_n s^n t_n and dp/ds from the stored terms (own rows only; Horner)
+// p(s) = sum_n s^n t_n and dp/ds from the stored terms (own rows only;
+// Horner from t_K down).  The terms are read four at a time, so one LDS
+// round trip serves four Horner steps.
 template <typename real, int R, int G>
 __device__ __forceinline__ void dense_output(const Terms<real, R, G> &T, int K, real s,
                                              cx<real> (&p)[R], cx<real> (&dp)[R], const Team<G> &tm) {
   load_lds(T[K], p, tm);
 #pragma unroll
   for (int m = 0; m < R; ++m) dp[m] = cx<real>{0, 0};
-  for (int n = K - 1; n >= 0; --n) {
+  int n = K - 1;
+  for (; n >= 3; n -= 4) {
+    cx<real> tq[4][R];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) load_lds(T[n - q], tq[q], tm);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        dp[m] = cx<real>{fma(dp[m].x, s, p[m].x), fma(dp[m].y, s, p[m].y)};
+        p[m] = cx<real>{fma(p[m].x, s, tq[q][m].x), fma(p[m].y, s, tq[q][m].y)};
+      }
+  }
+  for (; n >= 0; --n) {
     cx<real> tn[R];
     load_lds(T[n], tn, tm);
 #pragma unroll
@@ -522,6 +559,10 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
       st.r = 0.0;
       return;
     }
+    // the record's slot is claimed now; the atomic's round trip overlaps the
+    // root search
+    unsigned long long slot = 0;
+    if (tm.leader()) slot = atomicAdd(a.rec_count, 1ull);
     // ---- jump time: root of f(s) = ||p(s)||^2 - r for s in (0, 1] (tau = s tau_rem) ----
     {  // the series again, now keeping every term for the dense output
       cx<real> again[R];
@@ -603,7 +644,10 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
       }
     }
     if (lsel < 0) {
-      if (tm.leader()) atomicOr(a.err, kErrNoJumpWeight);
+      if (tm.leader()) {
+        atomicOr(a.err, kErrNoJumpWeight);
+        if (static_cast<long long>(slot) < a.rec_cap) a.rec[slot].op = -1;  // no jump took place
+      }
 #pragma unroll
       for (int m = 0; m < R; ++m) psi[m] = pt[m];
       st.nrm2 = norm2(pt, tm);
@@ -617,7 +661,6 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     for (int m = 0; m < R; ++m) ps[m] = cx<real>{y[m].x * inv, y[m].y * inv};
     const double elapsed = (h - tau_rem) + tau;
     if (tm.leader()) {
-      const unsigned long long slot = atomicAdd(a.rec_count, 1ull);
       if (static_cast<long long>(slot) < a.rec_cap) {
         tk_jump r;
         r.instance = static_cast<int32_t>(a.instance);
@@ -636,7 +679,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     st.r = rng.threshold(static_cast<uint64_t>(st.ordinal));
     n_s = norm2(ps, tm);
     tau_rem = tau_rem - tau;
-    const int Kr = taylor_order(bnd * tau_rem, a.tol, a.kmax);
+    const int Kr = taylor_order(a, bnd * tau_rem, Kc);
     if (Kr >= 1 && Kr < Kc) Kc = Kr;
   }
 }
@@ -650,9 +693,9 @@ struct StepPlan {
 
 // Substeps and polynomial order of step j from the norm bound of its H_eff:
 // enough substeps that ||H_eff|| h <= kMaxStepNorm and that the order fits the
-// kbuf - 1 term vectors in LDS.
+// kbuf - 1 term vectors in LDS.  `hint` is the previous step's order.
 template <int N>
-__device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&uj)[N]) {
+__device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&uj)[N], int hint) {
   double b = a.b0;
 #pragma unroll
   for (int i = 0; i < N; ++i) b += fabs(uj[i]) * a.bc[i];
@@ -661,16 +704,16 @@ __device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&
   p.bnd = b;
   const int kfit = a.kbuf - 1;  // largest order whose terms fit the LDS
   p.n_sub = x > kMaxStepNorm ? static_cast<int>(ceil(x / kMaxStepNorm)) : 1;
-  p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
+  p.K = taylor_order(a, p.n_sub == 1 ? x : x / static_cast<double>(p.n_sub), hint);
   while ((p.K < 0 || p.K > kfit) && p.n_sub < kMaxSubsteps) {
     p.n_sub += 1;
-    p.K = taylor_order(x / static_cast<double>(p.n_sub), a.tol, a.kmax);
+    p.K = taylor_order(a, x / static_cast<double>(p.n_sub), kfit);
   }
   if (p.K < 0 || p.K > kfit) {
     atomicOr(a.err, kErrTaylorOrder);
     p.K = kfit;
   }
-  p.h = a.dt / static_cast<double>(p.n_sub);
+  p.h = p.n_sub == 1 ? a.dt : a.dt / static_cast<double>(p.n_sub);
   return p;
 }
 
@@ -751,6 +794,7 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
 #pragma unroll
     for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + j0];
   }
+  int khint = 1;
   for (int jj = 0; jj < a.nt; ++jj) {
     const int j = DIR == 0 ? jj : a.nt - 1 - jj;
     double uj[NCX];
@@ -762,7 +806,8 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
       for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + jn];
     }
     op.set_pulses(uj, a.wc);
-    const StepPlan p = plan_step(a, uj);
+    const StepPlan p = plan_step(a, uj, khint);
+    khint = p.K;
     advance_step<real, R, WS, NC, G, DIR>(op, a, T, psi, st, rng, j, p, k, tm);
     if (DIR == 1) {
       // chi_k(t_j) = tau_k chi_hat_k(t_j)
@@ -825,6 +870,9 @@ __device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC, G> &o
   }
 }
 
+// chi_k(t_j), own rows.  Padding rows (row >= d) read row d - 1 instead of a
+// zero: they only ever multiply (H_i psi) rows that are exactly zero, and an
+// unconditional load needs no wait for the previous step's loads into ch.
 template <typename real, int R, int G>
 __device__ __forceinline__ void load_costate(const PassArgs &a, int j, int k, const Team<G> &tm,
                                              cx<real> (&ch)[R]) {
@@ -833,7 +881,7 @@ __device__ __forceinline__ void load_costate(const PassArgs &a, int j, int k, co
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int row = tm.gl + Team<G>::kLanes * m;
-    ch[m] = row < a.d ? chi[base + row] : cx<real>{0, 0};
+    ch[m] = chi[base + (row < a.d ? row : a.d - 1)];
   }
 }
 

@@ -332,18 +332,47 @@ int upload_vec(tk_ctx *c, DevBuf &buf, const std::vector<double> &v) {
   return upload(c, buf, f.data(), f.size() * sizeof(float));
 }
 
-// Taylor order of one step (same rule as the kernels).
-int taylor_order_host(double x, double tol, int kmax) {
-  const double ex = std::exp(x);
+// Remainder bound of the order-K Taylor polynomial of exp over ||A|| tau = x:
+// x^(K+1)/(K+1)! e^x.
+double remainder_bound(double x, int K) {
   double t = x;
-  for (int K = 1; K <= kmax; ++K) {
-    t *= x / static_cast<double>(K + 1);
-    if (t * ex <= tol) return K;
-  }
-  return kmax;
+  for (int n = 1; n <= K; ++n) t *= x / static_cast<double>(n + 1);
+  return t * std::exp(x);
 }
 
-double step_tol(const tk_ctx *c) { return c->precision == TK_FP64 ? 1e-16 : 6e-8; }
+// ord_x[K] = the largest x whose order-K remainder bound is within tol (by
+// bisection, keeping the side that meets it), made non-decreasing in K from
+// above so that every entry stays a sufficient condition.
+struct OrderTable {
+  double x[tk::kMaxTaylor + 1];
+  explicit OrderTable(double tol) {
+    x[0] = 0.0;
+    for (int K = 1; K <= tk::kMaxTaylor; ++K) {
+      double lo = 0.0, hi = 1.0;
+      while (remainder_bound(hi, K) <= tol) hi *= 2.0;
+      for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        (remainder_bound(mid, K) <= tol ? lo : hi) = mid;
+      }
+      x[K] = lo;
+    }
+    for (int K = tk::kMaxTaylor - 1; K >= 1; --K) x[K] = std::min(x[K], x[K + 1]);
+  }
+};
+
+const double *order_table(int precision) {
+  static const OrderTable t64(1e-16), t32(6e-8);
+  return precision == TK_FP64 ? t64.x : t32.x;
+}
+
+// Taylor order of one step (the kernels' rule): the smallest K with
+// x <= ord_x[K], else kmax.
+int taylor_order_host(double x, const double *ord_x, int kmax) {
+  for (int K = 1; K <= kmax; ++K)
+    if (x <= ord_x[K]) return K;
+  return kmax;
+}
 
 // Substeps and Taylor order of step j for pulses u (the kernels' rule without
 // the term-buffer limit).
@@ -353,7 +382,7 @@ void plan_step_host(const tk_ctx *c, const std::vector<double> &u, int j, int *n
     b += std::fabs(u[static_cast<size_t>(i) * c->nt + j]) * c->bc[i];
   const double x = b * (c->T / c->nt);
   *n_sub = x > tk::kMaxStepNorm ? static_cast<int>(std::ceil(x / tk::kMaxStepNorm)) : 1;
-  *K = taylor_order_host(x / *n_sub, step_tol(c), tk::kMaxTaylor);
+  *K = taylor_order_host(x / *n_sub, order_table(c->precision), tk::kMaxTaylor);
 }
 
 }  // namespace
@@ -420,6 +449,7 @@ tk::PassArgs base_args(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, bool
   for (int i = 0; i < tk::kMaxCtrl; ++i) a.bc[i] = c->bc[i];
   a.inv_n[0] = 0.0;
   for (int n = 1; n <= tk::kMaxTaylor; ++n) a.inv_n[n] = 1.0 / n;
+  std::memcpy(a.ord_x, order_table(c->precision), sizeof(a.ord_x));
   if (!backward) {
     a.scol = c->f_scol.as<int>();
     a.sval = c->f_sval.p;

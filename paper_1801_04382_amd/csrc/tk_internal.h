@@ -58,6 +58,9 @@ struct PassArgs {
   double bc[kMaxCtrl];  // bounds on ||H_i||_2
   double ftol;  // relative tolerance of the jump-time root
   double inv_n[kMaxTaylor + 1];  // 1/n for the Taylor recursion (entry 0 unused)
+  // ord_x[K]: the largest x = ||H_eff|| tau for which order K keeps the remainder
+  // bound x^(K+1)/(K+1)! e^x within tol; non-decreasing in K (entry 0 unused)
+  double ord_x[kMaxTaylor + 1];
   // operator used by the pass: H_eff pieces (forward) or their adjoints
   const int *scol;
   const void *sval;

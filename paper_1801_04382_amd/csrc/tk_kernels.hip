@@ -91,6 +91,27 @@ __device__ __forceinline__ void poll_slots(const unsigned long long *row, int la
                                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// True when every slot of a batch holds a partial; then acc = their sum per
+// lane (in the batch's fixed order).
+template <int NCX>
+__device__ __forceinline__ bool slots_complete(const unsigned long long (&bits)[kPollPerLane][NCX],
+                                               double (&acc)[NCX]) {
+  int missing = 0;
+#pragma unroll
+  for (int q = 0; q < kPollPerLane; ++q)
+#pragma unroll
+    for (int c = 0; c < NCX; ++c) missing |= bits[q][c] == kSlotEmpty;
+  if (__any(missing)) return false;
+#pragma unroll
+  for (int c = 0; c < NCX; ++c) {
+    acc[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPollPerLane; ++q)
+      acc[c] += __longlong_as_double(static_cast<long long>(bits[q][c]));
+  }
+  return true;
+}
+
 // ---- sequential Krotov forward pass (cooperative launch) ---------------------
 template <typename real, int R, int WS, int NC, int G>
 __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_krotov(
@@ -122,6 +143,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   cx<real> *v = T[0];  // scratch vector for the update's gathers
   const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
   if (threadIdx.x == 0) s_abort = 0;
+  if (threadIdx.x < NCX) s_upd[threadIdx.x] = 0.0;  // stays zero without controls
 
   // ---- start states and the first partial (t_0) ----
   double pc[NCX];
@@ -152,24 +174,29 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
     }
   }
 
-  // pulse inputs of the step about to be updated (j = 0); rows past n_ctrl are
-  // zero padding (lambda padded with 1), so no guards are needed
-  double uo[NCX], sf[NCX], inv_lm[NCX];
+  // rows past n_ctrl of the pulse inputs are zero padding (lambda padded with
+  // 1), so no guards are needed
+  double inv_lm[NCX];
 #pragma unroll
-  for (int i = 0; i < NCX; ++i) {
-    inv_lm[i] = 1.0 / (a.lam[i] * a.M);
-    uo[i] = a.u_old[static_cast<size_t>(i) * a.nt];
-    sf[i] = a.S[static_cast<size_t>(i) * a.nt] * inv_lm[i];
-  }
-
+  for (int i = 0; i < NCX; ++i) inv_lm[i] = 1.0 / (a.lam[i] * a.M);
+  double u_prev[NCX];  // block 0: the previous step's new pulse, stored with the next publish
+  int khint = 1;       // order of the previous step (where the order search starts)
   for (int j = 0; j < a.nt; ++j) {
+    // pulse inputs of interval j, loaded now and used after the exchange
+    double uo[NCX], so[NCX];
+#pragma unroll
+    for (int i = 0; i < NCX; ++i) {
+      const size_t ij = static_cast<size_t>(i) * a.nt + j;
+      uo[i] = a.u_old[ij];
+      so[i] = a.S[ij];
+    }
     // ---- reduce the partial of t_j: waves -> block (fixed order) -> publish ----
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double s = tm.sum(pc[c]);
       if (tm.leader()) wpart[team][c] = s;
     }
-    __syncthreads();
+    block_sync_lds();
     if (threadIdx.x < NCX) {  // control i's block partial (zero for padding controls)
       const int i = threadIdx.x;
       double s = 0.0;
@@ -177,39 +204,25 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
         for (int c = i * a.wc; c < (i + 1) * a.wc && c < NC; ++c) s += wpart[w][c];
       __hip_atomic_store(&a.slots[(static_cast<size_t>(j) * kMaxBlocks + blockIdx.x) * NCX + i],
                          __double_as_longlong(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // the new pulse of interval j - 1 leaves with this step's publish, so no
+      // wave waits for its write on its own
+      if (blockIdx.x == 0 && j > 0) a.u_new[static_cast<size_t>(i) * a.nt + j - 1] = u_prev[i];
     }
     // ---- wait for every block's partial of step j; sum in block order --------
     if (wib == 0 && a.n_ctrl > 0) {
       // every lane reads kPollPerLane blocks' slots in one batch of loads (slots of
-      // blocks past the grid hold zero, so the sum over all kMaxBlocks is exact);
-      // the next batch is issued before the current one is checked, so two polls
-      // are always in flight
+      // blocks past the grid hold zero, so the sum over all kMaxBlocks is exact).
+      // One batch is in flight at a time: when the loop ends no load is left
+      // outstanding for later code to wait for.
       const unsigned long long *row = a.slots + static_cast<size_t>(j) * kMaxBlocks * NCX;
       double acc[NCX];
-      unsigned long long cur[kPollPerLane][NCX], nxt[kPollPerLane][NCX];
-      poll_slots<NCX>(row, lane, cur);
       long long spins = 0;
       bool abort = false;
       for (;;) {
-        poll_slots<NCX>(row, lane, nxt);
-        __builtin_amdgcn_sched_barrier(0);
-        int missing = 0;
-#pragma unroll
-        for (int q = 0; q < kPollPerLane; ++q)
-#pragma unroll
-          for (int c = 0; c < NCX; ++c) missing |= cur[q][c] == kSlotEmpty;
-        if (!__any(missing)) {
-#pragma unroll
-          for (int c = 0; c < NCX; ++c) {
-            acc[c] = 0.0;
-#pragma unroll
-            for (int q = 0; q < kPollPerLane; ++q)
-              acc[c] += __longlong_as_double(static_cast<long long>(cur[q][c]));
-          }
-          break;
-        }
-        // another block's abort is looked for only now and then: the flag load
-        // waits for the poll in flight
+        unsigned long long bits[kPollPerLane][NCX];
+        poll_slots<NCX>(row, lane, bits);
+        if (slots_complete<NCX>(bits, acc)) break;
+        // another block's abort is looked for only now and then
         if (++spins > a.spin_limit ||
             ((spins & 255) == 0 &&
              (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
@@ -219,10 +232,6 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
           abort = true;
           break;
         }
-#pragma unroll
-        for (int q = 0; q < kPollPerLane; ++q)
-#pragma unroll
-          for (int c = 0; c < NCX; ++c) cur[q][c] = nxt[q][c];
       }
 #pragma unroll
       for (int c = 0; c < NCX; ++c) {
@@ -234,26 +243,19 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
         s_abort = 1;
       }
     }
-    __syncthreads();
+    block_sync_lds();
     if (s_abort) return;  // uniform across the block
     // ---- pulse update of interval j ---------------------------------------------
     double uj[NCX];
 #pragma unroll
-    for (int i = 0; i < NCX; ++i) uj[i] = uo[i] + sf[i] * s_upd[i];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-#pragma unroll
-      for (int i = 0; i < NCX; ++i) a.u_new[static_cast<size_t>(i) * a.nt + j] = uj[i];
-    }
-    if (j + 1 < a.nt) {  // prefetch the next step's pulse inputs
-#pragma unroll
-      for (int i = 0; i < NCX; ++i) {
-        const size_t ij = static_cast<size_t>(i) * a.nt + j + 1;
-        uo[i] = a.u_old[ij];
-        sf[i] = a.S[ij] * inv_lm[i];
-      }
+    for (int i = 0; i < NCX; ++i) {
+      const double sf = so[i] * inv_lm[i];
+      uj[i] = uo[i] + sf * s_upd[i];
+      u_prev[i] = uj[i];
     }
     op.set_pulses(uj, a.wc);
-    const StepPlan p = plan_step(a, uj);
+    const StepPlan p = plan_step(a, uj, khint);
+    khint = p.K;
     // ---- advance every trajectory; form the partial of t_{j+1} ----------------
 #pragma unroll
     for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
@@ -279,6 +281,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       tm.sync();
     }
   }
+  if (blockIdx.x == 0 && threadIdx.x < NCX) a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + a.nt - 1] = u_prev[threadIdx.x];
   // ---- functional: tau_k = <tgt|psi_hat_k(T)> and the final states ----------
   cx<real> *psiT = static_cast<cx<real> *>(a.psiT);
   for (int t = 0; t < Tw; ++t) {
