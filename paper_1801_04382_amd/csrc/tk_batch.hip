@@ -226,7 +226,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     uo[i] = a.u_old[static_cast<size_t>(i) * a.nt];
     sf[i] = a.S[static_cast<size_t>(i) * a.nt] * inv_lm[i];
   }
-  int khint = 1;  // order of the previous step (where the order search starts)
+  OrderHint khint;  // the previous step's order
   for (int j = 0; j < a.nt; ++j) {
     __syncthreads();  // every wave has used the previous step's s_upd
     if (wib == 0) {
@@ -262,7 +262,6 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     }
     op.set_pulses(uj, a.wc);
     const StepPlan p = plan_step(a, uj, khint);
-    khint = p.K;
     // the wave's trajectories in turn; the state, clock and costate of the next
     // one are loaded while the current one advances
     cx<real> psi[R], ch[R];
@@ -285,7 +284,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
         if (j + 1 < a.nt) load_costate<real, R, 1>(a, j + 1, kn, tm, ch_n);
       }
       const Stream rng = make_stream(a, k, 0, it);
-      advance_step<real, R, WS, NC, 1, 0>(op, a, T, psi, st, rng, j, p, k, tm);
+      advance_step<real, R, WS, NC, 1, 0, true>(op, a, T, psi, st, rng, j, p, k, tm);
 #pragma unroll
       for (int m = 0; m < R; ++m) psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m] = psi[m];
       if (lane == 0) meta_g[k] = st;

@@ -281,8 +281,13 @@ struct LaneOp {
   __device__ void set_pulses(const double (&uj)[NCX], int wc) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int i = c / wc;  // < NC, hence a valid index
-      const real ui = static_cast<real>(uj[i]);
+      // control c / wc (< NC, hence a valid index), by comparisons: the slot
+      // count is small and a division would cost more
+      double u = uj[0];
+#pragma unroll
+      for (int i = 1; i < NC; ++i)
+        if (c >= i * wc) u = uj[i];
+      const real ui = static_cast<real>(u);
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         const cx<real> q = cval_at(c, m);
@@ -352,14 +357,32 @@ struct Terms {
 
 // Smallest order K whose remainder bound x^(K+1)/(K+1)! e^x meets the step
 // tolerance, read from the launch's threshold table (x <= ord_x[K]), or -1
-// when kmax does not suffice.  The search starts at `hint` (the previous
-// step's order), so a step costs one or two comparisons.
+// when kmax does not suffice.  The search starts at `hint` (a nearby order),
+// so it costs one or two comparisons.
 __device__ __forceinline__ int taylor_order(const PassArgs &a, double x, int hint) {
   int K = hint < 1 ? 1 : (hint > a.kmax ? a.kmax : hint);
   while (K < a.kmax && x > a.ord_x[K]) ++K;
   while (K > 1 && x <= a.ord_x[K - 1]) --K;
   return x <= a.ord_x[K] ? K : -1;
 }
+
+// The order found for the previous step with its interval ord_x[K-1] < x <=
+// ord_x[K]: a step whose x falls in it (the usual case, pulses being smooth)
+// needs no table read.  Starts empty.
+struct OrderHint {
+  int K = 1;
+  double lo = 1.0, hi = 0.0;
+  __device__ __forceinline__ int order(const PassArgs &a, double x) {
+    if (x > lo && x <= hi) return K;
+    const int k = taylor_order(a, x, K);
+    if (k > 0) {
+      K = k;
+      lo = k > 1 ? a.ord_x[k - 1] : -1.0;
+      hi = a.ord_x[k];
+    }
+    return k;
+  }
+};
 
 // out = sum_{n=0..K} t_n with t_n = (s i tau Op)^n / n! in, s = -1 (forward)
 // or +1 (backward); t_n is also left in T[n] for dense output.  The small
@@ -398,18 +421,21 @@ __device__ void taylor(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
 
 // One term of the series from the term vector at the bound gather addresses
 // plus OFF elements: t = (s i tau / n) Op t_prev for the lane's rows.
+// `shift` (elements, uniform) moves every gather to a later term vector; a
+// run of terms with the same shift shares its address arithmetic.
 template <typename real, int R, int WS, int NC, int G, int SGN, int OFF>
 __device__ __forceinline__ void series_term(const LaneOp<real, R, WS, NC, G> &op, real cf,
-                                            cx<real> (&t)[R], cx<real> (&inc)[R]) {
+                                            cx<real> (&t)[R], cx<real> (&inc)[R],
+                                            int shift = 0) {
   cx<real> b[WS + NC][R];
 #pragma unroll
   for (int s = 0; s < WS; ++s)
 #pragma unroll
-    for (int m = 0; m < R; ++m) b[s][m] = op.sp[s][m][OFF];
+    for (int m = 0; m < R; ++m) b[s][m] = (op.sp[s][m] + shift)[OFF];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int m = 0; m < R; ++m) b[WS + c][m] = op.cp[c][m][OFF];
+    for (int m = 0; m < R; ++m) b[WS + c][m] = (op.cp[c][m] + shift)[OFF];
   __builtin_amdgcn_sched_barrier(0);
   cx<real> y[R];
 #pragma unroll
@@ -462,6 +488,54 @@ __device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const Pass
                                                 inc);
 #pragma unroll
     for (int m = 0; m < R; ++m) own[kL * m] = t[m];
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) out[m] = cx<real>{in[m].x + inc[m].x, in[m].y + inc[m].y};
+}
+
+// The series keeping every term t_n in T[n] (as taylor() does) at nearly the
+// cost of the ping-pong form: terms go in runs of four, each run reading its
+// gathers at the bound addresses moved once by the run's first vector plus
+// constant offsets of 0 .. 3 vector lengths.
+template <typename real, int R, int WS, int NC, int G, int SGN>
+__device__ void taylor_keep(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                            const Terms<real, R, G> &T, const cx<real> (&in)[R],
+                            cx<real> (&out)[R], double tau, int K, const Team<G> &tm) {
+  constexpr int kLen = Terms<real, R, G>::kLen;
+  constexpr int kL = Team<G>::kLanes;
+  cx<real> t[R], inc[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    t[m] = in[m];
+    inc[m] = cx<real>{0, 0};
+    T.base[tm.gl + kL * m] = t[m];
+  }
+  for (int n0 = 0; n0 < K; n0 += 4) {  // terms n0 + 1 .. n0 + 4 from T[n0 .. n0 + 3]
+    const int shift = n0 * kLen;
+    cx<real> *own = T.base + shift + tm.gl;
+    tm.sync();
+    series_term<real, R, WS, NC, G, SGN, 0>(op, static_cast<real>(tau * a.inv_n[n0 + 1]), t, inc,
+                                            shift);
+#pragma unroll
+    for (int m = 0; m < R; ++m) own[kLen + kL * m] = t[m];
+    if (n0 + 2 > K) break;
+    tm.sync();
+    series_term<real, R, WS, NC, G, SGN, kLen>(op, static_cast<real>(tau * a.inv_n[n0 + 2]), t,
+                                               inc, shift);
+#pragma unroll
+    for (int m = 0; m < R; ++m) own[2 * kLen + kL * m] = t[m];
+    if (n0 + 3 > K) break;
+    tm.sync();
+    series_term<real, R, WS, NC, G, SGN, 2 * kLen>(op, static_cast<real>(tau * a.inv_n[n0 + 3]),
+                                                   t, inc, shift);
+#pragma unroll
+    for (int m = 0; m < R; ++m) own[3 * kLen + kL * m] = t[m];
+    if (n0 + 4 > K) break;
+    tm.sync();
+    series_term<real, R, WS, NC, G, SGN, 3 * kLen>(op, static_cast<real>(tau * a.inv_n[n0 + 4]),
+                                                   t, inc, shift);
+#pragma unroll
+    for (int m = 0; m < R; ++m) own[4 * kLen + kL * m] = t[m];
   }
 #pragma unroll
   for (int m = 0; m < R; ++m) out[m] = cx<real>{in[m].x + inc[m].x, in[m].y + inc[m].y};
@@ -528,7 +602,12 @@ __device__ __forceinline__ void apply_jump(const PassArgs &a, int l, const cx<re
 // t0 + elapsed; DIR 1: backward, exp(+i H_eff^+ tau), times t0 - elapsed.
 // K is the order for the whole substep and bnd a bound on ||H_eff||; what is
 // left of a substep after a jump takes the (lower) order its length needs.
-template <typename real, int R, int WS, int NC, int G, int DIR>
+// KEEP: every series keeps its terms (taylor_keep) so that a step ending in a jump
+// goes straight to the root search; otherwise the series alternates two
+// vectors (taylor_pingpong, a little cheaper) and a step that ends in a jump
+// evaluates it again keeping the terms.  Passes whose step time is set by the
+// slowest trajectory (the sequential Krotov pass) keep the terms.
+template <typename real, int R, int WS, int NC, int G, int DIR, bool KEEP = false>
 __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                         const Terms<real, R, G> &T, cx<real> (&psi)[R], TrajMeta &st,
                         const Stream &rng, int j, double t0, double h, int K, double bnd, int k,
@@ -543,7 +622,10 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
   constexpr double eps_real = sizeof(real) == 8 ? 0x1.0p-52 : 0x1.0p-23;
   for (int guard = 0;; ++guard) {
     cx<real> out[R];
-    taylor_pingpong<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, Kc, tm);
+    if (KEEP)
+      taylor_keep<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, Kc, tm);
+    else
+      taylor_pingpong<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, Kc, tm);
     const double n_end = norm2(out, tm);
     if (!(n_end < st.r)) {
 #pragma unroll
@@ -564,12 +646,12 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     unsigned long long slot = 0;
     if (tm.leader()) slot = atomicAdd(a.rec_count, 1ull);
     // ---- jump time: root of f(s) = ||p(s)||^2 - r for s in (0, 1] (tau = s tau_rem) ----
-    {  // the series again, now keeping every term for the dense output
+    if (!KEEP) {  // the series again, now keeping every term for the dense output
       cx<real> again[R];
       tm.sync();
       taylor<real, R, WS, NC, G, SGN>(op, a, T, ps, again, tau_rem, Kc, tm);
-      tm.sync();
     }
+    tm.sync();
     double lo = 0.0, hi = 1.0;
     const double flo = n_s - st.r, fhi = n_end - st.r;
     double s = flo / (flo - fhi);
@@ -693,9 +775,10 @@ struct StepPlan {
 
 // Substeps and polynomial order of step j from the norm bound of its H_eff:
 // enough substeps that ||H_eff|| h <= kMaxStepNorm and that the order fits the
-// kbuf - 1 term vectors in LDS.  `hint` is the previous step's order.
+// kbuf - 1 term vectors in LDS.  `hint` carries the previous step's order.
 template <int N>
-__device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&uj)[N], int hint) {
+__device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&uj)[N],
+                                              OrderHint &hint) {
   double b = a.b0;
 #pragma unroll
   for (int i = 0; i < N; ++i) b += fabs(uj[i]) * a.bc[i];
@@ -704,7 +787,7 @@ __device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&
   p.bnd = b;
   const int kfit = a.kbuf - 1;  // largest order whose terms fit the LDS
   p.n_sub = x > kMaxStepNorm ? static_cast<int>(ceil(x / kMaxStepNorm)) : 1;
-  p.K = taylor_order(a, p.n_sub == 1 ? x : x / static_cast<double>(p.n_sub), hint);
+  p.K = hint.order(a, p.n_sub == 1 ? x : x / static_cast<double>(p.n_sub));
   while ((p.K < 0 || p.K > kfit) && p.n_sub < kMaxSubsteps) {
     p.n_sub += 1;
     p.K = taylor_order(a, x / static_cast<double>(p.n_sub), kfit);
@@ -718,7 +801,7 @@ __device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&
 }
 
 // Advance across the whole step j (its substeps).
-template <typename real, int R, int WS, int NC, int G, int DIR>
+template <typename real, int R, int WS, int NC, int G, int DIR, bool KEEP = false>
 __device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC, G> &op,
                                              const PassArgs &a, const Terms<real, R, G> &T,
                                              cx<real> (&psi)[R], TrajMeta &st,
@@ -727,7 +810,7 @@ __device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC, G> &o
   for (int s = 0; s < p.n_sub; ++s) {
     const double t0 = DIR == 0 ? static_cast<double>(j) * a.dt + s * p.h
                                : static_cast<double>(j + 1) * a.dt - s * p.h;
-    advance<real, R, WS, NC, G, DIR>(op, a, T, psi, st, rng, j, t0, p.h, p.K, p.bnd, k, tm);
+    advance<real, R, WS, NC, G, DIR, KEEP>(op, a, T, psi, st, rng, j, t0, p.h, p.K, p.bnd, k, tm);
   }
 }
 
@@ -794,7 +877,7 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
 #pragma unroll
     for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + j0];
   }
-  int khint = 1;
+  OrderHint khint;
   for (int jj = 0; jj < a.nt; ++jj) {
     const int j = DIR == 0 ? jj : a.nt - 1 - jj;
     double uj[NCX];
@@ -807,7 +890,6 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
     }
     op.set_pulses(uj, a.wc);
     const StepPlan p = plan_step(a, uj, khint);
-    khint = p.K;
     advance_step<real, R, WS, NC, G, DIR>(op, a, T, psi, st, rng, j, p, k, tm);
     if (DIR == 1) {
       // chi_k(t_j) = tau_k chi_hat_k(t_j)

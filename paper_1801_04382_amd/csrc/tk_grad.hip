@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   for (int k = wave; k < a.M; k += nwaves) {
     cx<real> *ck = static_cast<cx<real> *>(a.ckpt) + static_cast<size_t>(k) * nseg * R * kL;
     const int q_first = a.path_off[k], q_last = a.path_off[k + 1];
-    int khint = 1;  // order of the previous step (where the order search starts)
+    OrderHint khint;  // the previous step's order
     // ---- 1. forward replay with checkpoints ----
     cx<real> psi[R];
     get_rows(start, psi, tm);
@@ -254,7 +254,6 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
       opf.set_pulses(uj, a.wc);
       const StepPlan p = plan_step(a, uj, khint);
-      khint = p.K;
       replay_step<real, R, WS, NC, G>(opf, a, T, psi, j, q, nj, p, tm);
       q += nj;
     }
@@ -305,7 +304,6 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
         for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
         opf.set_pulses(uj, a.wc);
         const StepPlan p = plan_step(a, uj, khint);
-        khint = p.K;
         replay_step<real, R, WS, NC, G>(opf, a, T, psi, j, qr, nj, p, tm);
         qr += nj;
       }
@@ -319,7 +317,6 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
         opf.set_pulses(uj, a.wc);
         opb.set_pulses(uj, a.wc);
         const StepPlan p = plan_step(a, uj, khint);
-        khint = p.K;
         double bnd = a.b0;
 #pragma unroll
         for (int i = 0; i < NCX; ++i) bnd += fabs(uj[i]) * a.bc[i];

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
 #pragma unroll
   for (int i = 0; i < NCX; ++i) inv_lm[i] = 1.0 / (a.lam[i] * a.M);
   double u_prev[NCX];  // block 0: the previous step's new pulse, stored with the next publish
-  int khint = 1;       // order of the previous step (where the order search starts)
+  OrderHint khint;     // the previous step's order
   for (int j = 0; j < a.nt; ++j) {
     // pulse inputs of interval j, loaded now and used after the exchange
     double uo[NCX], so[NCX];
@@ -255,7 +255,6 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
     }
     op.set_pulses(uj, a.wc);
     const StepPlan p = plan_step(a, uj, khint);
-    khint = p.K;
     // ---- advance every trajectory; form the partial of t_{j+1} ----------------
 #pragma unroll
     for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
@@ -269,7 +268,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       load_lds(sv, psi, tm);
       TrajMeta st = meta[t];
       const Stream rng = make_stream(a, k, 0);
-      advance_step<real, R, WS, NC, G, 0>(op, a, T, psi, st, rng, j, p, k, tm);
+      advance_step<real, R, WS, NC, G, 0, true>(op, a, T, psi, st, rng, j, p, k, tm);
       tm.sync();
       store_lds(sv, psi, tm);
       if (tm.leader()) meta[t] = st;
