@@ -163,8 +163,7 @@ __device__ bool gather_shares(const unsigned long long *row, int M, int lane,
         for (int c = 0; c < NCX; ++c) cur[qq][c] = nxt[qq][c];
     }
   }
-#pragma unroll
-  for (int c = 0; c < NCX; ++c) acc[c] = wave_sum(acc[c]);
+  wave_sum_n<NCX>(acc);
   return true;
 }
 
@@ -219,16 +218,23 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     publish_share<NC>(a, I.tslots, k, pc, lane);
   }
 
-  double uo[NCX], sf[NCX], inv_lm[NCX];
+  double inv_lm[NCX];
 #pragma unroll
-  for (int i = 0; i < NCX; ++i) {
-    inv_lm[i] = 1.0 / (a.lam[i] * a.M);
-    uo[i] = a.u_old[static_cast<size_t>(i) * a.nt];
-    sf[i] = a.S[static_cast<size_t>(i) * a.nt] * inv_lm[i];
-  }
-  OrderHint khint;  // the previous step's order
+  for (int i = 0; i < NCX; ++i) inv_lm[i] = 1.0 / (a.lam[i] * a.M);
+  double u_prev[NCX];  // first block: the previous step's new pulse, written this step
+  OrderHint khint;     // the previous step's order
   for (int j = 0; j < a.nt; ++j) {
-    __syncthreads();  // every wave has used the previous step's s_upd
+    // pulse inputs of interval j, loaded now and used after the exchange
+    double uo[NCX], so[NCX];
+#pragma unroll
+    for (int i = 0; i < NCX; ++i) {
+      const size_t ij = static_cast<size_t>(i) * a.nt + j;
+      uo[i] = a.u_old[ij];
+      so[i] = a.S[ij];
+    }
+    block_sync_lds();  // every wave has used the previous step's s_upd
+    if (lb == 0 && j > 0 && threadIdx.x < NCX)
+      a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + j - 1] = u_prev[threadIdx.x];
     if (wib == 0) {
       double acc[NCX];
       const bool ok = a.n_ctrl == 0 ||
@@ -243,22 +249,14 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
         }
       }
     }
-    __syncthreads();
+    block_sync_lds();
     if (*s_abort) return;  // uniform across the block
     double uj[NCX];
 #pragma unroll
-    for (int i = 0; i < NCX; ++i) uj[i] = uo[i] + sf[i] * s_upd[i];
-    if (lb == 0 && threadIdx.x == 0) {
-#pragma unroll
-      for (int i = 0; i < NCX; ++i) a.u_new[static_cast<size_t>(i) * a.nt + j] = uj[i];
-    }
-    if (j + 1 < a.nt) {
-#pragma unroll
-      for (int i = 0; i < NCX; ++i) {
-        const size_t ij = static_cast<size_t>(i) * a.nt + j + 1;
-        uo[i] = a.u_old[ij];
-        sf[i] = a.S[ij] * inv_lm[i];
-      }
+    for (int i = 0; i < NCX; ++i) {
+      const double sf = so[i] * inv_lm[i];
+      uj[i] = uo[i] + sf * s_upd[i];
+      u_prev[i] = uj[i];
     }
     op.set_pulses(uj, a.wc);
     const StepPlan p = plan_step(a, uj, khint);
@@ -309,6 +307,8 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
       }
     }
   }
+  if (lb == 0 && threadIdx.x < NCX)
+    a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + a.nt - 1] = u_prev[threadIdx.x];
   // ---- tau_k = <tgt|psi_hat_k(T)> ----
   for (int k = w; k < a.M; k += nw) {
     const double inv = 1.0 / sqrt(meta_g[k].nrm2);

@@ -64,6 +64,14 @@ __device__ __forceinline__ void wave_sum2(double &x, double &y) {
   y = (read_lane(y, 0) + read_lane(y, 16)) + (read_lane(y, 32) + read_lane(y, 48));
 }
 
+// Wave sums of the first N entries of v, two at a time.
+template <int N, int L>
+__device__ __forceinline__ void wave_sum_n(double (&v)[L]) {
+#pragma unroll
+  for (int c = 0; c + 1 < N; c += 2) wave_sum2(v[c], v[c + 1]);
+  if (N % 2) v[N - 1] = wave_sum(v[N - 1]);
+}
+
 // The lanes that advance one trajectory together: G wavefronts (G = 1: one
 // wavefront; G > 1: the G waves of a block, which then holds just this team).
 // Row r of a state belongs to team lane r mod 64G as its slot m = r / 64G.
@@ -125,6 +133,13 @@ struct Team {
     par ^= 1;
     x = sx;
     y = sy;
+  }
+  // the first N entries of v summed over the team, two at a time
+  template <int N, int L>
+  __device__ __forceinline__ void sum_n(double (&v)[L]) const {
+#pragma unroll
+    for (int c = 0; c + 1 < N; c += 2) sum2(v[c], v[c + 1]);
+    if (N % 2) v[N - 1] = sum(v[N - 1]);
   }
   __device__ __forceinline__ bool leader() const { return gl == 0; }
 };
@@ -543,7 +558,9 @@ __device__ void taylor_keep(const LaneOp<real, R, WS, NC, G> &op, const PassArgs
 
 // p(s) = sum_n s^n t_n and dp/ds from the stored terms (own rows only;
 // Horner from t_K down).  The terms are read four at a time, so one LDS
-// round trip serves four Horner steps.
+// round trip serves four Horner steps.  (Issuing the next four before the
+// current four's multiply-adds needs twice the registers, which the series
+// kernels do not have to spare.)
 template <typename real, int R, int G>
 __device__ __forceinline__ void dense_output(const Terms<real, R, G> &T, int K, real s,
                                              cx<real> (&p)[R], cx<real> (&dp)[R], const Team<G> &tm) {

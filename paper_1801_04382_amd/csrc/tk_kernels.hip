@@ -191,11 +191,10 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       so[i] = a.S[ij];
     }
     // ---- reduce the partial of t_j: waves -> block (fixed order) -> publish ----
+    tm.template sum_n<NC>(pc);
+    if (tm.leader())
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const double s = tm.sum(pc[c]);
-      if (tm.leader()) wpart[team][c] = s;
-    }
+      for (int c = 0; c < NC; ++c) wpart[team][c] = pc[c];
     block_sync_lds();
     if (threadIdx.x < NCX) {  // control i's block partial (zero for padding controls)
       const int i = threadIdx.x;
@@ -233,11 +232,10 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
           break;
         }
       }
+      wave_sum_n<NCX>(acc);
+      if (lane == 0)
 #pragma unroll
-      for (int c = 0; c < NCX; ++c) {
-        const double sc = wave_sum(acc[c]);
-        if (lane == 0) s_upd[c] = sc;
-      }
+        for (int c = 0; c < NCX; ++c) s_upd[c] = acc[c];
       if (abort && lane == 0) {
         atomicOr(a.err, kErrSyncTimeout);
         s_abort = 1;
