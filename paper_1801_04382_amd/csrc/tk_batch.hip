@@ -198,14 +198,12 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
       psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m] = p[m];
     }
     const double n = norm2(p, tm);
-    if (lane == 0) {
-      TrajMeta st;
-      st.nrm2 = n;
-      st.r = make_stream(a, k, 0, it).threshold(0);
-      st.ordinal = 0;
-      st.pad = 0;
-      meta_g[k] = st;
-    }
+    TrajMeta st;
+    st.nrm2 = n;
+    make_stream(a, k, 0, it).draw(0, st);
+    st.ordinal = 0;
+    st.pad = 0;
+    if (lane == 0) meta_g[k] = st;
     cx<real> ch[R];
     load_costate<real, R, 1>(a, 0, k, tm, ch);
     double pc[NCX];
@@ -214,7 +212,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     wave_sync();
     store_lds(v, p, tm);
     wave_sync();
-    krotov_share<real, R, WS, NC, 1>(op, v, ch, 1.0 / sqrt(n), pc);
+    krotov_share<real, R, WS, NC, 1>(op, ch, 1.0 / sqrt(n), pc);
     publish_share<NC>(a, I.tslots, k, pc, lane);
   }
 
@@ -293,7 +291,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
         wave_sync();
         store_lds(v, psi, tm);
         wave_sync();
-        krotov_share<real, R, WS, NC, 1>(op, v, ch, 1.0 / sqrt(st.nrm2), pc);
+        krotov_share<real, R, WS, NC, 1>(op, ch, 1.0 / sqrt(st.nrm2), pc);
         publish_share<NC>(a, I.tslots + static_cast<size_t>(j + 1) * row_len, k, pc, lane);
       }
       wave_sync();

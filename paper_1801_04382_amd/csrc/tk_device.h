@@ -205,11 +205,8 @@ struct Stream {
     thr = to_unit(w0);
     choice = to_unit(w1);
   }
-  __device__ double threshold(uint64_t ordinal) const {
-    double t, c;
-    block(ordinal, t, c);
-    return t;
-  }
+  // threshold and operator-choice number of jump `ordinal` (one block)
+  __device__ void draw(uint64_t ordinal, TrajMeta &st) const { block(ordinal, st.r, st.x); }
 };
 
 // Stream of trajectory k: key [seed, (instance << 32) | k], counter
@@ -311,17 +308,18 @@ struct LaneOp {
     }
   }
 
-  // y = Op v for the lane's rows (v in LDS).  All gathers first.
-  __device__ void apply(const cx<real> *v, cx<real> (&y)[R]) const {
+  // y = Op v for the lane's rows, v the term vector `shift` elements past the
+  // one the gathers are bound to.  All gathers first.
+  __device__ void apply_at(int shift, cx<real> (&y)[R]) const {
     cx<real> b[WS + NC][R];
 #pragma unroll
     for (int s = 0; s < WS; ++s)
 #pragma unroll
-      for (int m = 0; m < R; ++m) b[s][m] = v[scol[s][m]];
+      for (int m = 0; m < R; ++m) b[s][m] = sp[s][m][shift];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int m = 0; m < R; ++m) b[WS + c][m] = v[ccol[c][m]];
+      for (int m = 0; m < R; ++m) b[WS + c][m] = cp[c][m][shift];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
@@ -334,6 +332,7 @@ struct LaneOp {
 #pragma unroll
       for (int m = 0; m < R; ++m) cfma(y[m], cv[c][m], b[WS + c][m]);
   }
+
 };
 
 template <typename real, int R, int G>
@@ -417,7 +416,7 @@ __device__ void taylor(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
   for (int n = 1; n <= K; ++n) {
     tm.sync();
     cx<real> y[R];
-    op.apply(T[n - 1], y);
+    op.apply_at((n - 1) * Terms<real, R, G>::kLen, y);
     const real c = static_cast<real>(tau * a.inv_n[n]);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -670,6 +669,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     }
     tm.sync();
     double lo = 0.0, hi = 1.0;
+    if (n_s < 0.0) n_s = norm2(ps, tm);
     const double flo = n_s - st.r, fhi = n_end - st.r;
     double s = flo / (flo - fhi);
     if (!(s > lo && s < hi)) s = 0.5;
@@ -707,8 +707,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     tm.sync();
     store_lds(T[0], pt, tm);
     tm.sync();
-    double thr_unused, x;
-    rng.block(static_cast<uint64_t>(st.ordinal), thr_unused, x);
+    const double x = st.x;
     int lsel = -1;
     double wsel = 0.0;
     cx<real> y[R];
@@ -775,8 +774,8 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
       }
     }
     st.ordinal += 1;
-    st.r = rng.threshold(static_cast<uint64_t>(st.ordinal));
-    n_s = norm2(ps, tm);
+    rng.draw(static_cast<uint64_t>(st.ordinal), st);
+    n_s = -1.0;  // ||ps||^2 is reduced only if another jump falls in this substep
     tau_rem = tau_rem - tau;
     const int Kr = taylor_order(a, bnd * tau_rem, Kc);
     if (Kr >= 1 && Kr < Kc) Kc = Kr;
@@ -881,7 +880,8 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
   TrajMeta st;
   st.nrm2 = norm2(psi, tm);
   st.ordinal = 0;
-  st.r = rng.threshold(0);
+  st.pad = 0;
+  rng.draw(0, st);
   double tau_re = 0.0, tau_im = 0.0;
   if (DIR == 1) {
     tau_re = a.tau_in[2 * k];
@@ -948,18 +948,18 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
   }
 }
 
-// Per-lane share of Im <chi|H_i|psi_hat> for every control slot c, added to pc.
-// v holds the (unnormalised) state, inv = 1/||psi||.
+// Per-lane share of Im <chi|H_i|psi_hat> for every control slot c, added to
+// pc.  The (unnormalised) state is in term vector 0, where the gathers are
+// bound; inv = 1/||psi||.
 template <typename real, int R, int WS, int NC, int G>
 __device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC, G> &op,
-                                             const cx<real> *v, const cx<real> (&ch)[R],
-                                             double inv, double *pc) {
+                                             const cx<real> (&ch)[R], double inv, double *pc) {
 #pragma unroll
   for (int m = 0; m < R; ++m) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const cx<real> q = op.cval_at(c, m);
-      const cx<real> b = v[op.ccol[c][m]];
+      const cx<real> b = op.cp[c][m][0];
       const double hx = static_cast<double>(q.x) * b.x - static_cast<double>(q.y) * b.y;
       const double hy = static_cast<double>(q.x) * b.y + static_cast<double>(q.y) * b.x;
       // Im(conj(chi) h) = chi.x h.y - chi.y h.x

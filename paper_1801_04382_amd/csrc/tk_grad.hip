@@ -136,17 +136,18 @@ __device__ void taylor_aug(const LaneOp<real, R, WS, NC, G> &op, const PassArgs 
   int cur = 0;
   for (int n = 1; n <= K; ++n) {
     tm.sync();
-    const cx<real> *xv = T[cur * (1 + NCX)];
+    constexpr int kLen = Terms<real, R, G>::kLen;
+    const int xshift = cur * (1 + NCX) * kLen;  // x_{n-1}: term vector cur (1 + NCX)
     // gathers of x_{n-1}: H x and the unscaled H_i x from the same loads
     cx<real> b[WS + NCX][R];
 #pragma unroll
     for (int s = 0; s < WS; ++s)
 #pragma unroll
-      for (int m = 0; m < R; ++m) b[s][m] = xv[op.scol[s][m]];
+      for (int m = 0; m < R; ++m) b[s][m] = op.sp[s][m][xshift];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int m = 0; m < R; ++m) b[WS + c][m] = xv[op.ccol[c][m]];
+      for (int m = 0; m < R; ++m) b[WS + c][m] = op.cp[c][m][xshift];
     __builtin_amdgcn_sched_barrier(0);
     cx<real> hx[R], hix[NCX][R];
 #pragma unroll
@@ -161,7 +162,10 @@ __device__ void taylor_aug(const LaneOp<real, R, WS, NC, G> &op, const PassArgs 
       for (int m = 0; m < R; ++m) cfma(hx[m], op.sval[s][m], b[s][m]);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int i = c / a.wc;
+      int i = 0;  // control of slot c: c / wc, by comparisons
+#pragma unroll
+      for (int ii = 1; ii < NC; ++ii)
+        if (c >= ii * a.wc) i = ii;
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         cfma(hx[m], op.cv[c][m], b[WS + c][m]);
@@ -186,7 +190,7 @@ __device__ void taylor_aug(const LaneOp<real, R, WS, NC, G> &op, const PassArgs 
     for (int i = 0; i < NCX; ++i) {
       if (i < nctl) {
         cx<real> hy[R];
-        op.apply(T[cur * (1 + NCX) + 1 + i], hy);
+        op.apply_at((cur * (1 + NCX) + 1 + i) * kLen, hy);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
           const real sx = hy[m].x + hix[i][m].x, sy = hy[m].y + hix[i][m].y;

@@ -35,6 +35,7 @@ constexpr uint64_t kSlotEmpty = 0xFFF7DEADBEEF5A5Aull;
 struct TrajMeta {
   double nrm2;  // squared norm of the unnormalised state
   double r;     // current threshold
+  double x;     // operator-choice number of the next jump (drawn with r)
   int ordinal;  // jumps so far in this pass
   int pad;
 };

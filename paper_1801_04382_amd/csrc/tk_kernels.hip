@@ -156,20 +156,20 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
     for (int m = 0; m < R; ++m) p[m] = start[tm.gl + kL * m];
     store_lds(states + t * R * kL, p, tm);
     const double n = norm2(p, tm);
-    if (tm.leader()) {
-      TrajMeta st;
-      st.nrm2 = n;
-      st.ordinal = 0;
-      st.pad = 0;
-      st.r = k < a.M ? make_stream(a, k, 0).threshold(0) : 0.0;
-      meta[t] = st;
-    }
+    TrajMeta st;
+    st.nrm2 = n;
+    st.ordinal = 0;
+    st.pad = 0;
+    st.r = 0.0;
+    st.x = 0.0;
+    if (k < a.M) make_stream(a, k, 0).draw(0, st);
+    if (tm.leader()) meta[t] = st;
     if (k < a.M) {
       cx<real> ch[R];
       load_costate<real, R, G>(a, 0, k, tm, ch);
       store_lds(v, p, tm);
       tm.sync();
-      krotov_share<real, R, WS, NC, G>(op, v, ch, 1.0 / sqrt(n), pc);
+      krotov_share<real, R, WS, NC, G>(op, ch, 1.0 / sqrt(n), pc);
       tm.sync();
     }
   }
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       if (j + 1 < a.nt) {
         store_lds(v, psi, tm);
         tm.sync();
-        krotov_share<real, R, WS, NC, G>(op, v, ch, 1.0 / sqrt(st.nrm2), pc);
+        krotov_share<real, R, WS, NC, G>(op, ch, 1.0 / sqrt(st.nrm2), pc);
       }
       tm.sync();
     }
