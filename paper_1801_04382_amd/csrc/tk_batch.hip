@@ -357,6 +357,340 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArg
   if (threadIdx.x == 0) atomicMax(&b.t_end[i], static_cast<unsigned long long>(wall_clock64()));
 }
 
+// ---- instances of multi-wave shapes (one G-wave team per block) --------------------
+// Kernel shapes with G > 1, in the order of variants() within a precision
+// (indices continue those of TK_BATCH_SHAPES); the d = 1296 shape exists in
+// FP32 only.
+#define TK_BATCH_WIDE_SHAPES(X) \
+  X(4, 1, 4, 2, 2)              \
+  X(5, 2, 6, 3, 2)
+#define TK_BATCH_WIDE_SHAPES_FP32(X) X(6, 3, 9, 4, 8)
+
+// Term vectors of the block's team at the start of dynamic LDS, trailing
+// zero elements set.
+template <typename real, int R, int G>
+__device__ __forceinline__ Terms<real, R, G> wide_terms(unsigned char *smem, int kbuf,
+                                                         const Team<G> &tm) {
+  Terms<real, R, G> T;
+  T.base = reinterpret_cast<cx<real> *>(smem);
+  block_sync_lds();  // earlier readers of these vectors are done
+  if (tm.gl < kbuf) T[tm.gl][R * Team<G>::kLanes] = cx<real>{0, 0};
+  block_sync_lds();
+  return T;
+}
+
+template <typename real, int R, int WS, int NC, int G, int DIR>
+__device__ void wide_pass_item(const PassArgs &a, int k, uint64_t it, unsigned char *smem,
+                               const Team<G> &tm) {
+  const Terms<real, R, G> T = wide_terms<real, R, G>(smem, a.kbuf, tm);
+  LaneOp<real, R, WS, NC, G> op;
+  op.load(a.scol, a.sval, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
+  op.bind(T[0]);
+  pass_trajectory<real, R, WS, NC, G, DIR>(op, a, T, k, make_stream(a, k, DIR, it), tm);
+}
+
+template <typename real, int DIR, int G>
+__global__ __launch_bounds__(kWave *G) void k_batch_wide_pass(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double team_red[4 * G];
+  const Team<G> tm = make_team<G>(team_red);
+  const uint64_t it = *b.iteration;
+  for (int q = blockIdx.x; q < b.n_witems; q += gridDim.x) {
+    const int2 item = b.witems[q];
+    const BatchInstance &I = b.inst[__builtin_amdgcn_readfirstlane(item.x)];
+    const PassArgs &a = DIR == 0 ? I.fw : I.bw;
+    const int k = __builtin_amdgcn_readfirstlane(item.y);
+    switch (I.variant) {
+#define TK_CASE(idx, R, WS, NC, GG)                                             \
+  case idx:                                                                     \
+    if constexpr (GG == G) wide_pass_item<real, R, WS, NC, G, DIR>(a, k, it, smem_raw, tm); \
+    break;
+      TK_BATCH_WIDE_SHAPES(TK_CASE)
+#undef TK_CASE
+#define TK_CASE(idx, R, WS, NC, GG)                                                     \
+  case idx:                                                                             \
+    if constexpr (GG == G && sizeof(real) == 4)                                         \
+      wide_pass_item<real, R, WS, NC, G, DIR>(a, k, it, smem_raw, tm);                  \
+    break;
+      TK_BATCH_WIDE_SHAPES_FP32(TK_CASE)
+#undef TK_CASE
+      default:
+        break;
+    }
+  }
+}
+
+// The costates of segment s (chi(t_j), j0 = s kSegment <= j <= e = min(j0 +
+// kSegment, nt), slot j - j0 of the instance's segment buffer) of the team's
+// trajectories k = w, w + nteam, ..: the backward pass replayed from the
+// checkpoint at t_e (from the target at t_nt for the last segment) with the
+// same stream, pulses and device code, so every value equals the one the full
+// backward pass computes.
+template <typename real, int R, int WS, int NC, int G>
+__device__ void wide_recompute(const BatchInstance &I, int w, int nteam, int s, uint64_t it,
+                               const Terms<real, R, G> &T, const Team<G> &tm) {
+  constexpr int kL = Team<G>::kLanes;
+  constexpr int NCX = NC > 0 ? NC : 1;
+  const PassArgs &ab = I.bw;
+  const int nt = ab.nt, M = ab.M, d = ab.d;
+  const int j0 = s * kSegment, e = min(j0 + kSegment, nt);
+  LaneOp<real, R, WS, NC, G> opb;
+  opb.load(ab.scol, ab.sval, ab.ccol, static_cast<const cx<real> *>(ab.cval), tm.gl);
+  opb.bind(T[0]);
+  cx<real> *seg = static_cast<cx<real> *>(I.fw.chi);
+  const cx<real> *start = static_cast<const cx<real> *>(ab.psi_start);
+  for (int k = w; k < M; k += nteam) {
+    cx<real> psi[R];
+    TrajMeta st;
+    const Stream rng = make_stream(ab, k, 1, it);
+    if (e == nt) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = start[tm.gl + kL * m];
+      st.nrm2 = norm2(psi, tm);
+      st.ordinal = 0;
+      st.pad = 0;
+      rng.draw(0, st);
+    } else {
+      const size_t c = static_cast<size_t>(s) * M + k;
+      const cx<real> *ck = static_cast<const cx<real> *>(ab.ck_psi) + c * R * kL;
+#pragma unroll
+      for (int m = 0; m < R; ++m) psi[m] = ck[tm.gl + kL * m];
+      st = ab.ck_meta[c];
+    }
+    const double tau_re = ab.tau_in[2 * k], tau_im = ab.tau_in[2 * k + 1];
+    if (e < nt)
+      store_costate<real, R, G>(seg + (static_cast<size_t>(e - j0) * M + k) * d, d, psi,
+                                st.nrm2, tau_re, tau_im, tm);
+    OrderHint hint;
+    for (int j = e - 1; j >= j0; --j) {
+      double uj[NCX];
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) uj[i] = ab.u[static_cast<size_t>(i) * nt + j];
+      opb.set_pulses(uj, ab.wc);
+      const StepPlan p = plan_step(ab, uj, hint);
+      advance_step<real, R, WS, NC, G, 1>(opb, ab, T, psi, st, rng, j, p, k, tm);
+      store_costate<real, R, G>(seg + (static_cast<size_t>(j - j0) * M + k) * d, d, psi,
+                                st.nrm2, tau_re, tau_im, tm);
+    }
+    tm.sync();  // the term vectors are reused by the next trajectory
+  }
+}
+
+// Share of one trajectory: pc summed over the team, then per control over its
+// slots, into the trajectory's slot of the step (team leader).
+template <int NC, int G>
+__device__ __forceinline__ void publish_share_team(const PassArgs &a, unsigned long long *row,
+                                                   int k, double (&pc)[NC > 0 ? NC : 1],
+                                                   const Team<G> &tm) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  tm.template sum_n<NC>(pc);
+  if (tm.leader()) {
+#pragma unroll
+    for (int i = 0; i < NCX; ++i) {
+      double s = 0.0;  // control i owns slots i wc .. i wc + wc - 1
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c >= i * a.wc && c < (i + 1) * a.wc) s += pc[c];
+      __hip_atomic_store(&row[static_cast<size_t>(k) * NCX + i], __double_as_longlong(s),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// costate of trajectory k at slot q of the segment buffer (own rows; padding
+// rows read row d - 1, see load_costate)
+template <typename real, int R, int G>
+__device__ __forceinline__ void load_seg_costate(const PassArgs &a, int q, int k, const Team<G> &tm,
+                                                 cx<real> (&ch)[R]) {
+  const cx<real> *chi = static_cast<const cx<real> *>(a.chi);
+  const size_t base = (static_cast<size_t>(q) * a.M + k) * a.d;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int row = tm.gl + Team<G>::kLanes * m;
+    ch[m] = chi[base + (row < a.d ? row : a.d - 1)];
+  }
+}
+
+// Sequential Krotov pass of one instance of a multi-wave shape; this block is
+// team lb of the instance's I.nblocks.  The costates come segment by segment
+// (wide_recompute) into one buffer; the shares, the fixed-order gather and the
+// update are those of the one-wave instances.
+template <typename real, int R, int WS, int NC, int G>
+__device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I, int lb,
+                                     uint64_t it, unsigned char *smem, double *s_upd,
+                                     int *s_abort, const Team<G> &tm) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  constexpr int kL = Team<G>::kLanes;
+  constexpr int kRows = R * kL;
+  const PassArgs &a = I.fw;
+  const int nt = a.nt, M = a.M;
+  const int nteam = I.nblocks, w = lb;
+  const int kbuf = max(I.fw.kbuf, I.bw.kbuf);
+  const Terms<real, R, G> T = wide_terms<real, R, G>(smem, kbuf, tm);
+  cx<real> *psi_g = static_cast<cx<real> *>(I.psi);
+  TrajMeta *meta_g = I.meta;
+  const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
+  const size_t row_len = static_cast<size_t>(M) * NCX;
+  double inv_lm[NCX];
+#pragma unroll
+  for (int i = 0; i < NCX; ++i) inv_lm[i] = 1.0 / (a.lam[i] * M);
+  double u_prev[NCX];  // first block: the previous step's new pulse, written this step
+  const int nseg = (nt + kSegment - 1) / kSegment;
+  for (int s = 0; s < nseg; ++s) {
+    const int j0 = s * kSegment, j1 = min(j0 + kSegment, nt);
+    wide_recompute<real, R, WS, NC, G>(I, w, nteam, s, it, T, tm);
+    LaneOp<real, R, WS, NC, G> op;
+    op.load(a.scol, a.sval, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
+    op.bind(T[0]);
+    if (s == 0) {  // start states and their shares at t_0
+      for (int k = w; k < M; k += nteam) {
+        cx<real> p[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          p[m] = start[tm.gl + kL * m];
+          psi_g[static_cast<size_t>(k) * kRows + tm.gl + kL * m] = p[m];
+        }
+        const double n = norm2(p, tm);
+        TrajMeta st;
+        st.nrm2 = n;
+        make_stream(a, k, 0, it).draw(0, st);
+        st.ordinal = 0;
+        st.pad = 0;
+        if (tm.leader()) meta_g[k] = st;
+        cx<real> ch[R];
+        load_seg_costate<real, R, G>(a, 0, k, tm, ch);
+        double pc[NCX];
+#pragma unroll
+        for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
+        tm.sync();
+        store_lds(T[0], p, tm);
+        tm.sync();
+        krotov_share<real, R, WS, NC, G>(op, ch, 1.0 / sqrt(n), pc);
+        publish_share_team<NC, G>(a, I.tslots, k, pc, tm);
+      }
+    }
+    OrderHint khint;
+    for (int j = j0; j < j1; ++j) {
+      double uo[NCX], so[NCX];
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) {
+        const size_t ij = static_cast<size_t>(i) * nt + j;
+        uo[i] = a.u_old[ij];
+        so[i] = a.S[ij];
+      }
+      block_sync_lds();  // every wave has used the previous step's s_upd
+      if (lb == 0 && j > 0 && threadIdx.x < NCX)
+        a.u_new[static_cast<size_t>(threadIdx.x) * nt + j - 1] = u_prev[threadIdx.x];
+      if (threadIdx.x < kWave) {
+        double acc[NCX];
+        const bool ok = a.n_ctrl == 0 ||
+                        gather_shares<NCX>(I.tslots + static_cast<size_t>(j) * row_len, M,
+                                           tm.lane, b.spin_limit, b.err, acc);
+        if (tm.lane == 0) {
+#pragma unroll
+          for (int c = 0; c < NCX; ++c) s_upd[c] = ok && a.n_ctrl > 0 ? acc[c] : 0.0;
+          if (!ok) {
+            atomicOr(b.err, kErrSyncTimeout);
+            *s_abort = 1;
+          }
+        }
+      }
+      block_sync_lds();
+      if (*s_abort) return;  // uniform across the block
+      double uj[NCX];
+#pragma unroll
+      for (int i = 0; i < NCX; ++i) {
+        const double sf = so[i] * inv_lm[i];
+        uj[i] = uo[i] + sf * s_upd[i];
+        u_prev[i] = uj[i];
+      }
+      op.set_pulses(uj, a.wc);
+      const StepPlan p = plan_step(a, uj, khint);
+      for (int k = w; k < M; k += nteam) {
+        cx<real> psi[R], ch[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) psi[m] = psi_g[static_cast<size_t>(k) * kRows + tm.gl + kL * m];
+        TrajMeta st = meta_g[k];
+        if (j + 1 < nt) load_seg_costate<real, R, G>(a, j + 1 - j0, k, tm, ch);
+        const Stream rng = make_stream(a, k, 0, it);
+        tm.sync();  // the previous trajectory's reads of the term vectors are done
+        advance_step<real, R, WS, NC, G, 0, true>(op, a, T, psi, st, rng, j, p, k, tm);
+#pragma unroll
+        for (int m = 0; m < R; ++m) psi_g[static_cast<size_t>(k) * kRows + tm.gl + kL * m] = psi[m];
+        if (tm.leader()) meta_g[k] = st;
+        if (j + 1 < nt) {
+          double pc[NCX];
+#pragma unroll
+          for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
+          tm.sync();
+          store_lds(T[0], psi, tm);
+          tm.sync();
+          krotov_share<real, R, WS, NC, G>(op, ch, 1.0 / sqrt(st.nrm2), pc);
+          publish_share_team<NC, G>(a, I.tslots + static_cast<size_t>(j + 1) * row_len, k, pc, tm);
+        }
+      }
+    }
+  }
+  if (lb == 0 && threadIdx.x < NCX)
+    a.u_new[static_cast<size_t>(threadIdx.x) * nt + nt - 1] = u_prev[threadIdx.x];
+  // ---- tau_k = <tgt|psi_hat_k(T)> ----
+  for (int k = w; k < M; k += nteam) {
+    const double inv = 1.0 / sqrt(meta_g[k].nrm2);
+    double tr = 0.0, ti = 0.0;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int row = tm.gl + kL * m;
+      const cx<real> q = psi_g[static_cast<size_t>(k) * kRows + row];
+      const double px = q.x * inv, py = q.y * inv;
+      const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
+      tr = fma(gx, px, fma(gy, py, tr));
+      ti = fma(gx, py, fma(-gy, px, ti));
+    }
+    tm.sum2(tr, ti);
+    if (tm.leader()) {
+      a.tau_out[2 * k] = tr;
+      a.tau_out[2 * k + 1] = ti;
+    }
+  }
+}
+
+template <typename real, int G>
+__global__ __launch_bounds__(kWave *G) void k_batch_wide_krotov(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double s_upd[kMaxCtrl];
+  __shared__ int s_abort;
+  __shared__ double team_red[4 * G];
+  const Team<G> tm = make_team<G>(team_red);
+  if (threadIdx.x == 0) {
+    s_abort = 0;
+    atomicMin(b.t_begin, static_cast<unsigned long long>(wall_clock64()));
+  }
+  const int i = __builtin_amdgcn_readfirstlane(b.wblock_inst[blockIdx.x]);
+  const BatchInstance &I = b.inst[i];
+  const int lb = blockIdx.x - I.block0;
+  const uint64_t it = *b.iteration;
+  switch (I.variant) {
+#define TK_CASE(idx, R, WS, NC, GG)                                                          \
+  case idx:                                                                                  \
+    if constexpr (GG == G)                                                                   \
+      wide_krotov_instance<real, R, WS, NC, G>(b, I, lb, it, smem_raw, s_upd, &s_abort, tm); \
+    break;
+    TK_BATCH_WIDE_SHAPES(TK_CASE)
+#undef TK_CASE
+#define TK_CASE(idx, R, WS, NC, GG)                                                          \
+  case idx:                                                                                  \
+    if constexpr (GG == G && sizeof(real) == 4)                                              \
+      wide_krotov_instance<real, R, WS, NC, G>(b, I, lb, it, smem_raw, s_upd, &s_abort, tm); \
+    break;
+    TK_BATCH_WIDE_SHAPES_FP32(TK_CASE)
+#undef TK_CASE
+    default:
+      break;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&b.t_end[i], static_cast<unsigned long long>(wall_clock64()));
+}
+
 // ---- bookkeeping kernels ------------------------------------------------------------
 // Per-trajectory slots of every instance <- sentinel (one block per instance).
 __global__ __launch_bounds__(256) void k_batch_fill(BatchArgs b) {
@@ -411,6 +745,18 @@ BatchKernels batch_kernels(int precision) {
     k.pass_fw = reinterpret_cast<const void *>(&k_batch_pass<float, 0>);
     k.pass_bw = reinterpret_cast<const void *>(&k_batch_pass<float, 1>);
     k.krotov = reinterpret_cast<const void *>(&k_batch_krotov<float>);
+  }
+  if (precision == TK_FP64) {
+    k.wpass_fw = reinterpret_cast<const void *>(&k_batch_wide_pass<double, 0, 2>);
+    k.wpass_bw = reinterpret_cast<const void *>(&k_batch_wide_pass<double, 1, 2>);
+    k.wkrotov = reinterpret_cast<const void *>(&k_batch_wide_krotov<double, 2>);
+  } else {
+    k.wpass_fw = reinterpret_cast<const void *>(&k_batch_wide_pass<float, 0, 2>);
+    k.wpass_bw = reinterpret_cast<const void *>(&k_batch_wide_pass<float, 1, 2>);
+    k.wkrotov = reinterpret_cast<const void *>(&k_batch_wide_krotov<float, 2>);
+    k.wpass_fw8 = reinterpret_cast<const void *>(&k_batch_wide_pass<float, 0, 8>);
+    k.wpass_bw8 = reinterpret_cast<const void *>(&k_batch_wide_pass<float, 1, 8>);
+    k.wkrotov8 = reinterpret_cast<const void *>(&k_batch_wide_krotov<float, 8>);
   }
   k.fill = reinterpret_cast<const void *>(&k_batch_fill);
   k.functional = reinterpret_cast<const void *>(&k_batch_functional);

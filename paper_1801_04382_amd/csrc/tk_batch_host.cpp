@@ -32,7 +32,9 @@ struct Member {
   int variant = -1;  // index among the kernel shapes of the precision
   int kbuf_fw = 0, kbuf_bw = 0;
   double step_cost = 0.0;  // model of one trajectory-step (relative units)
+  int G = 1;               // waves per trajectory of its shape
   DevBuf psi, meta, tslots;
+  DevBuf seg, ck_psi, ck_meta;  // multi-wave shapes: costate segment and checkpoints
   ~Member() {
     if (c) tk_destroy(c);
   }
@@ -42,7 +44,19 @@ struct LaunchPlan {
   int pass_wpb = 0, pass_blocks = 0;
   int kro_wpb = 0, kro_blocks = 0;
   size_t pass_lds = 0, kro_lds = 0;
-  std::vector<int> nblocks;  // Krotov blocks per instance
+  std::vector<int> nblocks;  // Krotov blocks per instance (one-wave instances)
+};
+
+// Instances of one multi-wave team size: kernels of their own, one team per
+// block, blocks split by the cost model.
+struct WideClass {
+  int G = 0;
+  std::vector<int> idx;  // member indices
+  const void *pass_fw = nullptr, *pass_bw = nullptr, *krotov = nullptr;
+  DevBuf items_dev, block_inst_dev;
+  int n_items = 0, pass_blocks = 0, kro_blocks = 0;
+  size_t lds = 0;
+  std::vector<int> nblocks;  // per entry of idx
 };
 
 }  // namespace
@@ -55,6 +69,8 @@ struct tk_batch {
   std::string err;
   int n_cu = 0;
   std::vector<std::unique_ptr<Member>> mem;
+  std::vector<int> narrow;       // members of one-wave shapes
+  std::vector<std::unique_ptr<WideClass>> wide;  // members of multi-wave shapes, by team size
   tk::BatchKernels kern{};
   bool ready = false;
   uint64_t next_iter = 0;  // iteration the next call starts with
@@ -112,27 +128,27 @@ size_t pass_wave_lds(const tk_batch *b, const Member &m) {
   return (bytes + 15) / 16 * 16;
 }
 
-// Krotov blocks per instance: every instance gets one, then blocks go one at a
-// time to the instance with the longest estimated pass,
+// Krotov blocks per instance of `idx`: every instance gets one, then blocks go
+// one at a time to the instance with the longest estimated pass,
 //   nt (ceil(M / (blocks * wpb)) cost + sync_cost),
 // until `capacity` blocks are given out or the longest cannot gain.  `cost` is
-// the time of one trajectory-step per instance (measured), or null for the
-// model m.step_cost.
-std::vector<int> split_blocks(const tk_batch *b, int capacity, int wpb, double sync_cost,
-                              const std::vector<double> *cost) {
-  const size_t n = b->mem.size();
+// the time of one trajectory-step per member (measured), or null for the
+// model m.step_cost.  Returns the blocks per entry of idx.
+std::vector<int> split_blocks(const tk_batch *b, const std::vector<int> &idx, int capacity,
+                              int wpb, double sync_cost, const std::vector<double> *cost) {
+  const size_t n = idx.size();
   std::vector<int> nb(n, 1);
-  auto est = [&](size_t i) {
-    const Member &m = *b->mem[i];
-    const double tw = std::ceil(static_cast<double>(m.M) / (static_cast<double>(nb[i]) * wpb));
-    return m.c->nt * (tw * (cost ? (*cost)[i] : m.step_cost) + sync_cost);
+  auto est = [&](size_t q) {
+    const Member &m = *b->mem[idx[q]];
+    const double tw = std::ceil(static_cast<double>(m.M) / (static_cast<double>(nb[q]) * wpb));
+    return m.c->nt * (tw * (cost ? (*cost)[idx[q]] : m.step_cost) + sync_cost);
   };
   int used = static_cast<int>(n);
-  while (used < capacity) {
+  while (used < capacity && n > 0) {
     size_t worst = 0;
-    for (size_t i = 1; i < n; ++i)
-      if (est(i) > est(worst)) worst = i;
-    const Member &m = *b->mem[worst];
+    for (size_t q = 1; q < n; ++q)
+      if (est(q) > est(worst)) worst = q;
+    const Member &m = *b->mem[idx[worst]];
     if (nb[worst] >= tk::kMaxBlocks || static_cast<int64_t>(nb[worst]) * wpb >= m.M) break;
     nb[worst]++;
     used++;
@@ -140,21 +156,33 @@ std::vector<int> split_blocks(const tk_batch *b, int capacity, int wpb, double s
   return nb;
 }
 
-// Instance table and Krotov block map for a launch plan.
+// Block map of one Krotov launch: the blocks of member idx[q] are nb[q]
+// consecutive blocks; sets block0 / nblocks of those members.
+int upload_block_map(tk_batch *b, const std::vector<int> &idx, const std::vector<int> &nb,
+                     DevBuf &dev, int *n_blocks) {
+  std::vector<int> block_inst;
+  for (size_t q = 0; q < idx.size(); ++q) {
+    b->inst[idx[q]].block0 = static_cast<int>(block_inst.size());
+    b->inst[idx[q]].nblocks = nb[q];
+    for (int r = 0; r < nb[q]; ++r) block_inst.push_back(idx[q]);
+  }
+  *n_blocks = static_cast<int>(block_inst.size());
+  if (block_inst.empty()) return TK_OK;
+  TK_BHIP(b, dev.ensure(block_inst.size() * sizeof(int)));
+  TK_BHIP(b, hipMemcpy(dev.p, block_inst.data(), block_inst.size() * sizeof(int),
+                       hipMemcpyHostToDevice));
+  return TK_OK;
+}
+
+// Instance table and the Krotov block maps of the current plans.
 int upload_tables(tk_batch *b) {
   const size_t n = b->mem.size();
-  std::vector<int> block_inst;
-  for (size_t i = 0; i < n; ++i) {
-    b->inst[i].block0 = static_cast<int>(block_inst.size());
-    b->inst[i].nblocks = b->plan.nblocks[i];
-    for (int q = 0; q < b->plan.nblocks[i]; ++q) block_inst.push_back(static_cast<int>(i));
-  }
-  b->plan.kro_blocks = static_cast<int>(block_inst.size());
+  int rc = upload_block_map(b, b->narrow, b->plan.nblocks, b->block_inst_dev, &b->plan.kro_blocks);
+  if (rc) return rc;
+  for (auto &w : b->wide)
+    if ((rc = upload_block_map(b, w->idx, w->nblocks, w->block_inst_dev, &w->kro_blocks))) return rc;
   TK_BHIP(b, b->inst_dev.ensure(n * sizeof(tk::BatchInstance)));
   TK_BHIP(b, hipMemcpy(b->inst_dev.p, b->inst.data(), n * sizeof(tk::BatchInstance),
-                       hipMemcpyHostToDevice));
-  TK_BHIP(b, b->block_inst_dev.ensure(block_inst.size() * sizeof(int)));
-  TK_BHIP(b, hipMemcpy(b->block_inst_dev.p, block_inst.data(), block_inst.size() * sizeof(int),
                        hipMemcpyHostToDevice));
   return TK_OK;
 }
@@ -167,7 +195,7 @@ tk::BatchArgs batch_args(tk_batch *b) {
   a.wave_lds = static_cast<int>(b->plan.pass_lds / std::max(b->plan.pass_wpb, 1));
   a.items = b->items_dev.as<int2>();
   int64_t items = 0;
-  for (const auto &m : b->mem) items += m->M;
+  for (int i : b->narrow) items += b->mem[i]->M;
   a.n_items = static_cast<int>(items);
   a.block_inst = b->block_inst_dev.as<int>();
   a.iteration = b->iter_dev.as<uint64_t>();
@@ -179,10 +207,18 @@ tk::BatchArgs batch_args(tk_batch *b) {
   return a;
 }
 
+tk::BatchArgs wide_args(tk_batch *b, WideClass &w) {
+  tk::BatchArgs a = batch_args(b);
+  a.witems = w.items_dev.as<int2>();
+  a.n_witems = w.n_items;
+  a.wblock_inst = w.block_inst_dev.as<int>();
+  return a;
+}
+
 // Pass plan with `wpb` waves per block: as many blocks as are co-resident.
 int plan_pass(tk_batch *b, int wpb) {
   size_t wl = 0;
-  for (const auto &m : b->mem) wl = std::max(wl, pass_wave_lds(b, *m));
+  for (int i : b->narrow) wl = std::max(wl, pass_wave_lds(b, *b->mem[i]));
   const size_t lds = wl * wpb;
   if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
   for (const void *k : {b->kern.pass_fw, b->kern.pass_bw})
@@ -193,7 +229,7 @@ int plan_pass(tk_batch *b, int wpb) {
                                                           lds));
   if (occ < 1) return TK_EUNSUPPORTED;
   int64_t items = 0;
-  for (const auto &m : b->mem) items += m->M;
+  for (int i : b->narrow) items += b->mem[i]->M;
   const int64_t blocks = std::min<int64_t>(static_cast<int64_t>(occ) * b->n_cu, (items + wpb - 1) / wpb);
   b->plan.pass_wpb = wpb;
   b->plan.pass_lds = lds;
@@ -205,8 +241,8 @@ int plan_pass(tk_batch *b, int wpb) {
 int plan_krotov(tk_batch *b, int wpb, double frac, double sync_cost,
                 const std::vector<double> *cost = nullptr) {
   size_t lds = 0;
-  for (const auto &m : b->mem)
-    lds = std::max(lds, tk::block_lds_bytes(*m->c->var, wpb, m->kbuf_fw, 0));
+  for (int i : b->narrow)
+    lds = std::max(lds, tk::block_lds_bytes(*b->mem[i]->c->var, wpb, b->mem[i]->kbuf_fw, 0));
   if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
   TK_BHIP(b, hipFuncSetAttribute(b->kern.krotov, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(lds)));
@@ -214,31 +250,80 @@ int plan_krotov(tk_batch *b, int wpb, double frac, double sync_cost,
   TK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, b->kern.krotov, tk::kWave * wpb,
                                                           lds));
   const int capacity = static_cast<int>(frac * occ * b->n_cu);
-  if (capacity < static_cast<int>(b->mem.size())) return TK_EUNSUPPORTED;
+  if (capacity < static_cast<int>(b->narrow.size())) return TK_EUNSUPPORTED;
   b->plan.kro_wpb = wpb;
   b->plan.kro_lds = lds;
-  b->plan.nblocks = split_blocks(b, capacity, wpb, sync_cost, cost);
+  b->plan.nblocks = split_blocks(b, b->narrow, capacity, wpb, sync_cost, cost);
   return upload_tables(b);
 }
 
-int launch_pass(tk_batch *b, int dir) {
-  tk::BatchArgs a = batch_args(b);
-  void *args[] = {&a};
-  TK_BHIP(b, hipLaunchKernel(dir == 0 ? b->kern.pass_fw : b->kern.pass_bw,
-                             dim3(b->plan.pass_blocks), dim3(tk::kWave * b->plan.pass_wpb), args,
-                             b->plan.pass_lds, b->stream));
+// Plans of a multi-wave class: one team per block; the pass takes as many
+// co-resident blocks as there is work, the Krotov pass splits the co-resident
+// blocks by the cost model.
+int plan_wide(tk_batch *b, WideClass &w) {
+  size_t lds = 0;
+  for (int i : w.idx) {
+    const Member &m = *b->mem[i];
+    lds = std::max(lds, tk::block_lds_bytes(*m.c->var, 1, std::max(m.kbuf_fw, m.kbuf_bw), 0));
+  }
+  if (lds > tk::kLdsBytes) return bfail(b, TK_EUNSUPPORTED, "team term vectors do not fit in LDS");
+  w.lds = lds;
+  int occ = tk::kLdsBytes;
+  for (const void *k : {w.pass_fw, w.pass_bw, w.krotov}) {
+    TK_BHIP(b, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(lds)));
+    int o = 0;
+    TK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, tk::kWave * w.G, lds));
+    occ = std::min(occ, o);
+  }
+  if (occ < 1) return bfail(b, TK_EUNSUPPORTED, "team kernels do not fit a compute unit");
+  const int capacity = occ * b->n_cu;
+  if (capacity < static_cast<int>(w.idx.size()))
+    return bfail(b, TK_EUNSUPPORTED, "instances do not fit one co-resident grid");
+  w.pass_blocks = std::max(1, std::min(capacity, w.n_items));
+  w.nblocks = split_blocks(b, w.idx, capacity, 1, 0.0, nullptr);
   return TK_OK;
 }
 
-int launch_krotov(tk_batch *b) {
+// which: 0 every instance, 1 one-wave instances only
+int launch_pass(tk_batch *b, int dir, int which = 0) {
+  if (!b->narrow.empty()) {
+    tk::BatchArgs a = batch_args(b);
+    void *args[] = {&a};
+    TK_BHIP(b, hipLaunchKernel(dir == 0 ? b->kern.pass_fw : b->kern.pass_bw,
+                               dim3(b->plan.pass_blocks), dim3(tk::kWave * b->plan.pass_wpb), args,
+                               b->plan.pass_lds, b->stream));
+  }
+  for (auto &wp : b->wide) {
+    if (which == 1) break;
+    WideClass &w = *wp;
+    tk::BatchArgs a = wide_args(b, w);
+    void *args[] = {&a};
+    TK_BHIP(b, hipLaunchKernel(dir == 0 ? w.pass_fw : w.pass_bw, dim3(w.pass_blocks),
+                               dim3(tk::kWave * w.G), args, w.lds, b->stream));
+  }
+  return TK_OK;
+}
+
+// which: 0 every instance, 1 one-wave instances only, 2 multi-wave ones only
+int launch_krotov(tk_batch *b, int which = 0) {
   tk::BatchArgs a = batch_args(b);
   void *args[] = {&a};
   TK_BHIP(b, hipLaunchKernel(b->kern.fill, dim3(static_cast<unsigned>(b->mem.size())), dim3(256),
                              args, 0, b->stream));
   // blocks are co-resident by the occupancy check of the plan; a block that
   // waits past the spin limit aborts the pass with an error instead of hanging
-  TK_BHIP(b, hipLaunchKernel(b->kern.krotov, dim3(b->plan.kro_blocks),
-                             dim3(tk::kWave * b->plan.kro_wpb), args, b->plan.kro_lds, b->stream));
+  if (!b->narrow.empty() && which != 2)
+    TK_BHIP(b, hipLaunchKernel(b->kern.krotov, dim3(b->plan.kro_blocks),
+                               dim3(tk::kWave * b->plan.kro_wpb), args, b->plan.kro_lds, b->stream));
+  for (auto &wp : b->wide) {
+    if (which == 1) break;
+    WideClass &w = *wp;
+    tk::BatchArgs wa = wide_args(b, w);
+    void *wargs[] = {&wa};
+    TK_BHIP(b, hipLaunchKernel(w.krotov, dim3(w.kro_blocks), dim3(tk::kWave * w.G), wargs, w.lds,
+                               b->stream));
+  }
   return TK_OK;
 }
 
@@ -301,14 +386,44 @@ int finalize(tk_batch *b) {
   TK_BHIP(b, hipMemset(b->rec_count_dev.p, 0, sizeof(unsigned long long)));
   b->inst.assign(n, tk::BatchInstance{});
   b->traj_steps = 0;
+  b->narrow.clear();
+  b->wide.clear();
   std::vector<std::pair<double, int2>> items;
+  std::vector<std::vector<std::pair<double, int2>>> witems;
   for (size_t i = 0; i < n; ++i) {
     Member &m = *b->mem[i];
     tk_ctx *c = m.c;
     const tk::Variant &v = *c->var;
-    const size_t vec = static_cast<size_t>(v.R) * tk::kWave * cplx_bytes(b->precision);
+    m.G = v.G;
+    const size_t cb = cplx_bytes(b->precision);
+    const size_t vec = static_cast<size_t>(v.R) * tk::kWave * v.G * cb;
     const int ncx = v.NC > 0 ? v.NC : 1;
-    TK_BHIP(b, c->chi.ensure(static_cast<size_t>(c->nt) * m.M * c->d * cplx_bytes(b->precision)));
+    size_t wc = 0;  // class of the member among the multi-wave ones
+    if (v.G == 1) {
+      b->narrow.push_back(static_cast<int>(i));
+      // every costate of the pass is kept
+      TK_BHIP(b, c->chi.ensure(static_cast<size_t>(c->nt) * m.M * c->d * cb));
+    } else {
+      while (wc < b->wide.size() && b->wide[wc]->G != v.G) ++wc;
+      if (wc == b->wide.size()) {
+        auto w = std::make_unique<WideClass>();
+        w->G = v.G;
+        w->pass_fw = v.G == 2 ? b->kern.wpass_fw : b->kern.wpass_fw8;
+        w->pass_bw = v.G == 2 ? b->kern.wpass_bw : b->kern.wpass_bw8;
+        w->krotov = v.G == 2 ? b->kern.wkrotov : b->kern.wkrotov8;
+        if (!w->pass_fw || !w->pass_bw || !w->krotov)
+          return bfail(b, TK_EUNSUPPORTED, "no batched kernels for this team size");
+        b->wide.push_back(std::move(w));
+        witems.emplace_back();
+      }
+      b->wide[wc]->idx.push_back(static_cast<int>(i));
+      // one segment of costates, and the backward pass's checkpoints
+      const int nseg = (c->nt + tk::kSegment - 1) / tk::kSegment;
+      TK_BHIP(b, m.seg.ensure(static_cast<size_t>(tk::kSegment + 1) * m.M * c->d * cb));
+      TK_BHIP(b, m.ck_psi.ensure(std::max(nseg - 1, 1) * static_cast<size_t>(m.M) * vec));
+      TK_BHIP(b, m.ck_meta.ensure(std::max(nseg - 1, 1) * static_cast<size_t>(m.M) *
+                                  sizeof(tk::TrajMeta)));
+    }
     TK_BHIP(b, c->tau.ensure(static_cast<size_t>(2) * m.M * sizeof(double)));
     TK_BHIP(b, c->u_new_dev.ensure(static_cast<size_t>(tk::kMaxCtrl) * c->nt * sizeof(double)));
     TK_BHIP(b, hipMemset(c->u_new_dev.p, 0, static_cast<size_t>(tk::kMaxCtrl) * c->nt * sizeof(double)));
@@ -329,8 +444,13 @@ int finalize(tk_batch *b) {
       a->rec_cap = 0;
       a->rec_count = b->rec_count_dev.as<unsigned long long>();
       a->err = b->err_dev.as<int>();
-      a->chi = c->chi.p;
+      a->chi = v.G == 1 ? c->chi.p : m.seg.p;
       a->spin_limit = 1ll << 22;
+    }
+    if (v.G > 1) {
+      I.bw.seg_len = tk::kSegment;
+      I.bw.ck_psi = m.ck_psi.p;
+      I.bw.ck_meta = m.ck_meta.as<tk::TrajMeta>();
     }
     I.fw.kbuf = m.kbuf_fw;
     I.bw.kbuf = m.kbuf_bw;
@@ -342,27 +462,46 @@ int finalize(tk_batch *b) {
     I.fw.lam = c->lam_dev.as<double>();
     I.bw.tau_in = c->tau.as<double>();
     I.variant = m.variant;
+    I.G = v.G;
     I.ncx = ncx;
     I.psi = m.psi.p;
     I.meta = m.meta.as<tk::TrajMeta>();
     I.tslots = m.tslots.as<unsigned long long>();
+    auto &list = v.G == 1 ? items : witems[wc];
     for (int k = 0; k < m.M; ++k)
-      items.push_back({c->nt * m.step_cost, int2{static_cast<int>(i), k}});
+      list.push_back({c->nt * m.step_cost, int2{static_cast<int>(i), k}});
     b->traj_steps += 2ll * m.M * c->nt;
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [](const auto &x, const auto &y) { return x.first > y.first; });
-  std::vector<int2> it(items.size());
-  for (size_t q = 0; q < items.size(); ++q) it[q] = items[q].second;
-  TK_BHIP(b, b->items_dev.ensure(it.size() * sizeof(int2)));
-  TK_BHIP(b, hipMemcpy(b->items_dev.p, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice));
-  int rc = plan_pass(b, tk::kWavesPerBlock);
-  if (rc == TK_EUNSUPPORTED) rc = plan_pass(b, 1);
-  if (rc) return rc == TK_EUNSUPPORTED ? bfail(b, rc, "pass term vectors do not fit in LDS") : rc;
-  const double sync_cost = 0.0;
-  rc = plan_krotov(b, tk::kWavesPerBlock, 1.0, sync_cost);
-  if (rc == TK_EUNSUPPORTED) rc = plan_krotov(b, 1, 1.0, sync_cost);
-  if (rc) return rc == TK_EUNSUPPORTED ? bfail(b, rc, "instances do not fit one co-resident grid") : rc;
+  // work lists, costliest first
+  auto upload_items = [&](std::vector<std::pair<double, int2>> &src, DevBuf &dev) -> int {
+    std::stable_sort(src.begin(), src.end(),
+                     [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<int2> it(src.size());
+    for (size_t q = 0; q < src.size(); ++q) it[q] = src[q].second;
+    if (it.empty()) return TK_OK;
+    TK_BHIP(b, dev.ensure(it.size() * sizeof(int2)));
+    TK_BHIP(b, hipMemcpy(dev.p, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice));
+    return TK_OK;
+  };
+  int rc = upload_items(items, b->items_dev);
+  if (rc) return rc;
+  for (size_t q = 0; q < b->wide.size(); ++q) {
+    b->wide[q]->n_items = static_cast<int>(witems[q].size());
+    if ((rc = upload_items(witems[q], b->wide[q]->items_dev))) return rc;
+    if ((rc = plan_wide(b, *b->wide[q]))) return rc;
+  }
+  if (!b->narrow.empty()) {
+    rc = plan_pass(b, tk::kWavesPerBlock);
+    if (rc == TK_EUNSUPPORTED) rc = plan_pass(b, 1);
+    if (rc) return rc == TK_EUNSUPPORTED ? bfail(b, rc, "pass term vectors do not fit in LDS") : rc;
+    const double sync_cost = 0.0;
+    rc = plan_krotov(b, tk::kWavesPerBlock, 1.0, sync_cost);
+    if (rc == TK_EUNSUPPORTED) rc = plan_krotov(b, 1, 1.0, sync_cost);
+    if (rc)
+      return rc == TK_EUNSUPPORTED ? bfail(b, rc, "instances do not fit one co-resident grid") : rc;
+  } else if ((rc = upload_tables(b))) {
+    return rc;
+  }
   b->ready = true;
   return TK_OK;
 }
@@ -376,7 +515,7 @@ int time_krotov(tk_batch *b, double *ms, std::vector<double> *inst_us) {
   TK_BHIP(b, hipMemcpy(b->t_begin_dev.p, &never, sizeof(never), hipMemcpyHostToDevice));
   TK_BHIP(b, hipMemcpy(b->t_end_dev.p, t_end.data(), n * sizeof(unsigned long long),
                        hipMemcpyHostToDevice));
-  int rc = timed(b, [&] { return launch_krotov(b); }, ms);
+  int rc = timed(b, [&] { return launch_krotov(b, 1); }, ms);
   if (rc) return rc;
   if ((rc = check_errors(b))) return rc;
   unsigned long long t0 = 0;
@@ -389,19 +528,24 @@ int time_krotov(tk_batch *b, double *ms, std::vector<double> *inst_us) {
   return TK_OK;
 }
 
-// Autotuner: times the costate pass for each waves-per-block choice, and the
-// Krotov pass for each waves-per-block choice with two block splits -- one from
-// the cost model, one from the per-instance times measured on the first run --
-// and keeps the fastest.  The
-// passes are deterministic and independent of the tile shape, so the repeated
-// runs leave the same results as one run.
+// Autotuner of the one-wave instances: times their costate pass for each
+// waves-per-block choice, and their Krotov pass for each waves-per-block choice
+// with two block splits -- one from the cost model, one from the per-instance
+// times measured on the first run -- and keeps the fastest.  The passes are
+// deterministic and independent of the tile shape, so the repeated runs leave
+// the same results as one run.  The multi-wave classes (one team per block)
+// keep the cost-model split.
 int autotune(tk_batch *b) {
+  if (b->narrow.empty()) {  // multi-wave classes keep their cost-model plans
+    b->tuned = true;
+    return TK_OK;
+  }
   double best = 1e300;
   int best_wpb = 0;
   for (int wpb : {4, 2, 1}) {
     if (plan_pass(b, wpb)) continue;
     double ms = 0.0;
-    int rc = timed(b, [&] { return launch_pass(b, 1); }, &ms);
+    int rc = timed(b, [&] { return launch_pass(b, 1, 1); }, &ms);
     if (rc) return rc;
     if (ms < best) {
       best = ms;
@@ -418,7 +562,8 @@ int autotune(tk_batch *b) {
   int kw = 0;
   std::vector<int> kblocks;
   double unit = 0.0;  // the cheapest instance's modelled step: scale of the exchange weight
-  for (const auto &m : b->mem) unit = unit == 0.0 ? m->step_cost : std::min(unit, m->step_cost);
+  for (int i : b->narrow)
+    unit = unit == 0.0 ? b->mem[i]->step_cost : std::min(unit, b->mem[i]->step_cost);
   for (int wpb : {4, 2, 1}) {
     std::vector<double> cost;
     for (int round = 0; round < 2; ++round) {
@@ -434,9 +579,10 @@ int autotune(tk_batch *b) {
       }
       // measured time of one trajectory-step (with its share of the exchange)
       cost.assign(b->mem.size(), 0.0);
-      for (size_t i = 0; i < b->mem.size(); ++i) {
+      for (size_t q = 0; q < b->narrow.size(); ++q) {
+        const int i = b->narrow[q];
         const Member &m = *b->mem[i];
-        const double tw = std::ceil(static_cast<double>(m.M) / (b->plan.nblocks[i] * wpb));
+        const double tw = std::ceil(static_cast<double>(m.M) / (b->plan.nblocks[q] * wpb));
         cost[i] = inst_us[i] / (m.c->nt * tw);
       }
     }
@@ -529,14 +675,16 @@ int tk_batch_add(tk_batch *b, uint32_t instance_id, int64_t d, const tk_csr *H0,
   auto m = std::make_unique<Member>();
   int rc = tk_create(&m->c, b->device, b->precision);
   if (rc) return bfail(b, rc, "context creation failed");
-  m->c->single_wave_only = true;  // the batched kernels run one-wave shapes
   if ((rc = tk_set_system(m->c, d, H0, n_ctrl, H_ctrl, n_jump, L_jump)) ||
       (rc = tk_set_states(m->c, psi0, psi_tgt)) ||
       (rc = tk_set_pulses(m->c, nt, T, u, S, lambda)))
     return bfail(b, rc, std::string("instance: ") + tk_last_error(m->c));
-  if (m->c->var->G != 1 || shape_index(m->c->var) < 0 || shape_index(m->c->var) > 3)
-    return bfail(b, TK_EUNSUPPORTED,
-                 "kernel shape not available in the batched kernels (one-wave shapes, d <= 256)");
+  {
+    const int si = shape_index(m->c->var), G = m->c->var->G;
+    const bool ok = (G == 1 && si >= 0 && si <= 3) || (G == 2 && (si == 4 || si == 5)) ||
+                    (G == 8 && si == 6 && b->precision == TK_FP32);
+    if (!ok) return bfail(b, TK_EUNSUPPORTED, "kernel shape not available in the batched kernels");
+  }
   m->id = instance_id;
   m->M = M;
   m->seed = seed;
@@ -571,7 +719,8 @@ int tk_batch_krotov_iterate(tk_batch *b, uint64_t first_iteration, int32_t n_ite
     if (!b->tuned) {
       // the first iteration runs step by step while the autotuner picks tiles
       if ((rc = launch_pass(b, 1))) return rc;
-      if ((rc = autotune(b))) return rc;
+      if ((rc = autotune(b))) return rc;  // runs the one-wave instances' Krotov pass
+      if (!b->wide.empty() && (rc = launch_krotov(b, 2))) return rc;
       if ((rc = launch_tail(b, 1))) return rc;
       if ((rc = build_graph(b))) return rc;
     } else {

@@ -869,6 +869,24 @@ __device__ __forceinline__ size_t terms_bytes(int kbuf) {
 // One trajectory of a plain pass over all nt steps: DIR 0 forward from
 // psi_start (final normalised state and tau_k = <tgt|psi_hat_k(T)>), DIR 1
 // backward from the target, storing chi_k(t_j) = tau_k chi_hat_k(t_j).
+// chi_k(t_j) = tau_k psi / ||psi|| for the rows < d (costate layout [M][d]
+// at `out`, the trajectory's row).
+template <typename real, int R, int G>
+__device__ __forceinline__ void store_costate(cx<real> *out, int d, const cx<real> (&psi)[R],
+                                              double nrm2, double tau_re, double tau_im,
+                                              const Team<G> &tm) {
+  const double inv = 1.0 / sqrt(nrm2);
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int row = tm.gl + Team<G>::kLanes * m;
+    if (row < d) {
+      const double px = psi[m].x * inv, py = psi[m].y * inv;
+      out[row] = cx<real>{static_cast<real>(tau_re * px - tau_im * py),
+                          static_cast<real>(tau_re * py + tau_im * px)};
+    }
+  }
+}
+
 template <typename real, int R, int WS, int NC, int G, int DIR>
 __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                                 const Terms<real, R, G> &T, int k, const Stream &rng, const Team<G> &tm) {
@@ -908,19 +926,16 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
     op.set_pulses(uj, a.wc);
     const StepPlan p = plan_step(a, uj, khint);
     advance_step<real, R, WS, NC, G, DIR>(op, a, T, psi, st, rng, j, p, k, tm);
-    if (DIR == 1) {
-      // chi_k(t_j) = tau_k chi_hat_k(t_j)
-      const double inv = 1.0 / sqrt(st.nrm2);
-      const size_t base = (static_cast<size_t>(j) * a.M + k) * a.d;
+    if (DIR == 1 && a.seg_len == 0)
+      store_costate<real, R, G>(chi + (static_cast<size_t>(j) * a.M + k) * a.d, a.d, psi,
+                                st.nrm2, tau_re, tau_im, tm);
+    if (DIR == 1 && a.seg_len > 0 && j % a.seg_len == 0 && j > 0) {
+      // checkpoint: the state at t_j, where segment j / seg_len - 1 ends
+      const size_t c = static_cast<size_t>(j / a.seg_len - 1) * a.M + k;
+      cx<real> *ck = static_cast<cx<real> *>(a.ck_psi) + c * R * Team<G>::kLanes;
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int row = tm.gl + Team<G>::kLanes * m;
-        if (row < a.d) {
-          const double px = psi[m].x * inv, py = psi[m].y * inv;
-          chi[base + row] = cx<real>{static_cast<real>(tau_re * px - tau_im * py),
-                                     static_cast<real>(tau_re * py + tau_im * px)};
-        }
-      }
+      for (int m = 0; m < R; ++m) ck[tm.gl + Team<G>::kLanes * m] = psi[m];
+      if (tm.leader()) a.ck_meta[c] = st;
     }
   }
   if (DIR == 0) {

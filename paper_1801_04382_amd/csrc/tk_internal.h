@@ -32,6 +32,11 @@ constexpr int kErrJumpLoop = 8;      // more jumps in one step than allowed
 constexpr uint64_t kSlotEmpty = 0xFFF7DEADBEEF5A5Aull;
 
 // Per-trajectory bookkeeping of the MCWF clock (kept in LDS by the Krotov pass).
+// Costate segment of the batched multi-wave instances: their backward pass
+// keeps checkpoints every kSegment steps and the Krotov pass recomputes the
+// costates of a segment from its checkpoint before it needs them.
+constexpr int kSegment = 64;
+
 struct TrajMeta {
   double nrm2;  // squared norm of the unnormalised state
   double r;     // current threshold
@@ -80,7 +85,13 @@ struct PassArgs {
   void *psiT;               // [M][d] normalised final states (bulk), may be null
   double *tau_out;          // [2M] overlaps <tgt|psi_hat(T)>, may be null
   const double *tau_in;     // [2M] costate weights (backward pass)
-  void *chi;                // [nt][M][d] costates (bulk precision)
+  void *chi;                // [nt][M][d] costates (bulk precision); in a batched
+                            // multi-wave instance [kSegment + 1][M][d], one segment
+  // costate checkpoints (backward pass of a batched multi-wave instance): the
+  // unnormalised backward state and its clock at t_{(s+1) kSegment}, s < nseg - 1
+  int seg_len;              // 0: the backward pass stores every chi(t_j); else kSegment
+  void *ck_psi;             // [nseg - 1][M][64 G R] (bulk)
+  TrajMeta *ck_meta;        // [nseg - 1][M]
   tk_jump *rec;             // [rec_cap] jump records
   unsigned long long *rec_count;
   long long rec_cap;
@@ -120,7 +131,8 @@ struct BatchInstance {
   int block0;         // first block of the batched Krotov launch serving it
   int nblocks;        // blocks serving it
   int ncx;            // shares per trajectory and step: the shape's NC (at least 1)
-  void *psi;          // [M][64 R] states between steps (bulk)
+  int G;              // waves per trajectory of the shape (1: one-wave kernels)
+  void *psi;          // [M][64 G R] states between steps (bulk)
   TrajMeta *meta;     // [M] MCWF clocks between steps
   unsigned long long *tslots;  // [nt][M][NCX] per-trajectory partials s_ik (FP64 bits)
 };
@@ -130,9 +142,12 @@ struct BatchArgs {
   const BatchInstance *inst;
   int n_inst;
   int wave_lds;          // LDS bytes per wave of the batched plain passes
-  const int2 *items;     // (instance, trajectory) work of the plain passes
+  const int2 *items;     // (instance, trajectory) work of the plain passes (one-wave shapes)
   int n_items;
-  const int *block_inst; // [blocks] instance of each block of the Krotov launch
+  const int *block_inst; // [blocks] instance of each block of the Krotov launch (one-wave)
+  const int2 *witems;    // the same for the instances of multi-wave shapes (one team a block)
+  int n_witems;
+  const int *wblock_inst;
   uint64_t *iteration;   // iteration of the passes being run (device counter)
   double *J_hist;        // [n_inst][kBatchHistory] J_T by iteration
   unsigned long long *t_begin;  // earliest block start of the Krotov launch (constant clock)
@@ -172,6 +187,10 @@ const void *grad_reduce_kernel();
 // of (R, WS, NC) in variants() among those of the same precision.
 struct BatchKernels {
   const void *pass_fw, *pass_bw, *krotov, *fill, *functional, *finish;
+  // multi-wave shapes, one team per block: two-wave teams, and eight-wave teams
+  // (FP32 only; null in FP64)
+  const void *wpass_fw, *wpass_bw, *wkrotov;
+  const void *wpass_fw8 = nullptr, *wpass_bw8 = nullptr, *wkrotov8 = nullptr;
 };
 BatchKernels batch_kernels(int precision);
 

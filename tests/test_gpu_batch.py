@@ -150,3 +150,45 @@ def test_batch_error_paths(tk):
         with pytest.raises(tk.TkError) as e:
             b.add(w, instance_id=4)
         assert e.value.code == tk.TK_ESTATE
+
+
+def test_batch_multiwave_segments_match_oracle(tk):
+    """d = 216 in FP64 runs the two-wave batched kernels, whose Krotov pass
+    recomputes the costates segment by segment (64 steps) from the backward
+    pass's checkpoints: nt = 150 spans two full segments and a ragged one.  J_T
+    and pulses against the oracle at the FP64 bars, beside a one-wave instance."""
+    big = config_workload("chain3_fock2", M=3, nt=150, seed=5).replace(instance=7)
+    small = config_workload("chain2_fock2", M=4, nt=70, seed=1).replace(instance=2)
+    with tk.Batch(precision="fp64") as b:
+        b.add(big)
+        b.add(small)
+        J = b.krotov_iterate(2)
+        u_big = b.get_pulses(0)
+        u_small = b.get_pulses(1)
+    for w, Jw, uw in ((big, J[0], u_big), (small, J[1], u_small)):
+        ref = oracle_run(w, 2)
+        say("  segments", w.name, "d", w.dim, "nt", w.nt, "J gpu", Jw.tolist(), "oracle", ref.J_T)
+        assert max_abs(Jw, ref.J_T) <= TOL
+        assert max_abs(uw, ref.u[-1]) <= TOL
+
+
+def test_batch_chain_of_four_nodes_fp32(tk):
+    """d = 1296 (eight-wave teams, costate segments) in an FP32 batch: J_T
+    against the oracle at the FP32 bar, and pulses against the single-system
+    path (same kernels for the step; only the summation order of the update
+    differs)."""
+    w = config_workload("chain4_fock2", M=4, nt=70, seed=1).replace(instance=0)
+    ref = oracle_run(w, 1)
+    with tk.Batch(precision="fp32") as b:
+        b.add(w)
+        J = b.krotov_iterate(1)[0]
+        ub = b.get_pulses(0)
+    with tk.Context(precision="fp32") as ctx:
+        ctx.load(w)
+        Js, _, _ = ctx.krotov_iterate(w.M, w.seed, 1, rec_cap=0)
+        us = ctx.get_pulses()
+    say("  d=1296 batch J", J.tolist(), "single", Js.tolist(), "oracle", ref.J_T,
+        "max|du| batch-single", max_abs(ub, us))
+    assert max_abs(J, ref.J_T) <= 1e-4
+    assert max_abs(J, Js) <= 1e-10
+    assert max_abs(ub, us) <= 1e-10
