@@ -121,7 +121,8 @@ def bench_batched(n_inst: int, steps: int, nodes, check: int) -> dict:
             "graph_iteration_ms": info["last_iteration_ms"],
             "launch": {k: info[k] for k in ("pass_waves_per_block", "pass_blocks",
                                              "krotov_waves_per_block", "krotov_blocks",
-                                             "tuned_pass_ms", "tuned_krotov_ms")},
+                                             "tuned_pass_ms", "tuned_krotov_ms", "multiwave_instances",
+                                             "multiwave_krotov_blocks", "tuned_multiwave_krotov_ms")},
             "max_abs_dJ_fp32_vs_fp64": max(dJ) if dJ else None,
             "dJ_checked_instances": len(dJ)}
 

@@ -284,6 +284,9 @@ typedef struct tk_batch_info {
   double tuned_pass_ms;            /* best costate pass seen by the tuner   */
   double tuned_krotov_ms;          /* best Krotov pass seen by the tuner    */
   int64_t traj_steps_per_iteration; /* sum over instances of 2 M nt         */
+  int32_t multiwave_instances;     /* instances of multi-wave shapes (one   */
+  int32_t multiwave_krotov_blocks; /* team a block, costate segments)      */
+  double tuned_multiwave_krotov_ms; /* their Krotov pass at the chosen split */
 } tk_batch_info;
 
 /* Create an empty batch on `device` in `precision` (as tk_create). */

@@ -462,10 +462,16 @@ __device__ void wide_recompute(const BatchInstance &I, int w, int nteam, int s, 
       store_costate<real, R, G>(seg + (static_cast<size_t>(e - j0) * M + k) * d, d, psi,
                                 st.nrm2, tau_re, tau_im, tm);
     OrderHint hint;
+    double un[NCX];  // pulses of the next step, loaded one step ahead
+#pragma unroll
+    for (int i = 0; i < NCX; ++i) un[i] = ab.u[static_cast<size_t>(i) * nt + e - 1];
     for (int j = e - 1; j >= j0; --j) {
       double uj[NCX];
 #pragma unroll
-      for (int i = 0; i < NCX; ++i) uj[i] = ab.u[static_cast<size_t>(i) * nt + j];
+      for (int i = 0; i < NCX; ++i) uj[i] = un[i];
+      if (j > j0)
+#pragma unroll
+        for (int i = 0; i < NCX; ++i) un[i] = ab.u[static_cast<size_t>(i) * nt + j - 1];
       opb.set_pulses(uj, ab.wc);
       const StepPlan p = plan_step(ab, uj, hint);
       advance_step<real, R, WS, NC, G, 1>(opb, ab, T, psi, st, rng, j, p, k, tm);

@@ -35,6 +35,7 @@ struct Member {
   int G = 1;               // waves per trajectory of its shape
   DevBuf psi, meta, tslots;
   DevBuf seg, ck_psi, ck_meta;  // multi-wave shapes: costate segment and checkpoints
+  DevBuf tau_save;              // the overlaps the multi-wave Krotov pass starts from
   ~Member() {
     if (c) tk_destroy(c);
   }
@@ -54,7 +55,7 @@ struct WideClass {
   std::vector<int> idx;  // member indices
   const void *pass_fw = nullptr, *pass_bw = nullptr, *krotov = nullptr;
   DevBuf items_dev, block_inst_dev;
-  int n_items = 0, pass_blocks = 0, kro_blocks = 0;
+  int n_items = 0, pass_blocks = 0, kro_blocks = 0, kro_capacity = 0;
   size_t lds = 0;
   std::vector<int> nblocks;  // per entry of idx
 };
@@ -82,7 +83,7 @@ struct tk_batch {
   std::vector<tk::BatchInstance> inst;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  double last_iter_ms = 0.0, tuned_pass_ms = 0.0, tuned_krotov_ms = 0.0;
+  double last_iter_ms = 0.0, tuned_pass_ms = 0.0, tuned_krotov_ms = 0.0, tuned_wide_krotov_ms = 0.0;
   int64_t traj_steps = 0;
 };
 
@@ -281,6 +282,7 @@ int plan_wide(tk_batch *b, WideClass &w) {
   if (capacity < static_cast<int>(w.idx.size()))
     return bfail(b, TK_EUNSUPPORTED, "instances do not fit one co-resident grid");
   w.pass_blocks = std::max(1, std::min(capacity, w.n_items));
+  w.kro_capacity = capacity;
   w.nblocks = split_blocks(b, w.idx, capacity, 1, 0.0, nullptr);
   return TK_OK;
 }
@@ -508,14 +510,14 @@ int finalize(tk_batch *b) {
 
 // One Krotov pass with the current plan: its duration (ms) and, per instance,
 // the time from the launch's first block start to the instance's last block end.
-int time_krotov(tk_batch *b, double *ms, std::vector<double> *inst_us) {
+int time_krotov(tk_batch *b, double *ms, std::vector<double> *inst_us, int which = 1) {
   const size_t n = b->mem.size();
   const unsigned long long never = ~0ull;
   std::vector<unsigned long long> t_end(n, 0ull);
   TK_BHIP(b, hipMemcpy(b->t_begin_dev.p, &never, sizeof(never), hipMemcpyHostToDevice));
   TK_BHIP(b, hipMemcpy(b->t_end_dev.p, t_end.data(), n * sizeof(unsigned long long),
                        hipMemcpyHostToDevice));
-  int rc = timed(b, [&] { return launch_krotov(b, 1); }, ms);
+  int rc = timed(b, [&] { return launch_krotov(b, which); }, ms);
   if (rc) return rc;
   if ((rc = check_errors(b))) return rc;
   unsigned long long t0 = 0;
@@ -593,6 +595,56 @@ int autotune(tk_batch *b) {
   if ((rc = upload_tables(b))) return rc;
   b->tuned_krotov_ms = kbest;
   b->tuned = true;
+  return TK_OK;
+}
+
+// Krotov pass of the multi-wave classes: run with the cost-model split, then
+// with a split from the per-trajectory-step times that run measured; the
+// faster plan is kept (the runs give identical results).  Their pass reads the
+// overlaps tau_k of the previous forward pass (the costate weights of the
+// segments it recomputes) and overwrites them at its end, so the second run
+// starts from a saved copy.
+int autotune_wide(tk_batch *b) {
+  if (b->wide.empty()) return TK_OK;
+  for (auto &wp : b->wide)
+    for (int i : wp->idx) {
+      Member &m = *b->mem[i];
+      const size_t bytes = static_cast<size_t>(2) * m.M * sizeof(double);
+      TK_BHIP(b, m.tau_save.ensure(bytes));
+      TK_BHIP(b, hipMemcpyAsync(m.tau_save.p, m.c->tau.p, bytes, hipMemcpyDeviceToDevice,
+                                b->stream));
+    }
+  double ms0 = 0.0;
+  std::vector<double> inst_us;
+  int rc = time_krotov(b, &ms0, &inst_us, 2);
+  if (rc) return rc;
+  for (auto &wp : b->wide)
+    for (int i : wp->idx) {
+      Member &m = *b->mem[i];
+      TK_BHIP(b, hipMemcpyAsync(m.c->tau.p, m.tau_save.p, static_cast<size_t>(2) * m.M * sizeof(double),
+                                hipMemcpyDeviceToDevice, b->stream));
+    }
+  std::vector<double> cost(b->mem.size(), 0.0);
+  std::vector<std::vector<int>> old;
+  for (auto &wp : b->wide) {
+    WideClass &w = *wp;
+    for (size_t q = 0; q < w.idx.size(); ++q) {
+      const int i = w.idx[q];
+      const Member &m = *b->mem[i];
+      const double tw = std::ceil(static_cast<double>(m.M) / w.nblocks[q]);
+      cost[i] = inst_us[i] / (m.c->nt * tw);
+    }
+    old.push_back(w.nblocks);
+    w.nblocks = split_blocks(b, w.idx, w.kro_capacity, 1, 0.0, &cost);
+  }
+  if ((rc = upload_tables(b))) return rc;
+  double ms1 = 0.0;
+  if ((rc = time_krotov(b, &ms1, &inst_us, 2))) return rc;
+  if (ms1 > ms0) {  // the model split was faster
+    for (size_t q = 0; q < b->wide.size(); ++q) b->wide[q]->nblocks = old[q];
+    if ((rc = upload_tables(b))) return rc;
+  }
+  b->tuned_wide_krotov_ms = std::min(ms0, ms1);
   return TK_OK;
 }
 
@@ -720,7 +772,7 @@ int tk_batch_krotov_iterate(tk_batch *b, uint64_t first_iteration, int32_t n_ite
       // the first iteration runs step by step while the autotuner picks tiles
       if ((rc = launch_pass(b, 1))) return rc;
       if ((rc = autotune(b))) return rc;  // runs the one-wave instances' Krotov pass
-      if (!b->wide.empty() && (rc = launch_krotov(b, 2))) return rc;
+      if ((rc = autotune_wide(b))) return rc;  // runs the multi-wave instances' Krotov pass
       if ((rc = launch_tail(b, 1))) return rc;
       if ((rc = build_graph(b))) return rc;
     } else {
@@ -769,6 +821,13 @@ int tk_batch_get_info(const tk_batch *b, tk_batch_info *out) {
   out->tuned_pass_ms = b->tuned_pass_ms;
   out->tuned_krotov_ms = b->tuned_krotov_ms;
   out->traj_steps_per_iteration = b->traj_steps;
+  out->multiwave_instances = 0;
+  out->multiwave_krotov_blocks = 0;
+  for (const auto &w : b->wide) {
+    out->multiwave_instances += static_cast<int32_t>(w->idx.size());
+    out->multiwave_krotov_blocks += w->kro_blocks;
+  }
+  out->tuned_multiwave_krotov_ms = b->tuned_wide_krotov_ms;
   return TK_OK;
 }
 

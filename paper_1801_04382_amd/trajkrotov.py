@@ -74,7 +74,10 @@ class tk_batch_info(ctypes.Structure):
                 ("krotov_blocks", ctypes.c_int32), ("autotuned", ctypes.c_int32),
                 ("last_iteration_ms", ctypes.c_double), ("tuned_pass_ms", ctypes.c_double),
                 ("tuned_krotov_ms", ctypes.c_double),
-                ("traj_steps_per_iteration", ctypes.c_int64)]
+                ("traj_steps_per_iteration", ctypes.c_int64),
+                ("multiwave_instances", ctypes.c_int32),
+                ("multiwave_krotov_blocks", ctypes.c_int32),
+                ("tuned_multiwave_krotov_ms", ctypes.c_double)]
 
 
 JUMP_DTYPE = np.dtype([("instance", np.int32), ("traj", np.int32), ("step", np.int32),
