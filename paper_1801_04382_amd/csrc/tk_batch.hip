@@ -232,7 +232,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     }
     block_sync_lds();  // every wave has used the previous step's s_upd
     if (lb == 0 && j > 0 && threadIdx.x < NCX)
-      a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + j - 1] = u_prev[threadIdx.x];
+      a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + j - 1] = pick(u_prev, threadIdx.x);
     if (wib == 0) {
       double acc[NCX];
       const bool ok = a.n_ctrl == 0 ||
@@ -306,7 +306,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     }
   }
   if (lb == 0 && threadIdx.x < NCX)
-    a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + a.nt - 1] = u_prev[threadIdx.x];
+    a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + a.nt - 1] = pick(u_prev, threadIdx.x);
   // ---- tau_k = <tgt|psi_hat_k(T)> ----
   for (int k = w; k < a.M; k += nw) {
     const double inv = 1.0 / sqrt(meta_g[k].nrm2);
@@ -586,7 +586,7 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
       }
       block_sync_lds();  // every wave has used the previous step's s_upd
       if (lb == 0 && j > 0 && threadIdx.x < NCX)
-        a.u_new[static_cast<size_t>(threadIdx.x) * nt + j - 1] = u_prev[threadIdx.x];
+        a.u_new[static_cast<size_t>(threadIdx.x) * nt + j - 1] = pick(u_prev, threadIdx.x);
       if (threadIdx.x < kWave) {
         double acc[NCX];
         const bool ok = a.n_ctrl == 0 ||
@@ -638,7 +638,7 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
     }
   }
   if (lb == 0 && threadIdx.x < NCX)
-    a.u_new[static_cast<size_t>(threadIdx.x) * nt + nt - 1] = u_prev[threadIdx.x];
+    a.u_new[static_cast<size_t>(threadIdx.x) * nt + nt - 1] = pick(u_prev, threadIdx.x);
   // ---- tau_k = <tgt|psi_hat_k(T)> ----
   for (int k = w; k < M; k += nteam) {
     const double inv = 1.0 / sqrt(meta_g[k].nrm2);

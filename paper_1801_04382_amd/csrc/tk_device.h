@@ -64,6 +64,17 @@ __device__ __forceinline__ void wave_sum2(double &x, double &y) {
   y = (read_lane(y, 0) + read_lane(y, 16)) + (read_lane(y, 32) + read_lane(y, 48));
 }
 
+// v[i] for a lane-dependent i < N, by comparisons (indexing a register array
+// with a lane value would move the array to scratch memory).
+template <int N>
+__device__ __forceinline__ double pick(const double (&v)[N], int i) {
+  double r = v[0];
+#pragma unroll
+  for (int q = 1; q < N; ++q)
+    if (i == q) r = v[q];
+  return r;
+}
+
 // Wave sums of the first N entries of v, two at a time.
 template <int N, int L>
 __device__ __forceinline__ void wave_sum_n(double (&v)[L]) {
@@ -437,31 +448,45 @@ __device__ void taylor(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
 // plus OFF elements: t = (s i tau / n) Op t_prev for the lane's rows.
 // `shift` (elements, uniform) moves every gather to a later term vector; a
 // run of terms with the same shift shares its address arithmetic.
-template <typename real, int R, int WS, int NC, int G, int SGN, int OFF>
+// Gathers and multiply-adds of slots [S0, S1) (static slots first, then the
+// control slots) into y, all gathers of the range issued first.
+template <typename real, int R, int WS, int NC, int G, int OFF, int S0, int S1>
+__device__ __forceinline__ void gather_fma(const LaneOp<real, R, WS, NC, G> &op, int shift,
+                                           cx<real> (&y)[R]) {
+  cx<real> b[S1 - S0][R];
+#pragma unroll
+  for (int s = S0; s < S1; ++s)
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      b[s - S0][m] = s < WS ? (op.sp[s < WS ? s : 0][m] + shift)[OFF]
+                            : (op.cp[s < WS ? 0 : s - WS][m] + shift)[OFF];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int s = S0; s < S1; ++s)
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      cfma(y[m], s < WS ? op.sval[s < WS ? s : 0][m] : op.cv[s < WS ? 0 : s - WS][m], b[s - S0][m]);
+}
+
+// One term of the series from the term vector at the bound gather addresses
+// plus OFF elements: t = (s i tau / n) Op t_prev for the lane's rows.  Shapes
+// of 2 waves per SIMD (G >= 4) with many gathers issue them in two halves,
+// so that half the gathered values need registers at a time (the other wave
+// of the SIMD covers the second wait); the multiply-adds keep their order.
+// SPLIT = false keeps one batch (the gradient kernel, whose other live values
+// make the halves slower there: d = 1296 passes 25 % faster split, its
+// gradient 16 % slower).
+template <typename real, int R, int WS, int NC, int G, int SGN, int OFF, bool SPLIT = true>
 __device__ __forceinline__ void series_term(const LaneOp<real, R, WS, NC, G> &op, real cf,
                                             cx<real> (&t)[R], cx<real> (&inc)[R],
                                             int shift = 0) {
-  cx<real> b[WS + NC][R];
-#pragma unroll
-  for (int s = 0; s < WS; ++s)
-#pragma unroll
-    for (int m = 0; m < R; ++m) b[s][m] = (op.sp[s][m] + shift)[OFF];
-#pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int m = 0; m < R; ++m) b[WS + c][m] = (op.cp[c][m] + shift)[OFF];
-  __builtin_amdgcn_sched_barrier(0);
+  constexpr int NS = WS + NC;
+  constexpr int H = (SPLIT && G >= 4 && NS * R > 24) ? (NS + 1) / 2 : NS;
   cx<real> y[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
-#pragma unroll
-  for (int s = 0; s < WS; ++s)
-#pragma unroll
-    for (int m = 0; m < R; ++m) cfma(y[m], op.sval[s][m], b[s][m]);
-#pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int m = 0; m < R; ++m) cfma(y[m], op.cv[c][m], b[WS + c][m]);
+  gather_fma<real, R, WS, NC, G, OFF, 0, H>(op, shift, y);
+  if constexpr (H < NS) gather_fma<real, R, WS, NC, G, OFF, H, NS>(op, shift, y);
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     if (SGN < 0)
@@ -477,7 +502,7 @@ __device__ __forceinline__ void series_term(const LaneOp<real, R, WS, NC, G> &op
 // and T[1], read through the addresses bound to T[0] (LaneOp::bind) plus a
 // constant, so the loop does no address arithmetic.  Steps that end in a jump
 // rebuild the stored terms with taylor() for the dense output.
-template <typename real, int R, int WS, int NC, int G, int SGN>
+template <typename real, int R, int WS, int NC, int G, int SGN, bool SPLIT = true>
 __device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                                 const Terms<real, R, G> &T, const cx<real> (&in)[R],
                                 cx<real> (&out)[R], double tau, int K, const Team<G> &tm) {
@@ -493,12 +518,12 @@ __device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const Pass
   }
   for (int n = 1; n <= K; n += 2) {
     tm.sync();
-    series_term<real, R, WS, NC, G, SGN, 0>(op, static_cast<real>(tau * a.inv_n[n]), t, inc);
+    series_term<real, R, WS, NC, G, SGN, 0, SPLIT>(op, static_cast<real>(tau * a.inv_n[n]), t, inc);
 #pragma unroll
     for (int m = 0; m < R; ++m) own[kLen + kL * m] = t[m];
     if (n + 1 > K) break;
     tm.sync();
-    series_term<real, R, WS, NC, G, SGN, kLen>(op, static_cast<real>(tau * a.inv_n[n + 1]), t,
+    series_term<real, R, WS, NC, G, SGN, kLen, SPLIT>(op, static_cast<real>(tau * a.inv_n[n + 1]), t,
                                                 inc);
 #pragma unroll
     for (int m = 0; m < R; ++m) own[kL * m] = t[m];

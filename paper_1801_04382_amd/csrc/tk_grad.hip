@@ -62,7 +62,7 @@ __device__ void propagate_piece(const LaneOp<real, R, WS, NC, G> &op, const Pass
   for (int s = 0; s < n; ++s) {
     cx<real> out[R];
     tm.sync();
-    taylor_pingpong<real, R, WS, NC, G, -1>(op, a, T, psi, out, hs, p.K, tm);
+    taylor_pingpong<real, R, WS, NC, G, -1, false>(op, a, T, psi, out, hs, p.K, tm);
     copy_state(out, psi);
   }
 }
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
             for (int ss = 0; ss < s; ++ss) {
               cx<real> out[R];
               tm.sync();
-              taylor_pingpong<real, R, WS, NC, G, -1>(opf, a, T, xs, out, hs, p.K, tm);
+              taylor_pingpong<real, R, WS, NC, G, -1, false>(opf, a, T, xs, out, hs, p.K, tm);
               copy_state(out, xs);
             }
             cx<real> X[R], Y[NCX][R];
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
             // lambda <- exp(+i H^+ hs) lambda
             cx<real> out[R];
             tm.sync();
-            taylor_pingpong<real, R, WS, NC, G, 1>(opb, a, T, lam, out, hs, p.K, tm);
+            taylor_pingpong<real, R, WS, NC, G, 1, false>(opb, a, T, lam, out, hs, p.K, tm);
             copy_state(out, lam);
           }
         }

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
                          __double_as_longlong(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // the new pulse of interval j - 1 leaves with this step's publish, so no
       // wave waits for its write on its own
-      if (blockIdx.x == 0 && j > 0) a.u_new[static_cast<size_t>(i) * a.nt + j - 1] = u_prev[i];
+      if (blockIdx.x == 0 && j > 0) a.u_new[static_cast<size_t>(i) * a.nt + j - 1] = pick(u_prev, i);
     }
     // ---- wait for every block's partial of step j; sum in block order --------
     if (wib == 0 && a.n_ctrl > 0) {
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       tm.sync();
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x < NCX) a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + a.nt - 1] = u_prev[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x < NCX) a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + a.nt - 1] = pick(u_prev, threadIdx.x);
   // ---- functional: tau_k = <tgt|psi_hat_k(T)> and the final states ----------
   cx<real> *psiT = static_cast<cx<real> *>(a.psiT);
   for (int t = 0; t < Tw; ++t) {
