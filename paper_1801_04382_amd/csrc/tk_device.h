@@ -470,18 +470,18 @@ __device__ __forceinline__ void gather_fma(const LaneOp<real, R, WS, NC, G> &op,
 
 // One term of the series from the term vector at the bound gather addresses
 // plus OFF elements: t = (s i tau / n) Op t_prev for the lane's rows.  Shapes
-// of 2 waves per SIMD (G >= 4) with many gathers issue them in two halves,
-// so that half the gathered values need registers at a time (the other wave
-// of the SIMD covers the second wait); the multiply-adds keep their order.
-// SPLIT = false keeps one batch (the gradient kernel, whose other live values
-// make the halves slower there: d = 1296 passes 25 % faster split, its
-// gradient 16 % slower).
+// with more than 16 gathers per lane issue them in two halves, so that half
+// the gathered values need registers at a time (these shapes are the ones
+// short of registers); the multiply-adds keep their order.  Measured: d = 1296
+// passes 24 % faster, d = 216 Krotov iterations 1-4 %.  SPLIT = false keeps
+// one batch (the gradient kernel, whose other live values make the halves
+// slower there: its d = 1296 gradient 16 %).
 template <typename real, int R, int WS, int NC, int G, int SGN, int OFF, bool SPLIT = true>
 __device__ __forceinline__ void series_term(const LaneOp<real, R, WS, NC, G> &op, real cf,
                                             cx<real> (&t)[R], cx<real> (&inc)[R],
                                             int shift = 0) {
   constexpr int NS = WS + NC;
-  constexpr int H = (SPLIT && G >= 4 && NS * R > 24) ? (NS + 1) / 2 : NS;
+  constexpr int H = (SPLIT && NS * R > 16) ? (NS + 1) / 2 : NS;
   cx<real> y[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
