@@ -263,7 +263,11 @@ TK_API int tk_grad_pathwise(tk_ctx *ctx, int32_t M, const tk_jump *rec, int64_t 
  * passes of every instance, one persistent launch runs their sequential
  * Krotov passes side by side (each instance with its own per-step reduction),
  * and one iteration of every instance is replayed as a HIP graph.  Instances
- * may differ in Hilbert dimension, sparsity, M and nt.  The instance id is
+ * may differ in Hilbert dimension, sparsity, M and nt.  Instances whose shape
+ * needs several waves per trajectory (d = 216 in FP64, d = 1296 in FP32) run
+ * in launches of their own, one team per block, and keep the costates of 64
+ * steps at a time: their Krotov pass recomputes each segment from checkpoints
+ * of the backward pass (same values, far less memory).  The instance id is
  * part of the random streams' key ([seed, (id << 32) | k], Sec. 2.1 MCWF
  * random numbers), so an instance's trajectories do not depend on the other
  * instances.  The per-step reduction of an instance sums the trajectories'

@@ -905,7 +905,7 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   const int nc = n_ctrl * wc;
   // the compiled variant with the fewest rows 64 G R >= d; among those, FP64
   // shapes with 4 rows per lane come last (they spill registers), then one-wave
-  // teams, then the narrowest slots.  Batch members take one-wave shapes only.
+  // teams, then the narrowest slots.
   // TK_VARIANT=<name> picks one by name instead.
   const char *want = std::getenv("TK_VARIANT");
   int nv = 0;
@@ -918,7 +918,7 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   for (int k = 0; k < nv; ++k) {
     const tk::Variant &v = vs[k];
     if (v.precision != c->precision || static_cast<int64_t>(v.R) * tk::kWave * v.G < d ||
-        v.WS < ws || v.NC < nc || (c->single_wave_only && v.G != 1))
+        v.WS < ws || v.NC < nc)
       continue;
     if (want && *want) {
       if (std::strcmp(want, v.name) == 0) best = &v;

@@ -101,7 +101,6 @@ struct tk_ctx {
   tk_kernel_timing tstat[TK_KERNEL_COUNT] = {};
   int last_wpb = 0, last_tw = 0, last_blocks = 0;
   bool cooperative = true;  // launch the Krotov pass with hipLaunchCooperativeKernel
-  bool single_wave_only = false;  // variant selection: one-wave teams (batch members)
 
   size_t bulk_cplx() const { return precision == TK_FP64 ? 16 : 8; }
 };
