@@ -21,6 +21,13 @@
 // therefore independent of how trajectories are split over waves and blocks:
 // an instance gives bit-identical pulses whatever the tile shape chosen and
 // whatever else runs in the batch.
+//
+// Instances whose shape needs a team of G > 1 waves per trajectory run in
+// kernels of their own (k_batch_wide_*, one team per block, launched after the
+// one-wave kernels of the same pass), with the same items, shares and gather.
+// They do not store their costates: the backward pass keeps checkpoints every
+// kSegment steps, and the Krotov pass recomputes each segment's costates from
+// its checkpoint before the segment's first step.
 #include <hip/hip_runtime.h>
 
 #include "tk_device.h"
