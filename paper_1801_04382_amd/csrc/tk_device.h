@@ -321,16 +321,22 @@ struct LaneOp {
 
   // y = Op v for the lane's rows, v the term vector `shift` elements past the
   // one the gathers are bound to.  All gathers first.
+  // Eight-wave shapes (short of registers) gather and multiply the static
+  // slots before gathering the control slots; the multiply-add order is the
+  // same either way.
   __device__ void apply_at(int shift, cx<real> (&y)[R]) const {
+    constexpr bool kHalves = G >= 4;
     cx<real> b[WS + NC][R];
 #pragma unroll
     for (int s = 0; s < WS; ++s)
 #pragma unroll
       for (int m = 0; m < R; ++m) b[s][m] = sp[s][m][shift];
+    if constexpr (!kHalves) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int m = 0; m < R; ++m) b[WS + c][m] = cp[c][m][shift];
+        for (int m = 0; m < R; ++m) b[WS + c][m] = cp[c][m][shift];
+    }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
@@ -338,6 +344,13 @@ struct LaneOp {
     for (int s = 0; s < WS; ++s)
 #pragma unroll
       for (int m = 0; m < R; ++m) cfma(y[m], sval[s][m], b[s][m]);
+    if constexpr (kHalves) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int m = 0; m < R; ++m) b[WS + c][m] = cp[c][m][shift];
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll

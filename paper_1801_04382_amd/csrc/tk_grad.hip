@@ -138,16 +138,21 @@ __device__ void taylor_aug(const LaneOp<real, R, WS, NC, G> &op, const PassArgs 
     tm.sync();
     constexpr int kLen = Terms<real, R, G>::kLen;
     const int xshift = cur * (1 + NCX) * kLen;  // x_{n-1}: term vector cur (1 + NCX)
-    // gathers of x_{n-1}: H x and the unscaled H_i x from the same loads
+    // gathers of x_{n-1}: H x and the unscaled H_i x from the same loads.
+    // Eight-wave teams (short of registers) gather the static slots, multiply
+    // them, then gather the control slots; the others issue all gathers first.
+    constexpr bool kHalves = G >= 4;
     cx<real> b[WS + NCX][R];
 #pragma unroll
     for (int s = 0; s < WS; ++s)
 #pragma unroll
       for (int m = 0; m < R; ++m) b[s][m] = op.sp[s][m][xshift];
+    if constexpr (!kHalves) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int m = 0; m < R; ++m) b[WS + c][m] = op.cp[c][m][xshift];
+        for (int m = 0; m < R; ++m) b[WS + c][m] = op.cp[c][m][xshift];
+    }
     __builtin_amdgcn_sched_barrier(0);
     cx<real> hx[R], hix[NCX][R];
 #pragma unroll
@@ -160,6 +165,13 @@ __device__ void taylor_aug(const LaneOp<real, R, WS, NC, G> &op, const PassArgs 
     for (int s = 0; s < WS; ++s)
 #pragma unroll
       for (int m = 0; m < R; ++m) cfma(hx[m], op.sval[s][m], b[s][m]);
+    if constexpr (kHalves) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int m = 0; m < R; ++m) b[WS + c][m] = op.cp[c][m][xshift];
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       int i = 0;  // control of slot c: c / wc, by comparisons
@@ -228,11 +240,12 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   T.base = reinterpret_cast<cx<real> *>(smem_raw) + static_cast<size_t>(team) * nbuf * kLen;
   if (tm.gl < nbuf) T[tm.gl][R * kL] = cx<real>{0, 0};
   __syncthreads();
-  LaneOp<real, R, WS, NC, G> opf, opb;
+  // the forward operator stays in registers; the costate operator is loaded
+  // where it is used (one series per substep of the reverse sweep), so the two
+  // slices never hold registers at once
+  LaneOp<real, R, WS, NC, G> opf;
   opf.load(a.scol, a.sval, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
-  opb.load(a.a_scol, a.a_sval, a.a_ccol, static_cast<const cx<real> *>(a.a_cval), tm.gl);
   opf.bind(T[0]);
-  opb.bind(T[0]);
 
   const int nseg = (a.nt + kGradCheckpoint - 1) / kGradCheckpoint;
   const int wave = blockIdx.x * tpb + team;  // global team index
@@ -319,7 +332,6 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
 #pragma unroll
         for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
         opf.set_pulses(uj, a.wc);
-        opb.set_pulses(uj, a.wc);
         const StepPlan p = plan_step(a, uj, khint);
         double bnd = a.b0;
 #pragma unroll
@@ -400,8 +412,14 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
               }
             // lambda <- exp(+i H^+ hs) lambda
             cx<real> out[R];
-            tm.sync();
-            taylor_pingpong<real, R, WS, NC, G, 1, false>(opb, a, T, lam, out, hs, p.K, tm);
+            {
+              LaneOp<real, R, WS, NC, G> opb;
+              opb.load(a.a_scol, a.a_sval, a.a_ccol, static_cast<const cx<real> *>(a.a_cval), tm.gl);
+              opb.bind(T[0]);
+              opb.set_pulses(uj, a.wc);
+              tm.sync();
+              taylor_pingpong<real, R, WS, NC, G, 1, false>(opb, a, T, lam, out, hs, p.K, tm);
+            }
             copy_state(out, lam);
           }
         }
