@@ -98,7 +98,8 @@ __device__ __forceinline__ void publish_share(const PassArgs &a, unsigned long l
   constexpr int NCX = NC > 0 ? NC : 1;
   double sc[NCX];
 #pragma unroll
-  for (int c = 0; c < NCX; ++c) sc[c] = c < NC ? wave_sum(pc[c]) : 0.0;
+  for (int c = 0; c < NCX; ++c) sc[c] = c < NC ? pc[c] : 0.0;
+  wave_sum_n<NC>(sc);  // two sums per exchange; the same bits as one at a time
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < NCX; ++i) {
