@@ -107,7 +107,7 @@ __device__ __forceinline__ void publish_share(const PassArgs &a, unsigned long l
 #pragma unroll
       for (int c = 0; c < NCX; ++c)
         if (c >= i * a.wc && c < (i + 1) * a.wc) s += sc[c];
-      __hip_atomic_store(&row[static_cast<size_t>(k) * NCX + i], __double_as_longlong(s),
+      __hip_atomic_store(gmem(row) + (static_cast<size_t>(k) * NCX + i), __double_as_longlong(s),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -122,7 +122,7 @@ __device__ __forceinline__ void load_shares(const unsigned long long *row, int M
     const int k = lane + kWave * (q0 + qq);
 #pragma unroll
     for (int c = 0; c < NCX; ++c)
-      v[qq][c] = k < M ? __hip_atomic_load(&row[static_cast<size_t>(k) * NCX + c],
+      v[qq][c] = k < M ? __hip_atomic_load(gmem(row) + (static_cast<size_t>(k) * NCX + c),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                        : 0ull;
   }
@@ -202,8 +202,8 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     cx<real> p[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      p[m] = start[lane + kWave * m];
-      psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m] = p[m];
+      p[m] = gld(start, lane + kWave * m);
+      gst(psi_g, static_cast<size_t>(k) * kRows + lane + kWave * m, p[m]);
     }
     const double n = norm2(p, tm);
     TrajMeta st;
@@ -211,7 +211,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     make_stream(a, k, 0, it).draw(0, st);
     st.ordinal = 0;
     st.pad = 0;
-    if (lane == 0) meta_g[k] = st;
+    if (lane == 0) gst(meta_g, k, st);
     cx<real> ch[R];
     load_costate<real, R, 1>(a, 0, k, tm, ch);
     double pc[NCX];
@@ -235,12 +235,12 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
 #pragma unroll
     for (int i = 0; i < NCX; ++i) {
       const size_t ij = static_cast<size_t>(i) * a.nt + j;
-      uo[i] = a.u_old[ij];
-      so[i] = a.S[ij];
+      uo[i] = gmem(a.u_old)[ij];
+      so[i] = gmem(a.S)[ij];
     }
     block_sync_lds();  // every wave has used the previous step's s_upd
     if (lb == 0 && j > 0 && threadIdx.x < NCX)
-      a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + j - 1] = pick(u_prev, threadIdx.x);
+      gmem(a.u_new)[static_cast<size_t>(threadIdx.x) * a.nt + j - 1] = pick(u_prev, threadIdx.x);
     if (wib == 0) {
       double acc[NCX];
       const bool ok = a.n_ctrl == 0 ||
@@ -272,8 +272,8 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     TrajMeta st;
     if (w < a.M) {
 #pragma unroll
-      for (int m = 0; m < R; ++m) psi[m] = psi_g[static_cast<size_t>(w) * kRows + lane + kWave * m];
-      st = meta_g[w];
+      for (int m = 0; m < R; ++m) psi[m] = gld(psi_g, static_cast<size_t>(w) * kRows + lane + kWave * m);
+      st = gld(meta_g, w);
       if (j + 1 < a.nt) load_costate<real, R, 1>(a, j + 1, w, tm, ch);
     }
     for (int k = w; k < a.M; k += nw) {
@@ -283,15 +283,15 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
       if (kn < a.M) {
 #pragma unroll
         for (int m = 0; m < R; ++m)
-          psi_n[m] = psi_g[static_cast<size_t>(kn) * kRows + lane + kWave * m];
-        st_n = meta_g[kn];
+          psi_n[m] = gld(psi_g, static_cast<size_t>(kn) * kRows + lane + kWave * m);
+        st_n = gld(meta_g, kn);
         if (j + 1 < a.nt) load_costate<real, R, 1>(a, j + 1, kn, tm, ch_n);
       }
       const Stream rng = make_stream(a, k, 0, it);
       advance_step<real, R, WS, NC, 1, 0, true>(op, a, T, psi, st, rng, j, p, k, tm);
 #pragma unroll
-      for (int m = 0; m < R; ++m) psi_g[static_cast<size_t>(k) * kRows + lane + kWave * m] = psi[m];
-      if (lane == 0) meta_g[k] = st;
+      for (int m = 0; m < R; ++m) gst(psi_g, static_cast<size_t>(k) * kRows + lane + kWave * m, psi[m]);
+      if (lane == 0) gst(meta_g, k, st);
       if (j + 1 < a.nt) {
         double pc[NCX];
 #pragma unroll
@@ -314,25 +314,25 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     }
   }
   if (lb == 0 && threadIdx.x < NCX)
-    a.u_new[static_cast<size_t>(threadIdx.x) * a.nt + a.nt - 1] = pick(u_prev, threadIdx.x);
+    gmem(a.u_new)[static_cast<size_t>(threadIdx.x) * a.nt + a.nt - 1] = pick(u_prev, threadIdx.x);
   // ---- tau_k = <tgt|psi_hat_k(T)> ----
   for (int k = w; k < a.M; k += nw) {
-    const double inv = 1.0 / sqrt(meta_g[k].nrm2);
+    const double inv = 1.0 / sqrt(gmem(meta_g)[k].nrm2);
     double tr = 0.0, ti = 0.0;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int row = lane + kWave * m;
-      const cx<real> q = psi_g[static_cast<size_t>(k) * kRows + row];
+      const cx<real> q = gld(psi_g, static_cast<size_t>(k) * kRows + row);
       const double px = q.x * inv, py = q.y * inv;
-      const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
+      const double gx = gmem(a.tgt)[2 * row], gy = gmem(a.tgt)[2 * row + 1];
       tr = fma(gx, px, fma(gy, py, tr));
       ti = fma(gx, py, fma(-gy, px, ti));
     }
     tr = wave_sum(tr);
     ti = wave_sum(ti);
     if (lane == 0) {
-      a.tau_out[2 * k] = tr;
-      a.tau_out[2 * k + 1] = ti;
+      gmem(a.tau_out)[2 * k] = tr;
+      gmem(a.tau_out)[2 * k + 1] = ti;
     }
   }
 }
@@ -453,7 +453,7 @@ __device__ void wide_recompute(const BatchInstance &I, int w, int nteam, int s, 
     const Stream rng = make_stream(ab, k, 1, it);
     if (e == nt) {
 #pragma unroll
-      for (int m = 0; m < R; ++m) psi[m] = start[tm.gl + kL * m];
+      for (int m = 0; m < R; ++m) psi[m] = gld(start, tm.gl + kL * m);
       st.nrm2 = norm2(psi, tm);
       st.ordinal = 0;
       st.pad = 0;
@@ -462,24 +462,24 @@ __device__ void wide_recompute(const BatchInstance &I, int w, int nteam, int s, 
       const size_t c = static_cast<size_t>(s) * M + k;
       const cx<real> *ck = static_cast<const cx<real> *>(ab.ck_psi) + c * R * kL;
 #pragma unroll
-      for (int m = 0; m < R; ++m) psi[m] = ck[tm.gl + kL * m];
-      st = ab.ck_meta[c];
+      for (int m = 0; m < R; ++m) psi[m] = gld(ck, tm.gl + kL * m);
+      st = gld(ab.ck_meta, c);
     }
-    const double tau_re = ab.tau_in[2 * k], tau_im = ab.tau_in[2 * k + 1];
+    const double tau_re = gmem(ab.tau_in)[2 * k], tau_im = gmem(ab.tau_in)[2 * k + 1];
     if (e < nt)
       store_costate<real, R, G>(seg + (static_cast<size_t>(e - j0) * M + k) * d, d, psi,
                                 st.nrm2, tau_re, tau_im, tm);
     OrderHint hint;
     double un[NCX];  // pulses of the next step, loaded one step ahead
 #pragma unroll
-    for (int i = 0; i < NCX; ++i) un[i] = ab.u[static_cast<size_t>(i) * nt + e - 1];
+    for (int i = 0; i < NCX; ++i) un[i] = gmem(ab.u)[static_cast<size_t>(i) * nt + e - 1];
     for (int j = e - 1; j >= j0; --j) {
       double uj[NCX];
 #pragma unroll
       for (int i = 0; i < NCX; ++i) uj[i] = un[i];
       if (j > j0)
 #pragma unroll
-        for (int i = 0; i < NCX; ++i) un[i] = ab.u[static_cast<size_t>(i) * nt + j - 1];
+        for (int i = 0; i < NCX; ++i) un[i] = gmem(ab.u)[static_cast<size_t>(i) * nt + j - 1];
       opb.set_pulses(uj, ab.wc);
       const StepPlan p = plan_step(ab, uj, hint);
       advance_step<real, R, WS, NC, G, 1>(opb, ab, T, psi, st, rng, j, p, k, tm);
@@ -505,7 +505,7 @@ __device__ __forceinline__ void publish_share_team(const PassArgs &a, unsigned l
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (c >= i * a.wc && c < (i + 1) * a.wc) s += pc[c];
-      __hip_atomic_store(&row[static_cast<size_t>(k) * NCX + i], __double_as_longlong(s),
+      __hip_atomic_store(gmem(row) + (static_cast<size_t>(k) * NCX + i), __double_as_longlong(s),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -521,7 +521,7 @@ __device__ __forceinline__ void load_seg_costate(const PassArgs &a, int q, int k
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int row = tm.gl + Team<G>::kLanes * m;
-    ch[m] = chi[base + (row < a.d ? row : a.d - 1)];
+    ch[m] = gld(chi, base + (row < a.d ? row : a.d - 1));
   }
 }
 
@@ -561,8 +561,8 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
         cx<real> p[R];
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-          p[m] = start[tm.gl + kL * m];
-          psi_g[static_cast<size_t>(k) * kRows + tm.gl + kL * m] = p[m];
+          p[m] = gld(start, tm.gl + kL * m);
+          gst(psi_g, static_cast<size_t>(k) * kRows + tm.gl + kL * m, p[m]);
         }
         const double n = norm2(p, tm);
         TrajMeta st;
@@ -570,7 +570,7 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
         make_stream(a, k, 0, it).draw(0, st);
         st.ordinal = 0;
         st.pad = 0;
-        if (tm.leader()) meta_g[k] = st;
+        if (tm.leader()) gst(meta_g, k, st);
         cx<real> ch[R];
         load_seg_costate<real, R, G>(a, 0, k, tm, ch);
         double pc[NCX];
@@ -589,12 +589,12 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
 #pragma unroll
       for (int i = 0; i < NCX; ++i) {
         const size_t ij = static_cast<size_t>(i) * nt + j;
-        uo[i] = a.u_old[ij];
-        so[i] = a.S[ij];
+        uo[i] = gmem(a.u_old)[ij];
+        so[i] = gmem(a.S)[ij];
       }
       block_sync_lds();  // every wave has used the previous step's s_upd
       if (lb == 0 && j > 0 && threadIdx.x < NCX)
-        a.u_new[static_cast<size_t>(threadIdx.x) * nt + j - 1] = pick(u_prev, threadIdx.x);
+        gmem(a.u_new)[static_cast<size_t>(threadIdx.x) * nt + j - 1] = pick(u_prev, threadIdx.x);
       if (threadIdx.x < kWave) {
         double acc[NCX];
         const bool ok = a.n_ctrl == 0 ||
@@ -623,15 +623,15 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
       for (int k = w; k < M; k += nteam) {
         cx<real> psi[R], ch[R];
 #pragma unroll
-        for (int m = 0; m < R; ++m) psi[m] = psi_g[static_cast<size_t>(k) * kRows + tm.gl + kL * m];
-        TrajMeta st = meta_g[k];
+        for (int m = 0; m < R; ++m) psi[m] = gld(psi_g, static_cast<size_t>(k) * kRows + tm.gl + kL * m);
+        TrajMeta st = gld(meta_g, k);
         if (j + 1 < nt) load_seg_costate<real, R, G>(a, j + 1 - j0, k, tm, ch);
         const Stream rng = make_stream(a, k, 0, it);
         tm.sync();  // the previous trajectory's reads of the term vectors are done
         advance_step<real, R, WS, NC, G, 0, true>(op, a, T, psi, st, rng, j, p, k, tm);
 #pragma unroll
-        for (int m = 0; m < R; ++m) psi_g[static_cast<size_t>(k) * kRows + tm.gl + kL * m] = psi[m];
-        if (tm.leader()) meta_g[k] = st;
+        for (int m = 0; m < R; ++m) gst(psi_g, static_cast<size_t>(k) * kRows + tm.gl + kL * m, psi[m]);
+        if (tm.leader()) gst(meta_g, k, st);
         if (j + 1 < nt) {
           double pc[NCX];
 #pragma unroll
@@ -646,24 +646,24 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
     }
   }
   if (lb == 0 && threadIdx.x < NCX)
-    a.u_new[static_cast<size_t>(threadIdx.x) * nt + nt - 1] = pick(u_prev, threadIdx.x);
+    gmem(a.u_new)[static_cast<size_t>(threadIdx.x) * nt + nt - 1] = pick(u_prev, threadIdx.x);
   // ---- tau_k = <tgt|psi_hat_k(T)> ----
   for (int k = w; k < M; k += nteam) {
-    const double inv = 1.0 / sqrt(meta_g[k].nrm2);
+    const double inv = 1.0 / sqrt(gmem(meta_g)[k].nrm2);
     double tr = 0.0, ti = 0.0;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int row = tm.gl + kL * m;
-      const cx<real> q = psi_g[static_cast<size_t>(k) * kRows + row];
+      const cx<real> q = gld(psi_g, static_cast<size_t>(k) * kRows + row);
       const double px = q.x * inv, py = q.y * inv;
-      const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
+      const double gx = gmem(a.tgt)[2 * row], gy = gmem(a.tgt)[2 * row + 1];
       tr = fma(gx, px, fma(gy, py, tr));
       ti = fma(gx, py, fma(-gy, px, ti));
     }
     tm.sum2(tr, ti);
     if (tm.leader()) {
-      a.tau_out[2 * k] = tr;
-      a.tau_out[2 * k + 1] = ti;
+      gmem(a.tau_out)[2 * k] = tr;
+      gmem(a.tau_out)[2 * k + 1] = ti;
     }
   }
 }

@@ -18,6 +18,54 @@ struct alignas(2 * sizeof(real)) cx {
   real x, y;
 };
 
+// Global-memory view of a pointer.  The batched kernels read their pointers
+// from an instance table in device memory, whose address space the compiler
+// cannot tell: it then emits flat instructions, which count against the LDS
+// wait counter as well, so every LDS wait also waits for global loads and
+// stores in flight.  Accesses through this view are global instructions.
+// (Pointers from kernel arguments are global already; there it changes
+// nothing.)
+#define TK_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ TK_GLOBAL T *gmem(T *p) {
+  return (TK_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const TK_GLOBAL T *gmem(const T *p) {
+  return (const TK_GLOBAL T *)p;
+}
+// complex elements move through the view as two-element vectors (a struct's
+// implicit assignment cannot take an object in the global address space)
+template <typename real>
+using vec2 = real __attribute__((ext_vector_type(2)));
+template <typename real>
+__device__ __forceinline__ cx<real> gld(const cx<real> *p, size_t i) {
+  const vec2<real> v = ((const TK_GLOBAL vec2<real> *)p)[i];
+  return cx<real>{v.x, v.y};
+}
+template <typename real>
+__device__ __forceinline__ void gst(cx<real> *p, size_t i, const cx<real> &c) {
+  ((TK_GLOBAL vec2<real> *)p)[i] = vec2<real>{c.x, c.y};
+}
+__device__ __forceinline__ TrajMeta gld(const TrajMeta *p, size_t i) {
+  const TK_GLOBAL TrajMeta *q = gmem(p) + i;
+  TrajMeta t;
+  t.nrm2 = q->nrm2;
+  t.r = q->r;
+  t.x = q->x;
+  t.ordinal = q->ordinal;
+  t.pad = q->pad;
+  return t;
+}
+__device__ __forceinline__ void gst(TrajMeta *p, size_t i, const TrajMeta &t) {
+  TK_GLOBAL TrajMeta *q = gmem(p) + i;
+  q->nrm2 = t.nrm2;
+  q->r = t.r;
+  q->x = t.x;
+  q->ordinal = t.ordinal;
+  q->pad = t.pad;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -270,14 +318,14 @@ struct LaneOp {
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         const int idx = (s * R + m) * kL + gl;
-        scol[s][m] = scol_g[idx];
-        sval[s][m] = sv[idx];
+        scol[s][m] = gmem(scol_g)[idx];
+        sval[s][m] = gld(sv, idx);
       }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        ccol[c][m] = ccol_g[(c * R + m) * kL + gl];
+        ccol[c][m] = gmem(ccol_g)[(c * R + m) * kL + gl];
         cv[c][m] = cx<real>{0, 0};
       }
     cval = cval_src + gl;
@@ -297,7 +345,11 @@ struct LaneOp {
 
   // unscaled control element of slot c, row slot m
   __device__ __forceinline__ cx<real> cval_at(int c, int m) const {
-    return cval[(c * R + m) * kL];
+    // one-wave teams read a copy in LDS, G-wave teams global memory
+    if constexpr (G > 1)
+      return gld(cval, (c * R + m) * kL);
+    else
+      return cval[(c * R + m) * kL];
   }
 
   // cv = u_{c / wc} * cval for the pulse values uj[0 .. NCX) (zero past n_ctrl)
@@ -640,7 +692,7 @@ __device__ void apply_packed(const int *lcol, const void *lval, int wl, int l,
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int idx = ((l * wl + w) * R + m) * Team<G>::kLanes + tm.gl;
-      cfma(y[m], lv[idx], v[lcol[idx]]);
+      cfma(y[m], gld(lv, idx), v[gmem(lcol)[idx]]);
     }
 }
 
@@ -919,8 +971,8 @@ __device__ __forceinline__ void store_costate(cx<real> *out, int d, const cx<rea
     const int row = tm.gl + Team<G>::kLanes * m;
     if (row < d) {
       const double px = psi[m].x * inv, py = psi[m].y * inv;
-      out[row] = cx<real>{static_cast<real>(tau_re * px - tau_im * py),
-                          static_cast<real>(tau_re * py + tau_im * px)};
+      gst(out, row, cx<real>{static_cast<real>(tau_re * px - tau_im * py),
+                          static_cast<real>(tau_re * py + tau_im * px)});
     }
   }
 }
@@ -932,7 +984,7 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
   cx<real> *chi = static_cast<cx<real> *>(a.chi);
   cx<real> psi[R];
 #pragma unroll
-  for (int m = 0; m < R; ++m) psi[m] = start[tm.gl + Team<G>::kLanes * m];
+  for (int m = 0; m < R; ++m) psi[m] = gld(start, tm.gl + Team<G>::kLanes * m);
   TrajMeta st;
   st.nrm2 = norm2(psi, tm);
   st.ordinal = 0;
@@ -940,15 +992,15 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
   rng.draw(0, st);
   double tau_re = 0.0, tau_im = 0.0;
   if (DIR == 1) {
-    tau_re = a.tau_in[2 * k];
-    tau_im = a.tau_in[2 * k + 1];
+    tau_re = gmem(a.tau_in)[2 * k];
+    tau_im = gmem(a.tau_in)[2 * k + 1];
   }
   constexpr int NCX = NC > 0 ? NC : 1;
   double un[NCX];  // pulses of the next step, loaded one step ahead (rows padded)
   {
     const int j0 = DIR == 0 ? 0 : a.nt - 1;
 #pragma unroll
-    for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + j0];
+    for (int i = 0; i < NCX; ++i) un[i] = gmem(a.u)[static_cast<size_t>(i) * a.nt + j0];
   }
   OrderHint khint;
   for (int jj = 0; jj < a.nt; ++jj) {
@@ -959,7 +1011,7 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
     if (jj + 1 < a.nt) {
       const int jn = DIR == 0 ? j + 1 : j - 1;
 #pragma unroll
-      for (int i = 0; i < NCX; ++i) un[i] = a.u[static_cast<size_t>(i) * a.nt + jn];
+      for (int i = 0; i < NCX; ++i) un[i] = gmem(a.u)[static_cast<size_t>(i) * a.nt + jn];
     }
     op.set_pulses(uj, a.wc);
     const StepPlan p = plan_step(a, uj, khint);
@@ -972,8 +1024,8 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
       const size_t c = static_cast<size_t>(j / a.seg_len - 1) * a.M + k;
       cx<real> *ck = static_cast<cx<real> *>(a.ck_psi) + c * R * Team<G>::kLanes;
 #pragma unroll
-      for (int m = 0; m < R; ++m) ck[tm.gl + Team<G>::kLanes * m] = psi[m];
-      if (tm.leader()) a.ck_meta[c] = st;
+      for (int m = 0; m < R; ++m) gst(ck, tm.gl + Team<G>::kLanes * m, psi[m]);
+      if (tm.leader()) gst(a.ck_meta, c, st);
     }
   }
   if (DIR == 0) {
@@ -985,18 +1037,18 @@ __device__ void pass_trajectory(LaneOp<real, R, WS, NC, G> &op, const PassArgs &
       const int row = tm.gl + Team<G>::kLanes * m;
       const double px = psi[m].x * inv, py = psi[m].y * inv;
       // tau_k = <tgt|psi_hat> = sum conj(tgt) psi_hat
-      const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
+      const double gx = gmem(a.tgt)[2 * row], gy = gmem(a.tgt)[2 * row + 1];
       tr = fma(gx, px, fma(gy, py, tr));
       ti = fma(gx, py, fma(-gy, px, ti));
       if (psiT != nullptr && row < a.d)
-        psiT[static_cast<size_t>(k) * a.d + row] =
-            cx<real>{static_cast<real>(px), static_cast<real>(py)};
+        gst(psiT, static_cast<size_t>(k) * a.d + row,
+            cx<real>{static_cast<real>(px), static_cast<real>(py)});
     }
     tr = tm.sum(tr);
     ti = tm.sum(ti);
     if (tm.leader() && a.tau_out != nullptr) {
-      a.tau_out[2 * k] = tr;
-      a.tau_out[2 * k + 1] = ti;
+      gmem(a.tau_out)[2 * k] = tr;
+      gmem(a.tau_out)[2 * k + 1] = ti;
     }
   }
 }
@@ -1033,7 +1085,7 @@ __device__ __forceinline__ void load_costate(const PassArgs &a, int j, int k, co
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int row = tm.gl + Team<G>::kLanes * m;
-    ch[m] = chi[base + (row < a.d ? row : a.d - 1)];
+    ch[m] = gld(chi, base + (row < a.d ? row : a.d - 1));
   }
 }
 
