@@ -2,17 +2,18 @@
 //
 // Every instance has its own system (operator slices), states, pulses,
 // costates and random streams (the instance index is part of the Philox key),
-// and its own kernel shape (rows per lane, slots); a launch serves all of them
-// and selects the shape per instance with a switch, so one persistent grid
-// runs instances of different Hilbert dimension side by side.
+// and its own kernel shape (rows per lane, slots).  Every shape has kernels of
+// its own, compiled for that shape alone, so a small shape is not held to the
+// registers of the largest one (more waves per SIMD); the instances of one
+// shape are served by one launch, the shapes one after another.
 //
 // Plain passes (guess forward, costates): a list of (instance, trajectory)
-// items, costliest first, dealt round-robin to the waves; an item is one
-// trajectory over all of its instance's steps, computed by the same device
-// code as the single-system passes.
+// items of one shape, costliest first, dealt round-robin to the waves; an item
+// is one trajectory over all of its instance's steps, computed by the same
+// device code as the single-system passes.
 //
-// Sequential Krotov pass: each instance owns a contiguous range of blocks,
-// all co-resident.  Trajectory states live in device memory between steps.
+// Sequential Krotov pass: each instance of the launch's shape owns a contiguous
+// range of its blocks, all co-resident.  Trajectory states live in device memory between steps.
 // After a trajectory reaches t_j its own FP64 share of
 // s_ij = sum_k Im <chi_k(t_j)|H_i|psi_hat_k(t_j)> is published into a
 // per-trajectory slot (initialised to a sentinel); every block of the instance
@@ -63,7 +64,8 @@ __device__ void batch_pass_item(const PassArgs &a, int k, uint64_t it, unsigned 
   pass_trajectory<real, R, WS, NC, 1, DIR>(op, a, T, k, make_stream(a, k, DIR, it), tm);
 }
 
-template <typename real, int DIR>
+// Plain pass over the items of shape S (b.items holds only those).
+template <typename real, int DIR, int S>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_pass(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Team<1> tm = make_team<1>(nullptr);
@@ -77,16 +79,11 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_pass(BatchArgs 
     const BatchInstance &I = b.inst[__builtin_amdgcn_readfirstlane(item.x)];
     const PassArgs &a = DIR == 0 ? I.fw : I.bw;
     const int k = __builtin_amdgcn_readfirstlane(item.y);
-    switch (I.variant) {
+    if (I.variant != S) continue;  // not an item of this launch (none are given)
 #define TK_CASE(idx, R, WS, NC) \
-  case idx:                     \
-    batch_pass_item<real, R, WS, NC, DIR>(a, k, it, wl, tm); \
-    break;
-      TK_BATCH_SHAPES(TK_CASE)
+  if constexpr (idx == S) batch_pass_item<real, R, WS, NC, DIR>(a, k, it, wl, tm);
+    TK_BATCH_SHAPES(TK_CASE)
 #undef TK_CASE
-      default:
-        break;
-    }
   }
 }
 
@@ -337,7 +334,9 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
   }
 }
 
-template <typename real>
+// Krotov pass of the instances of shape S; b.block_inst maps this launch's
+// blocks to them, and I.block0 is relative to the launch.
+template <typename real, int S>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double s_upd[kMaxCtrl];
@@ -350,15 +349,11 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArg
   const BatchInstance &I = b.inst[i];
   const int lb = blockIdx.x - I.block0;
   const uint64_t it = *b.iteration;
-  switch (I.variant) {
-#define TK_CASE(idx, R, WS, NC)                                                         \
-  case idx:                                                                             \
-    batch_krotov_instance<real, R, WS, NC>(b, I, lb, it, smem_raw, s_upd, &s_abort); \
-    break;
+  if (I.variant == S) {  // uniform over the instance's blocks
+#define TK_CASE(idx, R, WS, NC) \
+  if constexpr (idx == S) batch_krotov_instance<real, R, WS, NC>(b, I, lb, it, smem_raw, s_upd, &s_abort);
     TK_BATCH_SHAPES(TK_CASE)
 #undef TK_CASE
-    default:
-      break;
   }
   // the instance's finishing time, for the autotuner's block split
   __syncthreads();
@@ -751,15 +746,18 @@ __global__ __launch_bounds__(256) void k_batch_finish(BatchArgs b, int copy_puls
 
 BatchKernels batch_kernels(int precision) {
   BatchKernels k;
-  if (precision == TK_FP64) {
-    k.pass_fw = reinterpret_cast<const void *>(&k_batch_pass<double, 0>);
-    k.pass_bw = reinterpret_cast<const void *>(&k_batch_pass<double, 1>);
-    k.krotov = reinterpret_cast<const void *>(&k_batch_krotov<double>);
-  } else {
-    k.pass_fw = reinterpret_cast<const void *>(&k_batch_pass<float, 0>);
-    k.pass_bw = reinterpret_cast<const void *>(&k_batch_pass<float, 1>);
-    k.krotov = reinterpret_cast<const void *>(&k_batch_krotov<float>);
+#define TK_CASE(idx, R, WS, NC)                                                               \
+  if (precision == TK_FP64) {                                                                 \
+    k.pass_fw[idx] = reinterpret_cast<const void *>(&k_batch_pass<double, 0, idx>);           \
+    k.pass_bw[idx] = reinterpret_cast<const void *>(&k_batch_pass<double, 1, idx>);           \
+    k.krotov[idx] = reinterpret_cast<const void *>(&k_batch_krotov<double, idx>);             \
+  } else {                                                                                    \
+    k.pass_fw[idx] = reinterpret_cast<const void *>(&k_batch_pass<float, 0, idx>);            \
+    k.pass_bw[idx] = reinterpret_cast<const void *>(&k_batch_pass<float, 1, idx>);            \
+    k.krotov[idx] = reinterpret_cast<const void *>(&k_batch_krotov<float, idx>);              \
   }
+  TK_BATCH_SHAPES(TK_CASE)
+#undef TK_CASE
   if (precision == TK_FP64) {
     k.wpass_fw = reinterpret_cast<const void *>(&k_batch_wide_pass<double, 0, 2>);
     k.wpass_bw = reinterpret_cast<const void *>(&k_batch_wide_pass<double, 1, 2>);

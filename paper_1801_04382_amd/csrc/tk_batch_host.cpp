@@ -42,10 +42,18 @@ struct Member {
 };
 
 struct LaunchPlan {
-  int pass_wpb = 0, pass_blocks = 0;
-  int kro_wpb = 0, kro_blocks = 0;
+  int pass_wpb = 0, kro_wpb = 0;  // waves per block of the one-wave launches
+  std::vector<int> nblocks;       // Krotov blocks per entry of narrow
+};
+
+// One-wave instances of one kernel shape: kernels of their own (compiled for
+// that shape alone), launched one shape after another.
+struct NarrowGroup {
+  int S = 0;                   // shape index
+  size_t q0 = 0, q1 = 0;       // their entries in narrow
+  int item0 = 0, n_items = 0;  // their range of the one-wave work list
+  int pass_blocks = 0, kro_blocks = 0, kro_block0 = 0;
   size_t pass_lds = 0, kro_lds = 0;
-  std::vector<int> nblocks;  // Krotov blocks per instance (one-wave instances)
 };
 
 // Instances of one multi-wave team size: kernels of their own, one team per
@@ -70,7 +78,8 @@ struct tk_batch {
   std::string err;
   int n_cu = 0;
   std::vector<std::unique_ptr<Member>> mem;
-  std::vector<int> narrow;       // members of one-wave shapes
+  std::vector<int> narrow;       // members of one-wave shapes, grouped by shape
+  std::vector<NarrowGroup> groups;
   std::vector<std::unique_ptr<WideClass>> wide;  // members of multi-wave shapes, by team size
   tk::BatchKernels kern{};
   bool ready = false;
@@ -118,6 +127,8 @@ int shape_index(const tk::Variant *v) {
 }
 
 size_t cplx_bytes(int precision) { return precision == TK_FP64 ? 16 : 8; }
+
+constexpr size_t kLaunchSlots = 16;  // start-time slots of the Krotov launches
 
 // LDS bytes per wave of the batched plain passes for member m
 size_t pass_wave_lds(const tk_batch *b, const Member &m) {
@@ -178,8 +189,26 @@ int upload_block_map(tk_batch *b, const std::vector<int> &idx, const std::vector
 // Instance table and the Krotov block maps of the current plans.
 int upload_tables(tk_batch *b) {
   const size_t n = b->mem.size();
-  int rc = upload_block_map(b, b->narrow, b->plan.nblocks, b->block_inst_dev, &b->plan.kro_blocks);
-  if (rc) return rc;
+  if (b->plan.nblocks.size() == b->narrow.size()) {
+    // one-wave instances: one launch per shape, block0 relative to the launch
+    std::vector<int> block_inst;
+    for (auto &g : b->groups) {
+      g.kro_block0 = static_cast<int>(block_inst.size());
+      for (size_t q = g.q0; q < g.q1; ++q) {
+        const int i = b->narrow[q];
+        b->inst[i].block0 = static_cast<int>(block_inst.size()) - g.kro_block0;
+        b->inst[i].nblocks = b->plan.nblocks[q];
+        for (int r = 0; r < b->plan.nblocks[q]; ++r) block_inst.push_back(i);
+      }
+      g.kro_blocks = static_cast<int>(block_inst.size()) - g.kro_block0;
+    }
+    if (!block_inst.empty()) {
+      TK_BHIP(b, b->block_inst_dev.ensure(block_inst.size() * sizeof(int)));
+      TK_BHIP(b, hipMemcpy(b->block_inst_dev.p, block_inst.data(),
+                           block_inst.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+  }
+  int rc = TK_OK;
   for (auto &w : b->wide)
     if ((rc = upload_block_map(b, w->idx, w->nblocks, w->block_inst_dev, &w->kro_blocks))) return rc;
   TK_BHIP(b, b->inst_dev.ensure(n * sizeof(tk::BatchInstance)));
@@ -193,11 +222,7 @@ tk::BatchArgs batch_args(tk_batch *b) {
   std::memset(&a, 0, sizeof(a));
   a.inst = b->inst_dev.as<tk::BatchInstance>();
   a.n_inst = static_cast<int>(b->mem.size());
-  a.wave_lds = static_cast<int>(b->plan.pass_lds / std::max(b->plan.pass_wpb, 1));
   a.items = b->items_dev.as<int2>();
-  int64_t items = 0;
-  for (int i : b->narrow) items += b->mem[i]->M;
-  a.n_items = static_cast<int>(items);
   a.block_inst = b->block_inst_dev.as<int>();
   a.iteration = b->iter_dev.as<uint64_t>();
   a.J_hist = b->J_hist_dev.as<double>();
@@ -216,45 +241,58 @@ tk::BatchArgs wide_args(tk_batch *b, WideClass &w) {
   return a;
 }
 
-// Pass plan with `wpb` waves per block: as many blocks as are co-resident.
+// Pass plan with `wpb` waves per block: per shape, as many blocks as are
+// co-resident (the shapes' launches run one after another).
 int plan_pass(tk_batch *b, int wpb) {
-  size_t wl = 0;
-  for (int i : b->narrow) wl = std::max(wl, pass_wave_lds(b, *b->mem[i]));
-  const size_t lds = wl * wpb;
-  if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
-  for (const void *k : {b->kern.pass_fw, b->kern.pass_bw})
-    TK_BHIP(b, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   static_cast<int>(lds)));
-  int occ = 0;
-  TK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, b->kern.pass_bw, tk::kWave * wpb,
-                                                          lds));
-  if (occ < 1) return TK_EUNSUPPORTED;
-  int64_t items = 0;
-  for (int i : b->narrow) items += b->mem[i]->M;
-  const int64_t blocks = std::min<int64_t>(static_cast<int64_t>(occ) * b->n_cu, (items + wpb - 1) / wpb);
+  for (auto &g : b->groups) {
+    size_t wl = 0;
+    for (size_t q = g.q0; q < g.q1; ++q) wl = std::max(wl, pass_wave_lds(b, *b->mem[b->narrow[q]]));
+    const size_t lds = wl * wpb;
+    if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
+    int occ = 1 << 30;
+    for (const void *k : {b->kern.pass_fw[g.S], b->kern.pass_bw[g.S]}) {
+      TK_BHIP(b, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(lds)));
+      int o = 0;
+      TK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, tk::kWave * wpb, lds));
+      occ = std::min(occ, o);
+    }
+    if (occ < 1) return TK_EUNSUPPORTED;
+    const int64_t blocks =
+        std::min<int64_t>(static_cast<int64_t>(occ) * b->n_cu, (g.n_items + wpb - 1) / wpb);
+    g.pass_lds = lds;
+    g.pass_blocks = static_cast<int>(std::max<int64_t>(blocks, 1));
+  }
   b->plan.pass_wpb = wpb;
-  b->plan.pass_lds = lds;
-  b->plan.pass_blocks = static_cast<int>(std::max<int64_t>(blocks, 1));
   return TK_OK;
 }
 
 // Krotov plan with `wpb` waves per block and a fraction of the co-resident blocks.
+// Per shape, the launch's co-resident blocks are split among its instances.
 int plan_krotov(tk_batch *b, int wpb, double frac, double sync_cost,
                 const std::vector<double> *cost = nullptr) {
-  size_t lds = 0;
-  for (int i : b->narrow)
-    lds = std::max(lds, tk::block_lds_bytes(*b->mem[i]->c->var, wpb, b->mem[i]->kbuf_fw, 0));
-  if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
-  TK_BHIP(b, hipFuncSetAttribute(b->kern.krotov, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 static_cast<int>(lds)));
-  int occ = 0;
-  TK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, b->kern.krotov, tk::kWave * wpb,
-                                                          lds));
-  const int capacity = static_cast<int>(frac * occ * b->n_cu);
-  if (capacity < static_cast<int>(b->narrow.size())) return TK_EUNSUPPORTED;
+  std::vector<int> nb(b->narrow.size(), 0);
+  for (auto &g : b->groups) {
+    size_t lds = 0;
+    for (size_t q = g.q0; q < g.q1; ++q) {
+      const Member &m = *b->mem[b->narrow[q]];
+      lds = std::max(lds, tk::block_lds_bytes(*m.c->var, wpb, m.kbuf_fw, 0));
+    }
+    if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
+    const void *k = b->kern.krotov[g.S];
+    TK_BHIP(b, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(lds)));
+    int occ = 0;
+    TK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, tk::kWave * wpb, lds));
+    const int capacity = static_cast<int>(frac * occ * b->n_cu);
+    if (capacity < static_cast<int>(g.q1 - g.q0)) return TK_EUNSUPPORTED;
+    g.kro_lds = lds;
+    const std::vector<int> idx(b->narrow.begin() + g.q0, b->narrow.begin() + g.q1);
+    const std::vector<int> part = split_blocks(b, idx, capacity, wpb, sync_cost, cost);
+    std::copy(part.begin(), part.end(), nb.begin() + g.q0);
+  }
   b->plan.kro_wpb = wpb;
-  b->plan.kro_lds = lds;
-  b->plan.nblocks = split_blocks(b, b->narrow, capacity, wpb, sync_cost, cost);
+  b->plan.nblocks = nb;
   return upload_tables(b);
 }
 
@@ -289,12 +327,15 @@ int plan_wide(tk_batch *b, WideClass &w) {
 
 // which: 0 every instance, 1 one-wave instances only
 int launch_pass(tk_batch *b, int dir, int which = 0) {
-  if (!b->narrow.empty()) {
+  for (const auto &g : b->groups) {
     tk::BatchArgs a = batch_args(b);
+    a.items = b->items_dev.as<int2>() + g.item0;
+    a.n_items = g.n_items;
+    a.wave_lds = static_cast<int>(g.pass_lds / b->plan.pass_wpb);
     void *args[] = {&a};
-    TK_BHIP(b, hipLaunchKernel(dir == 0 ? b->kern.pass_fw : b->kern.pass_bw,
-                               dim3(b->plan.pass_blocks), dim3(tk::kWave * b->plan.pass_wpb), args,
-                               b->plan.pass_lds, b->stream));
+    TK_BHIP(b, hipLaunchKernel(dir == 0 ? b->kern.pass_fw[g.S] : b->kern.pass_bw[g.S],
+                               dim3(g.pass_blocks), dim3(tk::kWave * b->plan.pass_wpb), args,
+                               g.pass_lds, b->stream));
   }
   for (auto &wp : b->wide) {
     if (which == 1) break;
@@ -313,15 +354,24 @@ int launch_krotov(tk_batch *b, int which = 0) {
   void *args[] = {&a};
   TK_BHIP(b, hipLaunchKernel(b->kern.fill, dim3(static_cast<unsigned>(b->mem.size())), dim3(256),
                              args, 0, b->stream));
-  // blocks are co-resident by the occupancy check of the plan; a block that
-  // waits past the spin limit aborts the pass with an error instead of hanging
-  if (!b->narrow.empty() && which != 2)
-    TK_BHIP(b, hipLaunchKernel(b->kern.krotov, dim3(b->plan.kro_blocks),
-                               dim3(tk::kWave * b->plan.kro_wpb), args, b->plan.kro_lds, b->stream));
-  for (auto &wp : b->wide) {
+  // the blocks of each launch are co-resident by the occupancy check of the
+  // plan; a block that waits past the spin limit aborts the pass with an error
+  // instead of hanging.  Each launch takes its own start-time slot.
+  unsigned long long *t_begin = b->t_begin_dev.as<unsigned long long>();
+  for (size_t gi = 0; gi < b->groups.size() && which != 2; ++gi) {
+    const NarrowGroup &g = b->groups[gi];
+    tk::BatchArgs ga = batch_args(b);
+    ga.block_inst = b->block_inst_dev.as<int>() + g.kro_block0;
+    ga.t_begin = t_begin + gi;
+    void *gargs[] = {&ga};
+    TK_BHIP(b, hipLaunchKernel(b->kern.krotov[g.S], dim3(g.kro_blocks),
+                               dim3(tk::kWave * b->plan.kro_wpb), gargs, g.kro_lds, b->stream));
+  }
+  for (size_t wi = 0; wi < b->wide.size(); ++wi) {
     if (which == 1) break;
-    WideClass &w = *wp;
+    WideClass &w = *b->wide[wi];
     tk::BatchArgs wa = wide_args(b, w);
+    wa.t_begin = t_begin + b->groups.size() + wi;
     void *wargs[] = {&wa};
     TK_BHIP(b, hipLaunchKernel(w.krotov, dim3(w.kro_blocks), dim3(tk::kWave * w.G), wargs, w.lds,
                                b->stream));
@@ -377,7 +427,8 @@ int finalize(tk_batch *b) {
   TK_BHIP(b, b->err_dev.ensure(sizeof(int)));
   TK_BHIP(b, b->rec_dev.ensure(sizeof(tk_jump)));
   TK_BHIP(b, b->rec_count_dev.ensure(sizeof(unsigned long long)));
-  TK_BHIP(b, b->t_begin_dev.ensure(sizeof(unsigned long long)));
+  // start-time slots: one per Krotov launch (one-wave shapes, then team sizes)
+  TK_BHIP(b, b->t_begin_dev.ensure(kLaunchSlots * sizeof(unsigned long long)));
   TK_BHIP(b, b->t_end_dev.ensure(n * sizeof(unsigned long long)));
   {
     int khz = 0;
@@ -389,8 +440,9 @@ int finalize(tk_batch *b) {
   b->inst.assign(n, tk::BatchInstance{});
   b->traj_steps = 0;
   b->narrow.clear();
+  b->groups.clear();
   b->wide.clear();
-  std::vector<std::pair<double, int2>> items;
+  std::vector<std::pair<double, int2>> items[tk::kBatchShapes];
   std::vector<std::vector<std::pair<double, int2>>> witems;
   for (size_t i = 0; i < n; ++i) {
     Member &m = *b->mem[i];
@@ -469,15 +521,17 @@ int finalize(tk_batch *b) {
     I.psi = m.psi.p;
     I.meta = m.meta.as<tk::TrajMeta>();
     I.tslots = m.tslots.as<unsigned long long>();
-    auto &list = v.G == 1 ? items : witems[wc];
+    auto &list = v.G == 1 ? items[m.variant] : witems[wc];
     for (int k = 0; k < m.M; ++k)
       list.push_back({c->nt * m.step_cost, int2{static_cast<int>(i), k}});
     b->traj_steps += 2ll * m.M * c->nt;
   }
-  // work lists, costliest first
-  auto upload_items = [&](std::vector<std::pair<double, int2>> &src, DevBuf &dev) -> int {
+  // work lists, costliest first (per shape for the one-wave instances)
+  auto costliest_first = [](std::vector<std::pair<double, int2>> &src) {
     std::stable_sort(src.begin(), src.end(),
                      [](const auto &x, const auto &y) { return x.first > y.first; });
+  };
+  auto upload_items = [&](const std::vector<std::pair<double, int2>> &src, DevBuf &dev) -> int {
     std::vector<int2> it(src.size());
     for (size_t q = 0; q < src.size(); ++q) it[q] = src[q].second;
     if (it.empty()) return TK_OK;
@@ -485,10 +539,30 @@ int finalize(tk_batch *b) {
     TK_BHIP(b, hipMemcpy(dev.p, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice));
     return TK_OK;
   };
-  int rc = upload_items(items, b->items_dev);
+  // one-wave instances grouped by shape; one work list, a range per shape
+  std::stable_sort(b->narrow.begin(), b->narrow.end(),
+                   [&](int x, int y) { return b->mem[x]->variant < b->mem[y]->variant; });
+  std::vector<std::pair<double, int2>> all_items;
+  for (size_t q = 0; q < b->narrow.size();) {
+    NarrowGroup g;
+    g.S = b->mem[b->narrow[q]]->variant;
+    g.q0 = q;
+    while (q < b->narrow.size() && b->mem[b->narrow[q]]->variant == g.S) ++q;
+    g.q1 = q;
+    auto &src = items[g.S];
+    costliest_first(src);
+    g.item0 = static_cast<int>(all_items.size());
+    g.n_items = static_cast<int>(src.size());
+    all_items.insert(all_items.end(), src.begin(), src.end());
+    b->groups.push_back(g);
+  }
+  if (b->groups.size() + b->wide.size() > kLaunchSlots)
+    return bfail(b, TK_EUNSUPPORTED, "too many kernel shapes in one batch");
+  int rc = upload_items(all_items, b->items_dev);
   if (rc) return rc;
   for (size_t q = 0; q < b->wide.size(); ++q) {
     b->wide[q]->n_items = static_cast<int>(witems[q].size());
+    costliest_first(witems[q]);
     if ((rc = upload_items(witems[q], b->wide[q]->items_dev))) return rc;
     if ((rc = plan_wide(b, *b->wide[q]))) return rc;
   }
@@ -512,21 +586,29 @@ int finalize(tk_batch *b) {
 // the time from the launch's first block start to the instance's last block end.
 int time_krotov(tk_batch *b, double *ms, std::vector<double> *inst_us, int which = 1) {
   const size_t n = b->mem.size();
-  const unsigned long long never = ~0ull;
-  std::vector<unsigned long long> t_end(n, 0ull);
-  TK_BHIP(b, hipMemcpy(b->t_begin_dev.p, &never, sizeof(never), hipMemcpyHostToDevice));
+  std::vector<unsigned long long> t_begin(kLaunchSlots, ~0ull), t_end(n, 0ull);
+  TK_BHIP(b, hipMemcpy(b->t_begin_dev.p, t_begin.data(), kLaunchSlots * sizeof(unsigned long long),
+                       hipMemcpyHostToDevice));
   TK_BHIP(b, hipMemcpy(b->t_end_dev.p, t_end.data(), n * sizeof(unsigned long long),
                        hipMemcpyHostToDevice));
   int rc = timed(b, [&] { return launch_krotov(b, which); }, ms);
   if (rc) return rc;
   if ((rc = check_errors(b))) return rc;
-  unsigned long long t0 = 0;
-  TK_BHIP(b, hipMemcpy(&t0, b->t_begin_dev.p, sizeof(t0), hipMemcpyDeviceToHost));
+  TK_BHIP(b, hipMemcpy(t_begin.data(), b->t_begin_dev.p, kLaunchSlots * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost));
   TK_BHIP(b, hipMemcpy(t_end.data(), b->t_end_dev.p, n * sizeof(unsigned long long),
                        hipMemcpyDeviceToHost));
+  // each instance's time counts from the start of its own launch
+  std::vector<size_t> slot(n, 0);
+  for (size_t gi = 0; gi < b->groups.size(); ++gi)
+    for (size_t q = b->groups[gi].q0; q < b->groups[gi].q1; ++q) slot[b->narrow[q]] = gi;
+  for (size_t wi = 0; wi < b->wide.size(); ++wi)
+    for (int i : b->wide[wi]->idx) slot[i] = b->groups.size() + wi;
   inst_us->assign(n, 0.0);
-  for (size_t i = 0; i < n; ++i)
-    (*inst_us)[i] = t_end[i] > t0 ? (t_end[i] - t0) * 1e3 / b->clock_khz : 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    const unsigned long long t0 = t_begin[slot[i]];
+    (*inst_us)[i] = t_end[i] > t0 && t0 != ~0ull ? (t_end[i] - t0) * 1e3 / b->clock_khz : 0.0;
+  }
   return TK_OK;
 }
 
@@ -813,9 +895,13 @@ int tk_batch_get_info(const tk_batch *b, tk_batch_info *out) {
   if (!b || !out) return TK_EINVAL;
   out->n_instances = static_cast<int32_t>(b->mem.size());
   out->pass_waves_per_block = b->plan.pass_wpb;
-  out->pass_blocks = b->plan.pass_blocks;
+  out->pass_blocks = 0;
+  out->krotov_blocks = 0;
+  for (const auto &g : b->groups) {
+    out->pass_blocks += g.pass_blocks;
+    out->krotov_blocks += g.kro_blocks;
+  }
   out->krotov_waves_per_block = b->plan.kro_wpb;
-  out->krotov_blocks = b->plan.kro_blocks;
   out->autotuned = b->tuned ? 1 : 0;
   out->last_iteration_ms = b->last_iter_ms;
   out->tuned_pass_ms = b->tuned_pass_ms;

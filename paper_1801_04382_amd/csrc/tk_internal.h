@@ -144,13 +144,13 @@ struct BatchArgs {
   int wave_lds;          // LDS bytes per wave of the batched plain passes
   const int2 *items;     // (instance, trajectory) work of the plain passes (one-wave shapes)
   int n_items;
-  const int *block_inst; // [blocks] instance of each block of the Krotov launch (one-wave)
+  const int *block_inst; // [blocks] instance of each block of a one-wave Krotov launch
   const int2 *witems;    // the same for the instances of multi-wave shapes (one team a block)
   int n_witems;
   const int *wblock_inst;
   uint64_t *iteration;   // iteration of the passes being run (device counter)
   double *J_hist;        // [n_inst][kBatchHistory] J_T by iteration
-  unsigned long long *t_begin;  // earliest block start of the Krotov launch (constant clock)
+  unsigned long long *t_begin;  // earliest block start of one Krotov launch (constant clock)
   unsigned long long *t_end;    // [n_inst] latest block end of each instance
   int *err;
   long long spin_limit;
@@ -185,8 +185,11 @@ const void *grad_reduce_kernel();
 // Batched kernels of a precision (defined in tk_batch.hip).  The shape of an
 // instance is selected inside the kernels by BatchInstance::variant, the index
 // of (R, WS, NC) in variants() among those of the same precision.
+constexpr int kBatchShapes = 4;  // one-wave kernel shapes of the batched kernels
 struct BatchKernels {
-  const void *pass_fw, *pass_bw, *krotov, *fill, *functional, *finish;
+  // one-wave shapes: per shape index
+  const void *pass_fw[kBatchShapes], *pass_bw[kBatchShapes], *krotov[kBatchShapes];
+  const void *fill, *functional, *finish;
   // multi-wave shapes, one team per block: two-wave teams, and eight-wave teams
   // (FP32 only; null in FP64)
   const void *wpass_fw, *wpass_bw, *wkrotov;
