@@ -26,6 +26,8 @@
 //   3. dJ_T/du_ij = -(2/M) sum_k g_kij, summed over k in a fixed order.
 #include <hip/hip_runtime.h>
 
+// plain (not global-view) accesses: this kernel spills, and measured faster so
+#define TK_GENERIC_ACCESS
 #include "tk_device.h"
 #include "tk_internal.h"
 
