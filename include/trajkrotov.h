@@ -259,10 +259,11 @@ TK_API int tk_grad_pathwise(tk_ctx *ctx, int32_t M, const tk_jump *rec, int64_t 
 
 /* A batch holds independent optimisation instances -- each a full problem as
  * set by tk_set_system / tk_set_states / tk_set_pulses, with its own M and
- * seed -- and advances all of them together: one launch runs the costate
- * passes of every instance, one persistent launch runs their sequential
- * Krotov passes side by side (each instance with its own per-step reduction),
- * and one iteration of every instance is replayed as a HIP graph.  Instances
+ * seed -- and advances all of them together: per kernel shape, one launch
+ * runs the costate passes of the shape's instances and one persistent launch
+ * runs their sequential Krotov passes side by side (each instance with its
+ * own per-step reduction; the shapes' launches follow each other), and one
+ * iteration of every instance is replayed as a HIP graph.  Instances
  * may differ in Hilbert dimension, sparsity, M and nt.  Instances whose shape
  * needs several waves per trajectory (d = 216 in FP64, d = 1296 in FP32) run
  * in launches of their own, one team per block, and keep the costates of 64
@@ -280,9 +281,9 @@ typedef struct tk_batch tk_batch; /* opaque */
 typedef struct tk_batch_info {
   int32_t n_instances;
   int32_t pass_waves_per_block;    /* plain (costate / guess) passes         */
-  int32_t pass_blocks;
-  int32_t krotov_waves_per_block;  /* persistent Krotov launch               */
-  int32_t krotov_blocks;
+  int32_t pass_blocks;             /* summed over the one-wave shapes       */
+  int32_t krotov_waves_per_block;  /* persistent Krotov launches            */
+  int32_t krotov_blocks;           /* summed over the one-wave shapes       */
   int32_t autotuned;               /* 1 once the tile shapes are chosen      */
   double last_iteration_ms;        /* last replayed iteration (HIP events)  */
   double tuned_pass_ms;            /* best costate pass seen by the tuner   */
