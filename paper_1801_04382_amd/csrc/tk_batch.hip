@@ -17,9 +17,9 @@
 // After a trajectory reaches t_j its own FP64 share of
 // s_ij = sum_k Im <chi_k(t_j)|H_i|psi_hat_k(t_j)> is published into a
 // per-trajectory slot (initialised to a sentinel); every block of the instance
-// waits for the M shares of step j and sums them in one fixed order (lane l
-// adds k = l, l + 64, ... in increasing k; then the wave tree).  The update is
-// therefore independent of how trajectories are split over waves and blocks:
+// waits for the M shares of step j, all its waves reading parts of them, and
+// sums them in one fixed order (block_gather).  The update is therefore
+// independent of how trajectories are split over waves and blocks:
 // an instance gives bit-identical pulses whatever the tile shape chosen and
 // whatever else runs in the batch.
 //
@@ -125,24 +125,33 @@ __device__ __forceinline__ void load_shares(const unsigned long long *row, int M
   }
 }
 
-// Waits for the M shares of one step and sums them in a fixed order (lane l
-// takes k = l, l + 64, ... in increasing k; then the wave reduction).  The
-// trajectories are read in groups of 64 CH; the loads of the next group are in
-// flight while the current one is checked, and a group with a share still
-// missing is read again until it is complete.  Returns false if the spin
-// limit is reached or another block gave up.
+// The M shares of one step are summed in a fixed order that does not depend on
+// how trajectories, waves or blocks are split: the trajectories form groups of
+// 64 CH (k = 64 (CH q + qq) + l, qq < CH), and group q belongs to part
+// q mod kGatherParts.  Lane l sums its column of each part over the part's
+// groups in increasing k; the parts' column sums are added in part order, then
+// reduced over the lanes (wave tree).  Every wave of a block reads some of the
+// parts (wave w takes parts w, w + waves, ...), so a block has up to
+// kGatherParts groups of loads in flight instead of one.
+constexpr int kGatherParts = 4;
+
+// Column sums of part r (lane, control); waits for missing shares, reading a
+// group again until it is complete while the part's next group is in flight.
+// Returns false if the spin limit is reached or another block gave up.
 template <int NCX>
-__device__ bool gather_shares(const unsigned long long *row, int M, int lane,
-                              long long spin_limit, int *err, double (&acc)[NCX]) {
+__device__ bool gather_part(const unsigned long long *row, int M, int lane, int r,
+                            long long spin_limit, int *err, double (&acc)[NCX]) {
   constexpr int CH = 4;
+  constexpr int kStride = CH * kGatherParts;  // between a part's groups, in units of 64
 #pragma unroll
   for (int c = 0; c < NCX; ++c) acc[c] = 0.0;
+  if (r * CH * kWave >= M) return true;
   long long spins = 0;
   unsigned long long cur[CH][NCX], nxt[CH][NCX];
-  load_shares<NCX, CH>(row, M, lane, 0, cur);
-  for (int q0 = 0; q0 * kWave < M; q0 += CH) {
-    const bool more = (q0 + CH) * kWave < M;
-    if (more) load_shares<NCX, CH>(row, M, lane, q0 + CH, nxt);
+  load_shares<NCX, CH>(row, M, lane, r * CH, cur);
+  for (int q0 = r * CH; q0 * kWave < M; q0 += kStride) {
+    const bool more = (q0 + kStride) * kWave < M;
+    if (more) load_shares<NCX, CH>(row, M, lane, q0 + kStride, nxt);
     __builtin_amdgcn_sched_barrier(0);
     for (;;) {
       int missing = 0;
@@ -168,8 +177,48 @@ __device__ bool gather_shares(const unsigned long long *row, int M, int lane,
         for (int c = 0; c < NCX; ++c) cur[qq][c] = nxt[qq][c];
     }
   }
-  wave_sum_n<NCX>(acc);
   return true;
+}
+
+// The update's sums s_upd[c] of one step (0 without controls), from the shares
+// in `row`, by the block's `nwaves` waves.  On a timeout the block's abort flag
+// is set.  Ends with the sums in s_upd for wave 0 only: the caller's block
+// barrier publishes them.
+template <int NCX>
+__device__ __forceinline__ void block_gather(const unsigned long long *row, int M, bool active,
+                                             const BatchArgs &b, int nwaves,
+                                             double (&s_part)[kGatherParts][NCX][kWave],
+                                             double *s_upd, int *s_abort) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (active) {
+    bool ok = true;
+    for (int r = wib; r < kGatherParts && ok; r += nwaves) {
+      double acc[NCX];
+      ok = gather_part<NCX>(row, M, lane, r, b.spin_limit, b.err, acc);
+#pragma unroll
+      for (int c = 0; c < NCX; ++c) s_part[r][c][lane] = acc[c];
+    }
+    if (!ok && lane == 0) {
+      atomicOr(b.err, kErrSyncTimeout);
+      *s_abort = 1;
+    }
+  }
+  block_sync_lds();
+  if (wib == 0) {
+    double acc[NCX];
+#pragma unroll
+    for (int c = 0; c < NCX; ++c) acc[c] = 0.0;
+    if (active)
+#pragma unroll
+      for (int r = 0; r < kGatherParts; ++r)
+#pragma unroll
+        for (int c = 0; c < NCX; ++c) acc[c] += s_part[r][c][lane];
+    wave_sum_n<NCX>(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int c = 0; c < NCX; ++c) s_upd[c] = acc[c];
+  }
 }
 
 template <typename real, int R, int WS, int NC>
@@ -183,6 +232,7 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
   const int lane = tm.lane;
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int wpb = blockDim.x / kWave;
+  __shared__ double s_part[kGatherParts][NCX][kWave];  // column sums of the gather's parts
   LaneOp<real, R, WS, NC, 1> op;
   const Terms<real, R, 1> T =
       block_setup<real, R, WS, NC, 1>(a, smem, wib, tm, terms_bytes<real, R, 1>(a.kbuf), op);
@@ -238,20 +288,8 @@ __device__ void batch_krotov_instance(const BatchArgs &b, const BatchInstance &I
     block_sync_lds();  // every wave has used the previous step's s_upd
     if (lb == 0 && j > 0 && threadIdx.x < NCX)
       gmem(a.u_new)[static_cast<size_t>(threadIdx.x) * a.nt + j - 1] = pick(u_prev, threadIdx.x);
-    if (wib == 0) {
-      double acc[NCX];
-      const bool ok = a.n_ctrl == 0 ||
-                      gather_shares<NCX>(I.tslots + static_cast<size_t>(j) * row_len, a.M, lane,
-                                         b.spin_limit, b.err, acc);
-      if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < NCX; ++c) s_upd[c] = ok && a.n_ctrl > 0 ? acc[c] : 0.0;
-        if (!ok) {
-          atomicOr(b.err, kErrSyncTimeout);
-          *s_abort = 1;
-        }
-      }
-    }
+    block_gather<NCX>(I.tslots + static_cast<size_t>(j) * row_len, a.M, a.n_ctrl > 0, b, wpb,
+                      s_part, s_upd, s_abort);
     block_sync_lds();
     if (*s_abort) return;  // uniform across the block
     double uj[NCX];
@@ -534,6 +572,7 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
   const PassArgs &a = I.fw;
   const int nt = a.nt, M = a.M;
   const int nteam = I.nblocks, w = lb;
+  __shared__ double s_part[kGatherParts][NCX][kWave];  // column sums of the gather's parts
   const int kbuf = max(I.fw.kbuf, I.bw.kbuf);
   const Terms<real, R, G> T = wide_terms<real, R, G>(smem, kbuf, tm);
   cx<real> *psi_g = static_cast<cx<real> *>(I.psi);
@@ -590,20 +629,8 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
       block_sync_lds();  // every wave has used the previous step's s_upd
       if (lb == 0 && j > 0 && threadIdx.x < NCX)
         gmem(a.u_new)[static_cast<size_t>(threadIdx.x) * nt + j - 1] = pick(u_prev, threadIdx.x);
-      if (threadIdx.x < kWave) {
-        double acc[NCX];
-        const bool ok = a.n_ctrl == 0 ||
-                        gather_shares<NCX>(I.tslots + static_cast<size_t>(j) * row_len, M,
-                                           tm.lane, b.spin_limit, b.err, acc);
-        if (tm.lane == 0) {
-#pragma unroll
-          for (int c = 0; c < NCX; ++c) s_upd[c] = ok && a.n_ctrl > 0 ? acc[c] : 0.0;
-          if (!ok) {
-            atomicOr(b.err, kErrSyncTimeout);
-            *s_abort = 1;
-          }
-        }
-      }
+      block_gather<NCX>(I.tslots + static_cast<size_t>(j) * row_len, M, a.n_ctrl > 0, b, G, s_part,
+                        s_upd, s_abort);
       block_sync_lds();
       if (*s_abort) return;  // uniform across the block
       double uj[NCX];

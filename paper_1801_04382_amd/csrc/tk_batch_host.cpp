@@ -241,6 +241,13 @@ tk::BatchArgs wide_args(tk_batch *b, WideClass &w) {
   return a;
 }
 
+// LDS bytes a kernel declares statically (beside its dynamic LDS).
+size_t static_lds(const void *kernel) {
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) return tk::kLdsBytes;
+  return fa.sharedSizeBytes;
+}
+
 // Pass plan with `wpb` waves per block: per shape, as many blocks as are
 // co-resident (the shapes' launches run one after another).
 int plan_pass(tk_batch *b, int wpb) {
@@ -278,8 +285,8 @@ int plan_krotov(tk_batch *b, int wpb, double frac, double sync_cost,
       const Member &m = *b->mem[b->narrow[q]];
       lds = std::max(lds, tk::block_lds_bytes(*m.c->var, wpb, m.kbuf_fw, 0));
     }
-    if (lds > tk::kLdsBytes) return TK_EUNSUPPORTED;
     const void *k = b->kern.krotov[g.S];
+    if (lds + static_lds(k) > tk::kLdsBytes) return TK_EUNSUPPORTED;
     TK_BHIP(b, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
     int occ = 0;
@@ -305,7 +312,8 @@ int plan_wide(tk_batch *b, WideClass &w) {
     const Member &m = *b->mem[i];
     lds = std::max(lds, tk::block_lds_bytes(*m.c->var, 1, std::max(m.kbuf_fw, m.kbuf_bw), 0));
   }
-  if (lds > tk::kLdsBytes) return bfail(b, TK_EUNSUPPORTED, "team term vectors do not fit in LDS");
+  if (lds + static_lds(w.krotov) > tk::kLdsBytes)
+    return bfail(b, TK_EUNSUPPORTED, "team term vectors do not fit in LDS");
   w.lds = lds;
   int occ = tk::kLdsBytes;
   for (const void *k : {w.pass_fw, w.pass_bw, w.krotov}) {
