@@ -144,6 +144,11 @@ TK_API const char *tk_last_error(const tk_ctx *ctx);
 /* Version string of the library (static storage). */
 TK_API const char *tk_version(void);
 
+/* Digest of the sources and flags the library was built from (static
+ * storage); the Python binding compares it with the sources beside it and
+ * refuses a stale build. */
+TK_API const char *tk_build_id(void);
+
 /* ---- problem definition -------------------------------------------------- */
 
 /* Define H0, the n_ctrl control Hamiltonians H_ctrl[i] and the n_jump

@@ -820,7 +820,12 @@ int functional_value(tk_ctx *c, int M, double *J) {
 // ===========================================================================
 extern "C" {
 
-const char *tk_version(void) { return "trajkrotov 0.1 (gfx950)"; }
+const char *tk_version(void) { return "trajkrotov 0.2 (gfx950)"; }
+
+#ifndef TK_BUILD_ID
+#define TK_BUILD_ID "unknown"
+#endif
+const char *tk_build_id(void) { return TK_BUILD_ID; }
 
 const char *tk_last_error(const tk_ctx *ctx) {
   if (!ctx) return "no context";

@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from .build import lib_path
+from .build import lib_path, source_hash
 
 # ---------------------------------------------------------------------------
 # C types
@@ -91,6 +91,7 @@ _ctx_p = ctypes.c_void_p
 
 _SIGNATURES = {
     "tk_version": (ctypes.c_char_p, []),
+    "tk_build_id": (ctypes.c_char_p, []),
     "tk_last_error": (ctypes.c_char_p, [_ctx_p]),
     "tk_create": (ctypes.c_int, [_P(_ctx_p), ctypes.c_int, ctypes.c_int]),
     "tk_destroy": (None, [_ctx_p]),
@@ -134,8 +135,14 @@ EXPORTED = tuple(_SIGNATURES)
 
 
 def load_library(path: Optional[str] = None) -> ctypes.CDLL:
-    """Load libtrajkrotov (``TRAJKROTOV_LIB`` may name another build of it)."""
-    path = path or os.environ.get("TRAJKROTOV_LIB") or lib_path()
+    """Load libtrajkrotov (``TRAJKROTOV_LIB`` may name another build of it).
+
+    The in-tree library must have been built from the sources beside it: a
+    library whose build id differs from the digest of the current sources is
+    refused (rebuild with ``python -m paper_1801_04382_amd.build``).
+    """
+    explicit = path or os.environ.get("TRAJKROTOV_LIB")
+    path = explicit or lib_path()
     if not os.path.exists(path):
         raise ImportError(f"libtrajkrotov not built ({path}); run "
                           "`python -m paper_1801_04382_amd.build`")
@@ -144,6 +151,11 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if not explicit:
+        built, want = lib.tk_build_id().decode(), source_hash()
+        if built != want:
+            raise ImportError(f"libtrajkrotov at {path} is stale (built from {built}, sources "
+                              f"are {want}); run `python -m paper_1801_04382_amd.build`")
     return lib
 
 
@@ -205,6 +217,10 @@ def records_array(buf: np.ndarray, n: int) -> np.ndarray:
 
 def tk_version() -> str:
     return _lib.tk_version().decode()
+
+
+def tk_build_id() -> str:
+    return _lib.tk_build_id().decode()
 
 
 def tk_create(device: int = 0, precision: int = TK_FP64) -> int:

@@ -76,3 +76,11 @@ def test_create_reports_missing_device_or_succeeds_on_gfx950():
         assert code == tk.TK_ENODEV and not h.value
     assert tk._lib.tk_create(ctypes.byref(h), 0, 7) == tk.TK_EINVAL
     assert tk._lib.tk_last_error(None) == b"no context"
+
+
+def test_library_is_built_from_the_sources_beside_it():
+    """The binding refuses a library built from other sources (a stale build)."""
+    from paper_1801_04382_amd import build
+    from paper_1801_04382_amd import trajkrotov as tk
+    assert tk.tk_build_id() == build.source_hash()
+    assert build.source_hash(defines=("TK_SOMETHING",)) != build.source_hash()

@@ -360,3 +360,105 @@ def test_functional_definition():
     assert abs(krotov.functional(tau) - (1 - 1.5 / 3)) < 1e-15
     # the costate boundary is <tgt|psi> tgt (derivative of J_T wrt <psi|)
     assert abs(tau[0] - 1) < 1e-15 and abs(tau[2] - 1 / math.sqrt(2)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# costate (backward) jumps: the reverse clock and the recorded times
+# ---------------------------------------------------------------------------
+
+def test_backward_single_cavity_closed_form():
+    """Costate from one photon, atom in g, no drive, run backward from T.
+
+    exp(+i H_eff^+ tau) with H_eff = H - (i/2) kappa a^+a damps the photon as
+    exp(-kappa tau/2) in amplitude, so before its first jump the backward
+    state has ||chi~(t)||^2 = exp(-kappa (T - t)); the jump happens when that
+    reaches the threshold r0 of stream (seed, k, iteration, direction 1),
+    i.e. at t = T + ln(r0)/kappa, recorded with direction 1 in the step
+    that contains it; the jump leaves the empty (dark) cavity.
+    """
+    from oracle.mcwf import backward_pass
+    spec, sysd = _single_cavity()
+    i1 = basis_index(spec, [G_LEVEL], [1])
+    i0 = basis_index(spec, [G_LEVEL], [0])
+    chiT = np.zeros(spec.dim, complex)
+    chiT[i1] = 1.0
+    T, nt, M, seed, it = 5.0, 10, 24, 8, 3
+    dt = T / nt
+    ens, chi_hat = backward_pass(sysd, chiT[None, :].repeat(M, 0), np.zeros((1, nt)), T, M,
+                                 seed, it)
+    first = {}
+    for rec in ens.records:
+        assert rec.direction == 1
+        first.setdefault(rec.traj, rec)
+    n_jumps = 0
+    for k in range(M):
+        r0 = philox.TrajectoryStream(seed, k, it, 1).threshold(0)
+        t_ref = T + math.log(r0)  # kappa = 1
+        if t_ref > 0.0:
+            rec = first[k]
+            assert abs(rec.t - t_ref) < 1e-11, (rec.t, t_ref)
+            assert rec.step == int(t_ref // dt) and rec.ordinal == 0 and rec.op == 0
+            assert sum(r.traj == k for r in ens.records) == 1
+            # normalised costates: |g,1> after t_ref, |g,0> before it
+            for j in range(nt):
+                ref = i1 if j * dt > t_ref else i0
+                assert abs(abs(chi_hat[j, k, ref]) - 1.0) < 1e-12
+            n_jumps += 1
+        else:
+            assert k not in first
+            # no jump: the norm left at t = 0 is exp(-kappa T)
+            assert abs(norm2(ens.psi[k]) - math.exp(-T)) < 1e-13
+    assert n_jumps >= 10
+
+
+def test_backward_two_jumps_inside_one_step():
+    """Two photons, one step of length T run backward: the first jump is at
+    elapsed time e1 = -ln(r0)/2 (decay rate 2 kappa), the second at
+    e2 = e1 - ln(r1) (rate kappa), recorded as T - e1 and T - e2."""
+    from oracle.mcwf import backward_pass
+    spec, sysd = _single_cavity(n_fock=3)
+    chiT = np.zeros(spec.dim, complex)
+    chiT[basis_index(spec, [G_LEVEL], [2])] = 1.0
+    T, M, seed, it = 40.0, 12, 6, 2
+    ens, _ = backward_pass(sysd, chiT[None, :].repeat(M, 0), np.zeros((1, 1)), T, M, seed, it)
+    checked = 0
+    for k in range(M):
+        st = philox.TrajectoryStream(seed, k, it, 1)
+        e1 = -math.log(st.threshold(0)) / 2.0
+        e2 = e1 - math.log(st.threshold(1))
+        recs = sorted((r for r in ens.records if r.traj == k), key=lambda r: r.ordinal)
+        if e2 < T:
+            assert [(r.step, r.ordinal, r.direction) for r in recs] == [(0, 0, 1), (0, 1, 1)]
+            assert abs(recs[0].t - (T - e1)) < 1e-11 and abs(recs[1].t - (T - e2)) < 1e-10
+            checked += 1
+    assert checked >= 8
+
+
+# ---------------------------------------------------------------------------
+# the trajectory average converges to rho as 1/sqrt(M)
+# ---------------------------------------------------------------------------
+
+def test_ensemble_error_falls_as_inverse_sqrt_M():
+    """RMS Frobenius error of (1/M) sum_k |psi_hat_k><psi_hat_k| against the
+    master-equation rho(T), over disjoint groups of M trajectories of one run
+    of 16384, for M = 256 .. 16384: the log-log slope is -1/2 (trajectory
+    expansion of rho, Sec. 2.1; independent samples)."""
+    spec, sysd = _single_cavity()
+    u = np.full((1, 8), 0.8)
+    T, total, seed = 3.0, 16384, 12
+    psi0 = initial_state(spec)
+    ens, _ = forward_pass(sysd, psi0, u, T, total, seed, 0)
+    psi_hat = ens.normalised()
+    rho = lindblad.propagate_rho(sysd, np.outer(psi0, psi0.conj()), u, T)
+    Ms = [256, 1024, 4096, 16384]
+    rms = []
+    for M in Ms:
+        errs = []
+        for g in range(total // M):
+            p = psi_hat[g * M:(g + 1) * M]
+            rho_m = p.T @ p.conj() / M
+            errs.append(np.linalg.norm(rho_m - rho) ** 2)
+        rms.append(math.sqrt(np.mean(errs)))
+    slope = np.polyfit(np.log(Ms), np.log(rms), 1)[0]
+    assert len(ens.records) > 2000
+    assert abs(slope + 0.5) < 0.1, (slope, rms)
