@@ -28,6 +28,15 @@ Readings taken here:
 * Iterations: iteration 0 is a forward pass with the guess; iteration n >= 1 is
   a backward pass with u^(n-1) (random stream iteration n, direction 1)
   followed by the sequential forward pass (iteration n, direction 0).
+
+The cross-trajectory update of Sec. 2.3 (eq. cross_traj_update) is here too:
+  Delta u_i(t) = S_i(t) / (M^2 lambda_i)
+                 sum_{k,k'} Im[<xi_k(t)| H_i |Psi_k'(t)> <Psi_k'(t)|xi_k(t)>]
+with xi_k propagated backward from xi_k(T) = Psi_tgt.  Readings: xi_k runs
+the same reverse-time MCWF rules and streams as the costates above, and enters
+normalised (like the forward states), so that (1/M) sum_k |xi_k><xi_k| is the
+trajectory estimate of the backward-propagated target projector; the sums
+over k and k' are taken as printed, as two M x M overlap matrices per control.
 """
 
 from __future__ import annotations
@@ -125,4 +134,60 @@ def optimise(system: System, psi0, psi_tgt, u0, S, lam, T, M, seed, n_iter,
         if keep_chi:
             res.chi.append(chi)
         u, tau = p.u, p.tau
+    return res
+
+
+# ---------------------------------------------------------------------------
+# cross-trajectory update (Sec. 2.3, eq. cross_traj_update)
+# ---------------------------------------------------------------------------
+
+def cross_costates(system: System, psi_tgt, u, T, M, seed, iteration, instance=0):
+    """Backward trajectories from xi_k(T) = Psi_tgt: normalised xi_k(t_j), [nt, M, d]."""
+    xi_T = np.broadcast_to(psi_tgt / np.linalg.norm(psi_tgt), (M, psi_tgt.shape[0]))
+    ens, xi_hat = backward_pass(system, xi_T, u, T, M, seed, iteration, instance)
+    return xi_hat, ens.records
+
+
+def cross_update_term(system: System, xi_j: np.ndarray, psi_hat_j: np.ndarray) -> np.ndarray:
+    """s_i = sum_{k,k'} Im[<xi_k|H_i|Psi_k'> <Psi_k'|xi_k>] for every control i."""
+    B = psi_hat_j.conj() @ xi_j.T  # B[k', k] = <Psi_k'|xi_k>
+    s = np.zeros(len(system.H_ctrl))
+    for i, Hi in enumerate(system.H_ctrl):
+        A = xi_j.conj() @ (psi_hat_j @ Hi.T).T  # A[k, k'] = <xi_k|H_i|Psi_k'>
+        s[i] = float(np.sum(np.imag(A * B.T)))
+    return s
+
+
+def sequential_forward_cross(system: System, psi0, psi_tgt, u_old, xi, S, lam, T, M, seed,
+                             iteration, instance=0) -> PassResult:
+    """Forward pass with the sequential cross-trajectory Krotov update."""
+    u_new = np.array(u_old, dtype=np.float64, copy=True)
+
+    def hook(j: int, ens: Ensemble) -> np.ndarray:
+        s = cross_update_term(system, xi[j], ens.normalised())
+        u_new[:, j] = u_old[:, j] + S[:, j] * s / (lam * M * M)
+        return u_new[:, j]
+
+    ens, _ = forward_pass(system, psi0, u_new, T, M, seed, iteration, instance,
+                          pulse_hook=hook)
+    psi_hat = ens.normalised()
+    tau = overlaps(psi_hat, psi_tgt)
+    return PassResult(psi_hat, tau, functional(tau), ens.records, u_new)
+
+
+def optimise_cross(system: System, psi0, psi_tgt, u0, S, lam, T, M, seed, n_iter,
+                   instance=0) -> OptimisationResult:
+    """Iteration 0 = guess forward pass; then n_iter cross-trajectory iterations."""
+    first = plain_forward(system, psi0, psi_tgt, u0, T, M, seed, 0, instance)
+    res = OptimisationResult([first.J_T], [first.u], [first], [])
+    u = first.u
+    for n in range(1, n_iter + 1):
+        xi, brec = cross_costates(system, psi_tgt, u, T, M, seed, n, instance)
+        p = sequential_forward_cross(system, psi0, psi_tgt, u, xi, S, lam, T, M, seed, n,
+                                     instance)
+        res.J_T.append(p.J_T)
+        res.u.append(p.u)
+        res.passes.append(p)
+        res.backward_records.append(brec)
+        u = p.u
     return res

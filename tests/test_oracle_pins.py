@@ -462,3 +462,153 @@ def test_ensemble_error_falls_as_inverse_sqrt_M():
     slope = np.polyfit(np.log(Ms), np.log(rms), 1)[0]
     assert len(ens.records) > 2000
     assert abs(slope + 0.5) < 0.1, (slope, rms)
+
+
+# ---------------------------------------------------------------------------
+# pulse-noise measure (Sec. 3.4): Savitzky-Golay five-point cubic
+# ---------------------------------------------------------------------------
+
+def test_noise_filter_matches_scipy_savgol():
+    """The filter equals SciPy's Savitzky-Golay filter (window 5, order 3,
+    polynomial fit at the ends) -- a library routine."""
+    import scipy.signal
+    from oracle.noise import smooth_cubic5
+    rng = np.random.default_rng(4)
+    for n in (5, 6, 17, 400):
+        x = rng.normal(size=n) + np.linspace(0, 3, n) ** 2
+        ref = scipy.signal.savgol_filter(x, 5, 3, mode="interp")
+        assert np.abs(smooth_cubic5(x) - ref).max() < 1e-12
+
+
+def test_noise_filter_closed_forms():
+    """Cubic pulses pass unchanged (nu = 0); the centred weights are the
+    classic (-3, 12, 17, 12, -3)/35; an alternating ripple of amplitude e on a
+    smooth pulse leaves 48/35 e at every interior sample."""
+    from oracle.noise import pulse_noise, smooth_cubic5
+    t = np.linspace(-1.0, 2.0, 60)
+    cubic = 0.3 - 0.7 * t + 0.2 * t ** 2 + 0.9 * t ** 3
+    assert np.abs(smooth_cubic5(cubic) - cubic).max() < 1e-12
+    assert pulse_noise(cubic[None, :], 5.0)[0] < 1e-11
+    imp = np.zeros(11)
+    imp[5] = 1.0
+    w = smooth_cubic5(imp)[3:8]  # response of the samples around the impulse
+    assert np.abs(w * 35 - np.array([-3, 12, 17, 12, -3])).max() < 1e-12
+    e, n, T = 1e-3, 50, 10.0
+    ripple = e * (-1.0) ** np.arange(n)
+    resid = np.abs(ripple - smooth_cubic5(ripple))
+    assert np.abs(resid[2:-2] - 48.0 / 35.0 * e).max() < 1e-15
+    nu = pulse_noise(ripple[None, :], T)[0]
+    assert abs(nu - T / n * resid.sum()) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# cross-trajectory update (Sec. 2.3): kappa = 0, one trajectory
+# ---------------------------------------------------------------------------
+
+def test_cross_update_equals_independent_update_at_first_step():
+    """Without dissipation and with M = 1 the backward state xi and the costate
+    chi = tau chi_hat are the same unitary trajectory, and at t = 0 the forward
+    state is still psi0, so <psi0|xi(0)> = <psi(T)|tgt> = conj(tau): the two
+    updates of the first interval coincide (to rounding)."""
+    spec, sysd, tgt = _unitary_problem()
+    T, nt = 4.0, 100
+    rng = np.random.default_rng(7)
+    u0 = 0.6 + 0.2 * rng.normal(size=(2, nt))
+    S, lam = np.ones((2, nt)), np.full(2, 3.0)
+    ind = krotov.optimise(sysd, initial_state(spec), tgt, u0, S, lam, T, 1, 0, 1)
+    crs = krotov.optimise_cross(sysd, initial_state(spec), tgt, u0, S, lam, T, 1, 0, 1)
+    d_ind = ind.u[1][:, 0] - u0[:, 0]
+    d_crs = crs.u[1][:, 0] - u0[:, 0]
+    assert np.abs(d_ind).max() > 1e-4
+    assert np.abs(d_crs - d_ind).max() < 1e-13 * np.abs(d_ind).max() + 1e-16
+
+
+def test_cross_update_approaches_independent_update_as_lambda_grows():
+    """kappa = 0, M = 1: both updates are lambda^-1 times the same first-order
+    gradient; they differ only through the updated forward state in the
+    overlap <psi^(1)(t)|xi(t)>, i.e. at order lambda^-2: doubling lambda
+    quarters the gap, while the updates themselves halve."""
+    spec, sysd, tgt = _unitary_problem()
+    T, nt = 4.0, 100
+    rng = np.random.default_rng(8)
+    u0 = 0.6 + 0.2 * rng.normal(size=(2, nt))
+    S = np.ones((2, nt))
+    gaps, sizes = [], []
+    for lam in (20.0, 40.0):
+        L = np.full(2, lam)
+        ind = krotov.optimise(sysd, initial_state(spec), tgt, u0, S, L, T, 1, 0, 1)
+        crs = krotov.optimise_cross(sysd, initial_state(spec), tgt, u0, S, L, T, 1, 0, 1)
+        gaps.append(np.abs(crs.u[1] - ind.u[1]).max())
+        sizes.append(np.abs(ind.u[1] - u0).max())
+    assert 1.8 < sizes[0] / sizes[1] < 2.2
+    assert 3.4 < gaps[0] / gaps[1] < 4.6, gaps
+    assert gaps[0] < 0.2 * sizes[0]
+
+
+def test_cross_update_with_jumps_is_real_and_finite():
+    """With dissipation and several trajectories the cross update runs the
+    reverse-time MCWF rules for xi; each term sum is real-valued input to a
+    real pulse (the imaginary part of a complex sum), finite, and bounded by
+    ||H_i|| (|<xi|H_i|psi><psi|xi>| <= ||H_i|| for unit vectors)."""
+    spec = CascadeSpec(2, 2)
+    H0, Hc, L = build_cascade(spec)
+    sysd = System.from_sparse(H0, Hc, L)
+    from workloads.cascade import w_target
+    T, nt, M = 10.0, 60, 6
+    u0 = np.full((2, nt), 0.7)
+    res = krotov.optimise_cross(sysd, initial_state(spec), w_target(spec), u0,
+                                np.ones((2, nt)), np.full(2, 2.0), T, M, 3, 1)
+    du = res.u[1] - u0
+    assert np.all(np.isfinite(du))
+    assert np.abs(du).max() <= 0.5 / 2.0 + 1e-12
+    assert len(res.backward_records[0]) > 0
+
+
+# ---------------------------------------------------------------------------
+# density-matrix (Liouville-space) optimisation, Sec. 2.2
+# ---------------------------------------------------------------------------
+
+def test_rho_functional_and_adjoint_propagation():
+    """<<P(t)|rho(t)>> is the same at every t for the adjoint backward P and
+    the forward rho (the adjoint map), so 1 - <<P(0)|rho(0)>> = J_T; and the
+    functional equals 1 - the trajectory-free fidelity of the master equation."""
+    from oracle import density
+    spec = CascadeSpec(2, 2)
+    H0, Hc, L = build_cascade(spec)
+    sysd = System.from_sparse(H0, Hc, L)
+    from workloads.cascade import w_target
+    tgt = w_target(spec)
+    rng = np.random.default_rng(5)
+    nt, T = 30, 6.0
+    u = rng.normal(0.5, 0.3, (2, nt))
+    psi0 = initial_state(spec)
+    rhos = density.forward_rho(sysd, psi0, u, T, keep=True)
+    P = density.backward_P(sysd, tgt, u, T)
+    J = density.rho_functional(rhos[-1], tgt)
+    ovl = [np.trace(P[j].conj().T @ rhos[j]) for j in range(nt)]
+    assert np.abs(np.array(ovl) - (1.0 - J)).max() < 1e-12
+    rho_ref = lindblad.propagate_rho(sysd, np.outer(psi0, psi0.conj()), u, T)
+    assert abs(J - (1.0 - np.real(tgt.conj() @ rho_ref @ tgt))) < 1e-12
+    assert 0.0 < J < 1.0
+
+
+def test_rho_update_is_twice_the_cross_update_for_pure_states():
+    """kappa = 0 and a pure initial state: P(t) = |xi(t)><xi(t)| and
+    rho(t) = |psi(t)><psi(t)| exactly, so Im <<P|[H_i, rho]>> =
+    2 Im[<xi|H_i|psi><psi|xi>]: the density-matrix pass equals the
+    cross-trajectory pass with one trajectory at twice the step (lambda / 2),
+    interval by interval, although one propagates d x d matrices with the
+    Liouvillian and the other wave functions."""
+    from oracle import density
+    spec, sysd, tgt = _unitary_problem()
+    T, nt = 4.0, 80
+    rng = np.random.default_rng(9)
+    u0 = 0.6 + 0.2 * rng.normal(size=(2, nt))
+    S, lam = np.ones((2, nt)), np.full(2, 4.0)
+    rho = density.optimise_rho(sysd, initial_state(spec), tgt, u0, S, lam, T, 2)
+    crs = krotov.optimise_cross(sysd, initial_state(spec), tgt, u0, S, lam / 2.0, T, 1, 0, 2)
+    for n in (1, 2):
+        assert np.abs(rho.u[n] - crs.u[n]).max() < 1e-10, n
+        assert abs(rho.J_T[n] - crs.J_T[n]) < 1e-10
+    assert np.abs(rho.u[2] - u0).max() > 1e-3
+    assert rho.J_T[2] < rho.J_T[0]  # monotone without dissipation
