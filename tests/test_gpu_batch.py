@@ -98,7 +98,9 @@ def test_batch_agrees_with_single_system_path(tk):
 
 
 def test_batch_fp32_form_against_oracle(tk):
-    ws = mixed_instances()[:3]
+    """All four mixed instances in FP32, the d = 216 one (one-wave, four rows
+    per lane) included."""
+    ws = mixed_instances()
     with tk.Batch(precision="fp32") as b:
         for w in ws:
             b.add(w)
@@ -113,34 +115,27 @@ def test_batch_of_uneven_instances_at_scale(tk):
     """Eight instances of the batching workload (chains of 2, 3 or 4 nodes --
     this draw has four d = 1296 instances, run by the eight-wave kernels with
     costate segments --, M in [64, 2048], nt in [500, 4000]), FP32, two
-    iterations: every J_T is a valid fidelity error, and the first instance
-    agrees with the single-system path where that path takes it (its Krotov
-    pass keeps the states in LDS; at d = 1296 it holds fewer trajectories than
-    the 1328 of this draw's first instance)."""
+    iterations: every J_T is a valid fidelity error, and the two d = 36
+    instances of the draw (M = 675, nt = 643 and M = 96, nt = 1113) agree with
+    the oracle's own runs of them (stored by tests/golden/make_golden.py)."""
+    import os
     ws = batch_instances(8, seed=0, nodes=(2, 3, 4))
     with tk.Batch(precision="fp32") as b:
         for w in ws:
             b.add(w)
         J = b.krotov_iterate(2)
         info = b.info()
-        u0 = b.get_pulses(0)
+        u = {i: b.get_pulses(i) for i in (1, 2)}
     say("  uneven batch", [(w.dim, w.M, w.nt) for w in ws], info)
     assert info["multiwave_instances"] == sum(1 for w in ws if w.dim == 1296)
     assert np.all(np.isfinite(J)) and np.all(J >= 0.0) and np.all(J <= 1.0 + 1e-12)
-    w = ws[0]
-    with tk.Context(precision="fp32") as ctx:
-        ctx.load(w)
-        # the single-system path keys its streams with instance 0
-        if w.instance == 0:
-            try:
-                Js, _, _ = ctx.krotov_iterate(w.M, w.seed, 2, rec_cap=0)
-            except tk.TkError as e:
-                assert e.code == tk.TK_EUNSUPPORTED and w.dim == 1296
-                say("  instance 0: single-system Krotov pass does not take", w.M, "trajectories")
-                return
-            say("  instance 0 batch", J[0].tolist(), "single", Js.tolist())
-            assert max_abs(J[0], Js) <= 1e-6
-            assert max_abs(u0, ctx.get_pulses()) <= 1e-6
+    g = dict(np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                  "batch_seed0_inst1_2.npz")))
+    for i in (1, 2):
+        assert ws[i].dim == 36
+        say("  instance", i, "J gpu", J[i].tolist(), "oracle", g[f"J{i}"].tolist())
+        assert max_abs(J[i], g[f"J{i}"]) <= 1e-4
+        assert max_abs(u[i], g[f"u{i}"][-1]) <= 1e-4
 
 
 def test_batch_error_paths(tk):

@@ -1,0 +1,249 @@
+"""GPU parity at the launch shapes the larger workloads run, against the oracle.
+
+* The sequential Krotov pass with its full grid exchange: d = 81, M = 1024
+  trajectories (256 blocks of 4 one-wave teams), and passes whose waves keep
+  several trajectories' states in LDS (M = 1100: more trajectories than one
+  cooperative launch holds one to a wave), in FP64 (d = 36) and in the FP32
+  four-rows-per-lane shape of d = 216.
+* Several jumps inside one substep, forward and backward.
+* The pathwise gradient on the eight-wave d = 1296 path over many 64-step
+  checkpoint segments, against the oracle's adjoint and its central
+  differences.
+
+Expected values of the cases whose oracle runs take minutes are stored under
+tests/golden/ by tests/golden/make_golden.py (oracle only).  Bars: FP64 --
+discrete record fields identical, jump times within 1e-10 dt, J_T and pulses
+within 1e-10; FP32 -- record fields identical, times within 1e-2 dt, states
+within 1e-5, |dJ_T| <= 1e-4; gradients within 1e-4 of max |dJ_T/du| (FP32).
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import krotov as okrotov
+from oracle.mcwf import Ensemble, System, forward_pass
+from parity import compare_records, gpu_records, max_abs, oracle_records, oracle_system, say
+from workloads import config_workload
+from workloads.cascade import Workload
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def tk():
+    from paper_1801_04382_amd import trajkrotov
+    return trajkrotov
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.fail(f"missing {path}: run tests/golden/make_golden.py {name}")
+    return dict(np.load(path))
+
+
+def golden_records(g, iteration=None, direction=None):
+    out = []
+    for row, t in zip(g["rec_int"], g["rec_t"]):
+        it, dr = int(row[0]), int(row[1])
+        if iteration is not None and it != iteration:
+            continue
+        if direction is not None and dr != direction:
+            continue
+        out.append((it, dr, int(row[2]), int(row[3]), int(row[4]), int(row[5]), float(t)))
+    return sorted(out)
+
+
+def to_tk_records(tk, g):
+    arr = np.zeros(len(g["rec_t"]), dtype=tk.JUMP_DTYPE)
+    for q, (row, t) in enumerate(zip(g["rec_int"], g["rec_t"])):
+        it, dr, k, n, j, op = (int(x) for x in row)
+        arr[q] = (0, k, j, op, n, dr, it, 0, t)
+    return arr
+
+
+# ---------------------------------------------------------------------------
+# Krotov pass: full grid exchange and several states per wave
+# ---------------------------------------------------------------------------
+
+def test_krotov_full_grid_exchange_matches_oracle(tk):
+    """d = 81, M = 1024 (the headline launch: 256 blocks x 4 waves, one
+    trajectory each), nt = 200, two iterations."""
+    g = golden("krotov_chain2_fock3_M1024_nt200")
+    w = config_workload("chain2_fock3", M=1024, nt=200)
+    say("krotov full exchange d", w.dim, "M", w.M, "nt", w.nt)
+    with tk.Context(precision="fp64") as ctx:
+        ctx.load(w)
+        J, rec, n = ctx.krotov_iterate(w.M, w.seed, 2)
+        u = ctx.get_pulses()
+        info = ctx.launch_info()
+    say("  launch", info, "J gpu", J.tolist(), "oracle", g["J"].tolist(), "records", n)
+    assert (info["blocks"], info["waves_per_block"], info["traj_per_wave"]) == (256, 4, 1)
+    assert max_abs(J, g["J"]) <= 1e-10
+    assert max_abs(u, g["u"][-1]) <= 1e-10
+    worst = compare_records(gpu_records(rec), golden_records(g), 1e-10 * w.dt)
+    say("  max |dJ|", max_abs(J, g["J"]), "max |du|", max_abs(u, g["u"][-1]), "max |dt*|", worst)
+
+
+def test_krotov_several_states_per_wave_fp64(tk):
+    """d = 36, M = 1100: each wave keeps two trajectories' states in LDS."""
+    g = golden("krotov_chain2_fock2_M1100_nt60")
+    w = config_workload("chain2_fock2", M=1100, nt=60)
+    say("krotov traj_per_wave > 1, fp64 d", w.dim, "M", w.M)
+    with tk.Context(precision="fp64") as ctx:
+        ctx.load(w)
+        J, rec, n = ctx.krotov_iterate(w.M, w.seed, 2)
+        u = ctx.get_pulses()
+        info = ctx.launch_info()
+    say("  launch", info, "J gpu", J.tolist(), "oracle", g["J"].tolist())
+    assert info["traj_per_wave"] >= 2
+    assert max_abs(J, g["J"]) <= 1e-10
+    assert max_abs(u, g["u"][-1]) <= 1e-10
+    compare_records(gpu_records(rec), golden_records(g), 1e-10 * w.dt)
+
+
+def _single_costate(w, k, u, iteration, tau_k, js):
+    """Oracle costate of trajectory k alone (its stream depends only on seed, k)."""
+    sysd = oracle_system(w)
+    dt = w.T / w.nt
+    start = w.psi_tgt / np.linalg.norm(w.psi_tgt)
+    ens = Ensemble(sysd, start[None, :], 1, w.seed, iteration, 1)
+    ens.streams[0] = type(ens.streams[0])(w.seed, k, iteration, 1)
+    ens.r[0] = ens.streams[0].threshold(0)
+    out = {}
+    for j in range(w.nt - 1, -1, -1):
+        ens.advance(j, u[:, j], dt, (j + 1) * dt)
+        if j in js:
+            out[j] = tau_k * ens.normalised()[0]
+    return out
+
+
+def test_fp32_four_rows_per_lane_shape_d216(tk):
+    """C3's FP32 kernel shape (d = 216, four rows per lane, one wave): guess
+    pass, costate pass and two Krotov iterations with M = 1100 (two states per
+    wave in the Krotov pass)."""
+    g = golden("krotov_chain3_fock2_M1100_nt40")
+    w = config_workload("chain3_fock2", M=1100, nt=40, T=2.0)
+    dt = w.T / w.nt
+    say("fp32 d=216 M", w.M, "nt", w.nt)
+    with tk.Context(precision="fp32") as ctx:
+        ctx.load(w)
+        assert ctx.launch_info()["variant"] == "fp32 R=4 WS=6 NC=3"
+        psiT, tau, rec, n = ctx.propagate_forward(w.M, w.seed, 0)
+        worst = compare_records(gpu_records(rec), golden_records(g, 0, 0), 1e-2 * dt)
+        assert max_abs(psiT[g["sample_k"]], g["sample_psi"]) <= 1e-5
+        # tau_k = <tgt|psi_hat_k> with ||tgt|| = 1: |dtau| <= ||dpsi||_2, which the
+        # elementwise state bar bounds by sqrt(d) 1e-5
+        assert max_abs(tau, g["tau0"]) <= 1e-5 * np.sqrt(w.dim)
+        brec, bn = ctx.propagate_backward(w.M, w.seed, 1)
+        compare_records(gpu_records(brec), golden_records(g, 1, 1), 1e-2 * dt)
+        chis = {j: ctx.get_costate(j, w.M) for j in (0, w.nt // 2)}
+        for k in (0, 1099):
+            for j, c in _single_costate(w, k, w.u0, 1, g["tau0"][k], (0, w.nt // 2)).items():
+                assert max_abs(chis[j][k], c) <= 1e-5
+        ctx.load(w)
+        J, krec, _ = ctx.krotov_iterate(w.M, w.seed, 2)
+        u = ctx.get_pulses()
+        info = ctx.launch_info()
+    say("  launch", info, "J gpu", J.tolist(), "oracle", g["J"].tolist(), "fw records", n,
+        "max |dt*|", worst)
+    assert info["traj_per_wave"] >= 2
+    assert max_abs(J, g["J"]) <= 1e-4
+    assert max_abs(u, g["u"][-1]) <= 1e-4
+    compare_records(gpu_records(krec), golden_records(g), 1e-2 * dt)
+
+
+# ---------------------------------------------------------------------------
+# several jumps inside one substep
+# ---------------------------------------------------------------------------
+
+def cavity_workload(M=256, nt=40, T=18.0, seed=21):
+    """A lone cavity truncated at 3 levels starting with two photons, no drive:
+    H_eff = -(i/2) a^+a has norm 1, so a step of 0.45 is a single substep, in
+    which a photon decays at rate 2 and then the second at rate 1 -- many
+    trajectories lose both photons inside one (sub)step."""
+    a = sp.csr_matrix(np.diag([1.0, math.sqrt(2.0)], 1).astype(complex))
+    H0 = sp.csr_matrix((3, 3), dtype=complex)
+    Hc = [sp.csr_matrix((a + a.T).astype(complex))]
+    psi0 = np.array([0, 0, 1], complex)
+    tgt = np.array([1, 0, 1], complex) / math.sqrt(2.0)
+    u0 = np.zeros((1, nt))
+    return Workload("cavity2", H0, Hc, [a], psi0, tgt, T, nt, u0, np.ones((1, nt)),
+                    np.ones(1), M, seed, 1)
+
+
+def _same_step_pairs(recs, direction):
+    seen = {}
+    for r in recs:
+        if r[1] == direction:
+            seen[(r[2], r[4])] = seen.get((r[2], r[4]), 0) + 1
+    return sum(1 for v in seen.values() if v >= 2)
+
+
+def test_two_jumps_in_one_substep_forward_and_backward(tk):
+    w = cavity_workload()
+    dt = w.T / w.nt
+    sysd = oracle_system(w)
+    fw = okrotov.plain_forward(sysd, w.psi0, w.psi_tgt, w.u0, w.T, w.M, w.seed, 0)
+    chi_ref, brec = okrotov.costates(sysd, w.psi_tgt, fw.tau, w.u0, w.T, w.M, w.seed, 1)
+    with tk.Context(precision="fp64") as ctx:
+        ctx.load(w)
+        psiT, tau, rec, n = ctx.propagate_forward(w.M, w.seed, 0)
+        brec_g, bn = ctx.propagate_backward(w.M, w.seed, 1)
+        chi0 = ctx.get_costate(0, w.M)
+    ref_f = oracle_records(fw.records, 0)
+    ref_b = oracle_records(brec, 1)
+    pairs_f, pairs_b = _same_step_pairs(ref_f, 0), _same_step_pairs(ref_b, 1)
+    say("two jumps per step: forward", pairs_f, "backward", pairs_b, "records", n, bn)
+    assert pairs_f >= 5 and pairs_b >= 5
+    worst_f = compare_records(gpu_records(rec), ref_f, 1e-10 * dt)
+    worst_b = compare_records(gpu_records(brec_g), ref_b, 1e-10 * dt)
+    assert max_abs(psiT, fw.psi_hat_T) <= 1e-10
+    assert max_abs(chi0, chi_ref[0]) <= 1e-10
+    say("  max |dt*| forward", worst_f, "backward", worst_b)
+
+
+# ---------------------------------------------------------------------------
+# pathwise gradient on the eight-wave d = 1296 path
+# ---------------------------------------------------------------------------
+
+def test_gradient_d1296_full_nt_against_oracle_adjoint(tk):
+    """One trajectory of the four-node chain over the full nt = 4000 (63
+    checkpoint segments of the eight-wave gradient kernel)."""
+    g = golden("grad_chain4_fock2_nt4000_M1")
+    w = config_workload("chain4_fock2", M=1, nt=4000)
+    with tk.Context(precision="fp32") as ctx:
+        ctx.load(w)
+        assert "G=8" in ctx.launch_info()["variant"]
+        J, tau, grad = ctx.grad_pathwise(w.M, to_tk_records(tk, g))
+    scale = float(np.max(np.abs(g["g"])))
+    say("grad d=1296 nt=4000: records", len(g["rec_t"]), "J", J, float(g["J"]), "max|dg|",
+        max_abs(grad, g["g"]), "scale", scale)
+    assert abs(J - float(g["J"])) <= 1e-5
+    assert max_abs(grad, g["g"]) <= 1e-4 * scale
+
+
+def test_gradient_d1296_segments_against_central_differences(tk):
+    """d = 1296, M = 4, nt = 200 (four segments): the gradient against the
+    oracle's adjoint and its central differences (h = 1e-4) on 16 entries,
+    five at segment boundaries, with the oracle's jump records fixed."""
+    g = golden("grad_chain4_fock2_nt200_M4")
+    w = config_workload("chain4_fock2", M=4, nt=200, T=25.0)
+    with tk.Context(precision="fp32") as ctx:
+        ctx.load(w)
+        J, tau, grad = ctx.grad_pathwise(w.M, to_tk_records(tk, g))
+    scale = float(np.max(np.abs(g["g"])))
+    ent = g["fd_entries"]
+    fd_gpu = grad[ent[:, 0], ent[:, 1]]
+    say("grad d=1296 nt=200: records", len(g["rec_t"]), "max|dg| adjoint",
+        max_abs(grad, g["g"]), "fd", max_abs(fd_gpu, g["fd"]), "scale", scale)
+    assert len(g["rec_t"]) >= 1
+    assert abs(J - float(g["J"])) <= 1e-5
+    assert max_abs(grad, g["g"]) <= 1e-4 * scale
+    assert max_abs(fd_gpu, g["fd"]) <= 1e-4 * scale
