@@ -56,6 +56,79 @@ def measured_traffic(kernel: str, workload: str, prec: str, M: int, nt: int):
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
+# ---------------------------------------------------------------------------
+# algorithmic work (the method's minimum, independent of the implementation)
+# ---------------------------------------------------------------------------
+# Per trajectory-step: K sparse products with H_eff and K accumulations, plus
+# the FP64 norm: 8 K nnz + 8 K d + 4 d real flops, K the smallest order whose
+# Taylor remainder x^(K+1)/(K+1)! is within the step tolerance (1e-14 FP64,
+# 1e-7 FP32) for x = ||H_eff(u_j)||_2 dt; bytes: the costate written once and
+# read once per iteration (d complex elements per trajectory-step pair).
+ALG_TOL = {"fp64": 1e-14, "fp32": 1e-7}
+
+
+def alg_order(x: float, tol: float) -> int:
+    K, term = 0, x  # term = x^(K+1)/(K+1)!
+    while term > tol:
+        K += 1
+        term *= x / (K + 1)
+    return max(K, 1)
+
+
+def _spectral_norm(m) -> float:
+    import numpy as np
+    import scipy.sparse as sp
+    if m.shape[0] <= 256:
+        return float(np.linalg.norm(m.toarray() if sp.issparse(m) else m, 2))
+    a = sp.csr_matrix(m)
+    ah = a.conj().T.tocsr()
+    x = np.ones(a.shape[0], dtype=np.complex128)
+    lam = 0.0
+    for _ in range(300):  # power iteration on A^+ A
+        x /= np.linalg.norm(x)
+        y = ah @ (a @ x)
+        lam = float(np.sqrt(max(np.vdot(x, y).real, 0.0)))
+        x = y
+    return lam
+
+
+_NORMS = {}
+
+
+def operator_norms(w):
+    """Exact 2-norms of H0 - (i/2) sum L^+L and of each H_i, and nnz(H_eff)."""
+    import scipy.sparse as sp
+    key = (w.H0.shape[0], w.H0.nnz, len(w.H_ctrl), len(w.L_jump))
+    if key not in _NORMS:
+        A = sp.csr_matrix(w.H0, dtype=complex)
+        for L in w.L_jump:
+            A = A - 0.5j * (L.conj().T @ L)
+        pattern = abs(A)
+        for h in w.H_ctrl:
+            pattern = pattern + abs(h)
+        _NORMS[key] = (_spectral_norm(A), [_spectral_norm(h) for h in w.H_ctrl],
+                       int(sp.csr_matrix(pattern).nnz))
+    return _NORMS[key]
+
+
+def alg_flops_per_traj_step(w, u, prec: str):
+    """Algorithmic flops of each step j of one trajectory (array [nt])."""
+    import numpy as np
+    a0, ac, nnz = operator_norms(w)
+    dt = w.T / w.nt
+    x = (a0 + np.abs(np.asarray(u)).T @ np.asarray(ac)) * dt
+    K = np.array([alg_order(float(v), ALG_TOL[prec]) for v in x])
+    return 8.0 * K * nnz + 8.0 * K * w.dim + 4.0 * w.dim, K
+
+
+def roofline_entry(flops: float, seconds: float, prec: str, **extra) -> dict:
+    achieved = flops / seconds / 1e12
+    out = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK[prec],
+           "unit": "TFLOP/s", "frac": round(achieved / PEAK[prec], 5)}
+    out.update(extra)
+    return out
+
+
 def cpu_baseline(name: str, M_sub: int, nt: int) -> dict:
     """The FP64 oracle timed on this host for one Krotov iteration (bounded sample)."""
     import numpy as np
@@ -79,9 +152,36 @@ def cpu_baseline(name: str, M_sub: int, nt: int) -> dict:
     return {"value": 2.0 * M_sub * nt / el, "unit": "trajectory-steps/s",
             "cores": blas_threads,
             "kind": "oracle",
+            "krotov_iters_per_s_at_sample": 1.0 / el,
             "sample": f"one Krotov iteration (backward + sequential forward) of {name} with "
                       f"M={M_sub} of the workload's trajectories, full nt={nt}; "
                       f"{el:.1f} s; host cores {cores}, BLAS threads {blas_threads}"}
+
+
+def cpu_baseline_window(name: str, M_sub: int, n_steps: int) -> dict:
+    """The oracle's pass cost on a window of a large workload: M_sub
+    trajectories over the first n_steps steps forward and the last n_steps
+    steps backward (same operators and step length as the full workload)."""
+    from oracle.mcwf import Ensemble, System
+    from workloads import config_workload
+    from threadpoolctl import threadpool_limits
+    limiter = threadpool_limits(limits=1)
+    w = config_workload(name)
+    sysd = System.from_sparse(w.H0, w.H_ctrl, w.L_jump)
+    dt = w.T / w.nt
+    t0 = time.perf_counter()
+    fw = Ensemble(sysd, w.psi0, M_sub, w.seed, 1, 0)
+    for j in range(n_steps):
+        fw.advance(j, w.u0[:, j], dt, j * dt)
+    bw = Ensemble(sysd, w.psi_tgt, M_sub, w.seed, 1, 1)
+    for j in range(w.nt - 1, w.nt - 1 - n_steps, -1):
+        bw.advance(j, w.u0[:, j], dt, (j + 1) * dt)
+    el = time.perf_counter() - t0
+    limiter.restore_original_limits()
+    return {"workload": name, "value": 2.0 * M_sub * n_steps / el,
+            "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{name} (d={w.dim}): {M_sub} trajectories over the first {n_steps} of "
+                      f"{w.nt} steps forward and the last {n_steps} backward; {el:.1f} s"}
 
 
 def bench_batched(n_inst: int, steps: int, nodes, check: int) -> dict:
@@ -103,13 +203,20 @@ def bench_batched(n_inst: int, steps: int, nodes, check: int) -> dict:
         el = time.perf_counter() - t0
         info = b.info()
     J32 = np.concatenate([J0, J], axis=1)
-    dJ = []
+    dJ, dJ_dims = [], []
     for i in [q for q in range(n_inst) if ws[q].dim <= 256][:check]:
+        dJ_dims.append(int(ws[i].dim))
         with tk.Batch(precision="fp64") as b64:
             b64.add(ws[i])
             J64 = b64.krotov_iterate(1 + steps)
         dJ.append(float(np.max(np.abs(J64[0] - J32[i]))))
     ts = info["traj_steps_per_iteration"]
+    # algorithmic flops of one iteration: 2 M nt trajectory-steps per instance
+    # at the instance's own step cost (guess pulses)
+    flops = 0.0
+    for w in ws:
+        f, _ = alg_flops_per_traj_step(w, w.u0, "fp32")
+        flops += 2.0 * w.M * float(f.sum())
     return {"workload": f"batch of {n_inst} instances, chain of {min(nodes)}-{max(nodes)} nodes, "
                         "cavity at 2 levels, M in [64, 2048], nt in [500, 4000]",
             "dims": sorted({int(w.dim) for w in ws}),
@@ -124,7 +231,12 @@ def bench_batched(n_inst: int, steps: int, nodes, check: int) -> dict:
                                              "tuned_pass_ms", "tuned_krotov_ms", "multiwave_instances",
                                              "multiwave_krotov_blocks", "tuned_multiwave_krotov_ms")},
             "max_abs_dJ_fp32_vs_fp64": max(dJ) if dJ else None,
-            "dJ_checked_instances": len(dJ)}
+            "dJ_checked_instances": len(dJ),
+            "dJ_checked_dims": dJ_dims,
+            "roofline": roofline_entry(flops, el / steps, "fp32", scope="whole iteration",
+                                       note="per-instance algorithmic step cost at FP32 "
+                                            "tolerance; packed FP32 is not used, so the "
+                                            "reachable FP32 rate is half this peak")}
 
 
 def bench_grad(workload: str, reps: int) -> dict:
@@ -144,12 +256,15 @@ def bench_grad(workload: str, reps: int) -> dict:
         el = time.perf_counter() - t0
         t = ctx.timing(tk.TK_KERNEL_GRAD)
     avg = t["ms_total"] / t["launches"]
+    f, _ = alg_flops_per_traj_step(w, w.u0, "fp64")
+    # replay, segment recompute, costate sweep and the augmented series (1 +
+    # n_ctrl chains): 4 + n_ctrl pass-equivalents
+    flops = (4.0 + len(w.H_ctrl)) * w.M * float(f.sum())
     return {"workload": workload, "d": w.dim, "M": w.M, "nt": w.nt, "records": int(n),
             "ms_per_gradient": 1e3 * el / reps, "kernel_ms": avg,
             "value": w.M * w.nt * reps / el, "unit": "trajectory-steps/s (replay + reverse sweep)",
-            "roofline": {"bound": "alu", "achieved": t["flops"] / t["launches"] / (avg * 1e-3) / 1e12,
-                         "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                         "frac": t["flops"] / t["launches"] / (avg * 1e-3) / 1e12 / PEAK["fp64"]}}
+            "roofline": roofline_entry(flops, avg * 1e-3, "fp64", kernel="k_grad",
+                                       pass_equivalents=4 + len(w.H_ctrl))}
 
 
 def bench_precision(workload: str) -> dict:
@@ -169,9 +284,12 @@ def bench_precision(workload: str) -> dict:
             J1, _, _ = ctx.krotov_iterate(w.M, w.seed, 1, first_iteration=1, rec_cap=0)
             el = time.perf_counter() - t0
             J[prec] = np.concatenate([J0, J1])
+            f, _ = alg_flops_per_traj_step(w, ctx.get_pulses(), prec)
             out[prec] = {"ms_per_iteration": 1e3 * el,
                          "value": 2.0 * w.M * w.nt / el, "unit": "trajectory-steps/s",
-                         "variant": ctx.launch_info()["variant"]}
+                         "variant": ctx.launch_info()["variant"],
+                         "roofline": roofline_entry(2.0 * w.M * float(f.sum()), el, prec,
+                                                    scope="whole iteration")}
     out["fp32_over_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
     out["max_abs_dJ_fp32_vs_fp64"] = float(np.max(np.abs(J["fp32"] - J["fp64"])))
     return out
@@ -192,9 +310,99 @@ def bench_grad_large(workload: str) -> dict:
         el = time.perf_counter() - t0
         t = ctx.timing(tk.TK_KERNEL_GRAD)
         variant = ctx.launch_info()["variant"]
+    f, _ = alg_flops_per_traj_step(w, w.u0, "fp32")
+    flops = (4.0 + len(w.H_ctrl)) * w.M * float(f.sum())
     return {"workload": workload, "d": w.dim, "M": w.M, "nt": w.nt, "records": int(n),
             "variant": variant, "s_per_gradient": el, "kernel_ms": t["ms_total"],
-            "value": w.M * w.nt / el, "unit": "trajectory-steps/s (replay + reverse sweep)"}
+            "value": w.M * w.nt / el, "unit": "trajectory-steps/s (replay + reverse sweep)",
+            "roofline": roofline_entry(flops, t["ms_total"] * 1e-3, "fp32", kernel="k_grad",
+                                       pass_equivalents=4 + len(w.H_ctrl))}
+
+
+def bench_cross(workload: str, steps: int) -> dict:
+    """Cross-trajectory update (Sec. 2.3) on the plain workload, FP64: guess pass
+    and one iteration untimed, then `steps` iterations timed; the Gram kernel's
+    matrix-core roofline (FP64 MFMA peak)."""
+    from paper_1801_04382_amd import trajkrotov as tk
+    from workloads import config_workload
+    w = config_workload(workload)
+    with tk.Context(precision="fp64") as ctx:
+        ctx.load(w)
+        ctx.krotov_iterate_cross(w.M, w.seed, 1, rec_cap=0)
+        ctx.reset_timing()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        J, _, _ = ctx.krotov_iterate_cross(w.M, w.seed, steps, first_iteration=2, rec_cap=0)
+        el = time.perf_counter() - t0
+        kern = {}
+        for kind, name in [(tk.TK_KERNEL_BACKWARD, "backward"), (tk.TK_KERNEL_CROSS_GRAM, "gram"),
+                           (tk.TK_KERNEL_KROTOV, "krotov_cross")]:
+            t = ctx.timing(kind)
+            if t["launches"]:
+                kern[name] = {"avg_ms": t["ms_total"] / t["launches"], "flops": t["flops"] / t["launches"]}
+    g = kern["gram"]
+    return {"workload": workload, "d": w.dim, "M": w.M, "nt": w.nt, "iterations": steps,
+            "ms_per_iteration": 1e3 * el / steps, "value": 2.0 * w.M * w.nt * steps / el,
+            "unit": "trajectory-steps/s", "krotov_iters_per_s": steps / el,
+            "J_T_last": float(J[-1]),
+            "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
+            "roofline": {"bound": "mfma", "kernel": "k_cross_gram",
+                         "achieved": round(g["flops"] / (g["avg_ms"] * 1e-3) / 1e12, 4),
+                         "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": round(g["flops"] / (g["avg_ms"] * 1e-3) / 1e12 / 78.6, 5),
+                         "note": "FP64 matrix-core peak; d^2 M nt complex products (Hermitian "
+                                 "symmetry not used)"}}
+
+
+def bench_noise_scaling(workload: str, Ms, iterations: int) -> dict:
+    """Pulse-noise measure nu_i (Sec. 3.4) of pulses optimised with M trajectories
+    (independent update, `iterations` iterations, same guess), and the fitted
+    exponent of nu against M (the paper finds about -1/2)."""
+    import numpy as np
+    from paper_1801_04382_amd import trajkrotov as tk
+    from workloads import config_workload
+    nus = []
+    for M in Ms:
+        w = config_workload(workload, M=M)
+        with tk.Context(precision="fp64") as ctx:
+            ctx.load(w)
+            ctx.krotov_iterate(M, w.seed, iterations, rec_cap=0)
+            nus.append(ctx.pulse_noise().tolist())
+    nu = np.array(nus)
+    slopes = [float(np.polyfit(np.log(Ms), np.log(nu[:, i]), 1)[0]) for i in range(nu.shape[1])]
+    return {"workload": workload, "M": list(Ms), "iterations": iterations, "nu": nus,
+            "fitted_exponent_per_control": slopes}
+
+
+def bench_step_methods(cases, M: int, reps: int) -> dict:
+    """One step propagator for M states: the passes' sparse series against the
+    dense operator on the matrix cores (same K), FP64 and FP32."""
+    import numpy as np
+    from paper_1801_04382_amd import trajkrotov as tk
+    from workloads import config_workload
+    out = {}
+    for case in cases:
+        w = config_workload(case, M=M)
+        for prec in ("fp64", "fp32"):
+            f, K = alg_flops_per_traj_step(w, w.u0[:, :1], prec)
+            rng = np.random.default_rng(0)
+            x = rng.standard_normal((M, w.dim)) + 1j * rng.standard_normal((M, w.dim))
+            with tk.Context(precision=prec) as ctx:
+                ctx.load(w)
+                try:
+                    _, ms_s = ctx.step_bench(tk.TK_STEP_SPARSE, x, int(K[0]), reps)
+                except tk.TkError:  # multi-wave shape: no one-wave sparse step to time
+                    continue
+                _, ms_d = ctx.step_bench(tk.TK_STEP_DENSE_MFMA, x, int(K[0]), reps)
+            dp = (w.dim + 15) // 16 * 16
+            out[f"{case}_{prec}"] = {
+                "d": w.dim, "K": int(K[0]), "M": M, "sparse_ms": round(ms_s, 5),
+                "dense_mfma_ms": round(ms_d, 5),
+                "sparse_alg_tflops": round(M * float(f[0]) / (ms_s * 1e-3) / 1e12, 3),
+                "dense_mfma_tflops_executed": round(
+                    M * 8.0 * int(K[0]) * dp * dp / (ms_d * 1e-3) / 1e12, 3),
+                "faster": "sparse" if ms_s <= ms_d else "dense_mfma"}
+    return out
 
 
 def copy_probe(mib: int, reps: int) -> int:
@@ -270,11 +478,20 @@ def main() -> int:
                              "gbs": t["bytes"] / t["launches"] / (avg_ms * 1e-3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     kd = kernels[dom]
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(kd["tflops"], 4),
-                "peak": PEAK[prec], "unit": "TFLOP/s",
-                "frac": round(kd["tflops"] / PEAK[prec], 5),
-                "traffic": measured_traffic(dom, args.workload, prec, w.M, w.nt),
-                "hbm_gbs": round(kd["gbs"], 2)}
+    # algorithmic flops of one launch of the dominant kernel: M trajectories
+    # over nt steps at the step cost of the method (order K from the exact
+    # ||H_eff(u_j)||_2, tolerance 1e-14 / 1e-7), with the final pulses
+    u_fin = ctx.get_pulses()
+    f_alg, K_alg = alg_flops_per_traj_step(w, u_fin, prec)
+    alg_flops = w.M * float(f_alg.sum())
+    impl_flops = kd["tflops"] * 1e12 * kd["avg_ms"] * 1e-3
+    alg_bytes = float(w.M) * w.nt * w.dim * (16 if prec == "fp64" else 8)
+    roofline = roofline_entry(alg_flops, kd["avg_ms"] * 1e-3, prec, kernel=dom,
+                              traffic=measured_traffic(dom, args.workload, prec, w.M, w.nt),
+                              K_algorithmic=[int(K_alg.min()), int(K_alg.max())],
+                              implementation_flops_ratio=round(impl_flops / alg_flops, 4),
+                              hbm_gbs=round(alg_bytes / (kd["avg_ms"] * 1e-3) / 1e9, 2),
+                              hbm_frac=round(alg_bytes / (kd["avg_ms"] * 1e-3) / 8e12, 5))
     info = ctx.launch_info()
     out = {
         "metric": "trajectory-steps/s + Krotov iters/s (FP32 batched vs FP64 plain) at "
@@ -306,11 +523,26 @@ def main() -> int:
             "grad_fp64": bench_grad(args.workload, 3),
             "precision_fp32_vs_fp64": bench_precision("chain3_fock2"),
             "grad_fp32_d1296": bench_grad_large("chain4_fock2"),
+            "cross_trajectory_fp64": bench_cross(args.workload, 2),
+            "pulse_noise_vs_M": bench_noise_scaling("chain2_fock2", [16, 64, 256, 1024], 5),
+            "step_dense_mfma_vs_sparse": bench_step_methods(
+                ["chain2_fock2", "chain2_fock3", "chain3_fock2"], 1024, 20),
         }
-        out["forms"]["fp32_batched_chains_2_3_vs_fp64_plain"] = (
+        # the target figure: the batching workload as configured (chains of 2-4
+        # nodes) against the plain FP64 form; trajectory-steps of different d
+        # are counted alike, so d = 1296 steps (~29x the work of a d = 81 step)
+        # weigh heavily.  The chains-of-2-3 draw is a diagnostic only.
+        out["forms"]["fp32_batched_C4_vs_fp64_plain"] = (
+            out["forms"]["batched_fp32"]["value"] / out["value"])
+        out["forms"]["diagnostic_fp32_batched_chains_2_3_vs_fp64_plain"] = (
             out["forms"]["batched_fp32_chains_2_3"]["value"] / out["value"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, w.nt)
+        if not args.no_forms:
+            out["cpu_baseline"]["other_workloads"] = [
+                dict(cpu_baseline("chain2_fock2", 8, 500), workload="chain2_fock2 (full)"),
+                cpu_baseline_window("chain3_fock2", 2, 150),
+            ]
     print(json.dumps(out), flush=True)
     return 0
 

@@ -25,9 +25,11 @@
  * Conventions (all entry points):
  *   - Every function returns an int status (TK_OK = 0, negative = error) and
  *     never throws across the ABI; tk_last_error() describes the last error.
- *   - All pointer arguments are HOST pointers.  Inputs are copied during the
- *     call (the caller may free them on return); outputs are caller-allocated
- *     and written before the call returns.  Calls are synchronous.
+ *   - All pointer arguments are HOST pointers, except in the *_dev calls,
+ *     whose arrays are device pointers (see there).  Inputs are copied during
+ *     the call (the caller may free them on return); outputs are
+ *     caller-allocated and written before the call returns.  Calls are
+ *     synchronous.
  *   - Complex numbers are interleaved (re, im) doubles: a complex vector of
  *     length n is a double array of length 2n.
  *   - Time steps are 0-based: step j is the interval (j dt, (j+1) dt], dt = T/nt.
@@ -122,10 +124,16 @@ enum tk_kernel_kind {
   TK_KERNEL_BACKWARD = 1,  /* costate pass                                  */
   TK_KERNEL_KROTOV = 2,    /* sequential forward pass with pulse update     */
   TK_KERNEL_GRAD = 3,      /* pathwise gradient (replay + reverse sweep)    */
-  TK_KERNEL_COUNT = 4
+  TK_KERNEL_CROSS_GRAM = 4, /* Gram matrices of the cross-trajectory update */
+  TK_KERNEL_COUNT = 5
 };
 
 typedef struct tk_ctx tk_ctx; /* opaque */
+
+/* A HIP stream (the same type as hipStream_t, named here so that this header
+ * needs no HIP header). */
+struct ihipStream_t;
+typedef struct ihipStream_t *tk_stream_t;
 
 /* ---- lifecycle ---------------------------------------------------------- */
 
@@ -233,6 +241,21 @@ TK_API int tk_krotov_iterate(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t fir
                       int32_t n_iter, double *J_T_out, tk_jump *rec, int64_t cap,
                       int64_t *n_rec);
 
+/* Krotov iterations with the cross-trajectory update (Sec. 2.3, eq.
+ * cross_traj_update), otherwise as tk_krotov_iterate: iteration n runs the
+ * backward trajectories xi_k from xi_k(T) = Psi_tgt (normalised, stream
+ * iteration n, direction 1; no overlap weight), then the sequential forward
+ * pass, which at every step j sets
+ *   u_ij = u_ij + S_ij / (M^2 lambda_i)
+ *          sum_{k,k'} Im[<xi_k|H_i|Psi_hat_k'> <Psi_hat_k'|xi_k>]   (t_j).
+ * The double sum is evaluated as M sum_k' Im <P_j Psi_hat_k'|H_i|Psi_hat_k'>
+ * with P_j = (1/M) sum_k |xi_k(t_j)><xi_k(t_j)|, formed on the matrix cores
+ * after the backward pass (FP64).  One-wave kernel shapes only (d <= 256; in
+ * FP64 d <= 128): TK_EUNSUPPORTED otherwise.  Errors: as tk_krotov_iterate. */
+TK_API int tk_krotov_iterate_cross(tk_ctx *ctx, int32_t M, uint64_t seed,
+                                   uint64_t first_iteration, int32_t n_iter, double *J_T_out,
+                                   tk_jump *rec, int64_t cap, int64_t *n_rec);
+
 /* ---- pathwise gradient ------------------------------------------------------ */
 
 /* Gradient of the trajectory functional with the jump record held fixed.
@@ -259,6 +282,47 @@ TK_API int tk_krotov_iterate(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t fir
  * recorded jump with ||L_l psi|| = 0), TK_EHIP, TK_EUNSUPPORTED. */
 TK_API int tk_grad_pathwise(tk_ctx *ctx, int32_t M, const tk_jump *rec, int64_t n_rec,
                      double *J_T, double *tau_out, double *dJdu);
+
+/* ---- device-pointer variants ---------------------------------------------- */
+
+/* The calls below take DEVICE pointers (memory of the context's device, e.g.
+ * torch tensors) for their array arguments and a HIP stream (NULL: the
+ * device's null stream).  The context's work is ordered after everything already queued on
+ * `stream`, and `stream` is ordered after the context's work when the call
+ * returns, so a producer or consumer of the arrays on that stream needs no
+ * synchronisation of its own; the calls still return when the host-side
+ * checks of the pass (kernel error flags) are done.  Arguments, layouts and
+ * errors are those of the host-pointer call named; device arrays are read
+ * during the call and may be reused once `stream` has passed the call. */
+
+/* tk_set_pulses with device u [n_ctrl * nt], S [n_ctrl * nt] (NULL: 1) and
+ * lambda [n_ctrl] (NULL: 1) (Sec. 2.2, the extended functional).  The
+ * context copies them device to device and also reads them back once, to
+ * plan each step's polynomial order and substeps on the host and to check
+ * them (non-finite u, S outside [0, 1], lambda <= 0 give TK_EINVAL). */
+TK_API int tk_set_pulses_dev(tk_ctx *ctx, int32_t nt, double T, const double *u,
+                             const double *S, const double *lambda, tk_stream_t stream);
+
+/* tk_get_pulses into device memory u_out [n_ctrl * nt]. */
+TK_API int tk_get_pulses_dev(const tk_ctx *ctx, double *u_out, tk_stream_t stream);
+
+/* tk_functional (Sec. 2.3, trajectory functional) with J_T [1] and tau_out
+ * [2M] (may be NULL) in device memory. */
+TK_API int tk_functional_dev(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t iteration,
+                             double *J_T, double *tau_out, tk_stream_t stream);
+
+/* tk_krotov_iterate (Sec. 2.2 sequential update, Sec. 2.3 independent-
+ * trajectory update) with the J_T values in device memory J_T_out (n_iter + 1
+ * values when first_iteration = 0, else n_iter); no jump records. */
+TK_API int tk_krotov_iterate_dev(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t first_iteration,
+                                 int32_t n_iter, double *J_T_out, tk_stream_t stream);
+
+/* tk_grad_pathwise (gradient of the Sec. 2.3 functional along a fixed jump
+ * record) with J_T [1], tau_out [2M] (may be NULL) and dJdu [n_ctrl * nt] in
+ * device memory; the jump records `rec` [n_rec] stay in HOST memory (as
+ * tk_propagate_forward writes them). */
+TK_API int tk_grad_pathwise_dev(tk_ctx *ctx, int32_t M, const tk_jump *rec, int64_t n_rec,
+                                double *J_T, double *tau_out, double *dJdu, tk_stream_t stream);
 
 /* ---- batched form: many optimisation instances at once --------------------- */
 
@@ -332,6 +396,65 @@ TK_API int tk_batch_get_pulses(tk_batch *batch, int32_t index, double *u_out);
 
 /* Launch shapes and timings of the batch. */
 TK_API int tk_batch_get_info(const tk_batch *batch, tk_batch_info *out);
+
+/* ---- density-matrix optimisation (Sec. 2.2) ------------------------------------ */
+
+/* Density-matrix functional of the current pulses (Sec. 2.2, eq. functional):
+ * rho(0) = |psi0><psi0| propagated with the Lindblad master equation of
+ * Sec. 2.1, d rho/dt = -i (H_eff rho - rho H_eff^+) + sum_l L_l rho L_l^+, and
+ * J_T = 1 - <<rho(T)|P_tgt>> = 1 - <tgt|rho(T)|tgt>: the physical error of
+ * the pulses, free of trajectory noise.  FP64 whatever the context's
+ * precision.  Errors: TK_ESTATE, TK_EINVAL, TK_ENUMERIC, TK_EHIP, TK_ENOMEM. */
+TK_API int tk_density_functional(tk_ctx *ctx, double *J_T);
+
+/* Krotov's method on the density matrix (Sec. 2.2): J_T_out[0] is the
+ * functional of the current pulses; each of the n_iter iterations propagates
+ * P backward from P(T) = P_tgt with the adjoint Lindbladian (eqs. bwprop,
+ * krotov_boundary), stores P(t_j), then propagates rho forward with the
+ * sequential update of every interval j (left point t_j, eq. krotovupdate
+ * with dL/du_i = [H_i, rho] as printed):
+ *   u_ij = u_ij + S_ij / lambda_i Im <<P(t_j)| [H_i, rho(t_j)]>>,
+ * and writes J_T_out[n] (n_iter + 1 values).  The context's pulses become the
+ * optimised ones.  Memory: nt d^2 complex128 for P.  Errors: as
+ * tk_density_functional. */
+TK_API int tk_density_krotov_iterate(tk_ctx *ctx, int32_t n_iter, double *J_T_out);
+
+/* ---- pulse noise (Sec. 3.4) -------------------------------------------------- */
+
+/* Noise measure of pulses (Sec. 3.4, eq. noise):
+ *   nu_i = int_0^T |Omega_i(t) - Omega_i^smooth(t)| dt = dt sum_j |u_ij - s_ij|
+ * for piecewise-constant pulses, where s_i is the Savitzky-Golay smoothing
+ * with a five-point cubic convolute (value at a sample = the least-squares
+ * cubic of a five-sample window at that sample; the centred window inside,
+ * the first / last five samples for the first / last two).  u: host
+ * [n_ctrl * nt] row-major, or NULL for the context's current pulses (then
+ * n_ctrl, nt and T are the context's and the arguments are ignored).
+ * nu_out [n_ctrl] (host).  Errors: TK_ESTATE (no pulses), TK_EINVAL (n_ctrl
+ * outside [1, 8], nt < 5, T <= 0, non-finite u). */
+TK_API int tk_pulse_noise(tk_ctx *ctx, int32_t n_ctrl, int32_t nt, double T, const double *u,
+                          double *nu_out);
+
+/* ---- the step on the matrix cores versus the sparse step --------------------- */
+
+enum tk_step_method {
+  TK_STEP_SPARSE = 0,     /* the passes' series on the packed per-lane slots */
+  TK_STEP_DENSE_MFMA = 1  /* dense H_eff times 16-trajectory column tiles on the
+                             matrix cores (FP64 or FP32 MFMA) */
+};
+
+/* One step propagator of the passes, the K-term Taylor polynomial
+ *   y_k = sum_{n=0..K} (-i dt H_eff(u_0))^n / n! x_k,   k < M,
+ * (the matrix-vector products that Sec. 2.3 names the fundamental operation;
+ * u_0 = the current pulses of the first interval, dt = T / nt) with the given
+ * method, `reps` times after one warm-up launch; *ms_per_launch = mean HIP-event
+ * time of a launch.  x [M * 2d] host states (any norm); y [M * 2d] (host, may be
+ * NULL) the result of the last launch.  It exists to measure whether a dense
+ * operator on the matrix cores beats the sparse product; the passes use the
+ * sparse one.  Dense: d <= 256; sparse: one-wave shapes (TK_EUNSUPPORTED
+ * otherwise).  Errors: TK_ESTATE, TK_EINVAL, TK_EUNSUPPORTED, TK_ENOMEM,
+ * TK_EHIP. */
+TK_API int tk_step_bench(tk_ctx *ctx, int32_t method, int32_t M, int32_t K, const double *x,
+                         double *y, int32_t reps, double *ms_per_launch);
 
 /* ---- instrumentation ------------------------------------------------------ */
 

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "_lib")
 LIBNAME = "libtrajkrotov.so"
 
-SOURCES = ["tk_kernels.hip", "tk_grad.hip", "tk_batch.hip", "tk_host.cpp", "tk_batch_host.cpp"]
+SOURCES = ["tk_kernels.hip", "tk_grad.hip", "tk_batch.hip", "tk_cross.hip", "tk_dense.hip",
+           "tk_post.hip", "tk_rho.hip", "tk_host.cpp", "tk_batch_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -500,9 +500,10 @@ int reset_counters(tk_ctx *c) {
   return TK_OK;
 }
 
-int check_kernel_errors(tk_ctx *c) {
+int check_kernel_errors(tk_ctx *c, const int *err_dev = nullptr) {
   int e = 0;
-  TK_HIP(c, hipMemcpyAsync(&e, c->err_dev.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TK_HIP(c, hipMemcpyAsync(&e, err_dev ? err_dev : c->err_dev.p, sizeof(int),
+                           hipMemcpyDeviceToHost, c->stream));
   TK_HIP(c, hipStreamSynchronize(c->stream));
   if (e & tk::kErrSyncTimeout)
     return fail(c, TK_EHIP, "grid-wide step reduction timed out (blocks not co-resident)");
@@ -557,12 +558,32 @@ struct TimedLaunch {
   }
 };
 
-int run_forward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap) {
+// Plain forward pass.  `fixed` (no-allocation entry point) supplies the error
+// bits, record counter and record slot, the overlaps' destination and no final
+// states; otherwise the context's buffers are used.
+struct FixedBuffers {
+  int *err;
+  unsigned long long *rec_count;
+  tk_jump *rec;
+  double *tau;
+};
+
+int run_forward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap,
+                const FixedBuffers *fixed = nullptr) {
   tk::PassArgs a = base_args(c, M, seed, iteration, false);
-  a.psiT = c->psiT.p;
-  a.tau_out = c->tau.as<double>();
-  a.rec = c->rec.as<tk_jump>();
-  a.rec_cap = cap;
+  if (fixed) {
+    a.err = fixed->err;
+    a.rec_count = fixed->rec_count;
+    a.rec = fixed->rec;
+    a.rec_cap = 0;
+    a.tau_out = fixed->tau;
+    a.psiT = nullptr;
+  } else {
+    a.psiT = c->psiT.p;
+    a.tau_out = c->tau.as<double>();
+    a.rec = c->rec.as<tk_jump>();
+    a.rec_cap = cap;
+  }
   const int wpb = pass_waves(c, a.kbuf);
   if (!wpb) return fail(c, TK_EUNSUPPORTED, "the step's Taylor terms do not fit in LDS");
   const int blocks = (M + wpb - 1) / wpb;
@@ -576,18 +597,32 @@ int run_forward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap
   int rc = tl.finish(static_cast<int64_t>(M) * c->nt, pass_flops(c, c->u, M),
                      static_cast<double>(M) * c->d * c->bulk_cplx());
   if (rc) return rc;
-  c->tau_M = M;
-  c->tau_seed = seed;
-  c->tau_iter = static_cast<int64_t>(iteration);
+  if (!fixed) {
+    c->tau_M = M;
+    c->tau_seed = seed;
+    c->tau_iter = static_cast<int64_t>(iteration);
+  }
   return TK_OK;
 }
 
-int run_backward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap) {
+// Costate pass.  unit_weights: every trajectory starts with weight 1 instead of
+// its overlap tau_k (the backward states xi_k of the cross-trajectory update).
+int run_backward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap,
+                 bool unit_weights = false) {
   const size_t chi_bytes = static_cast<size_t>(c->nt) * M * c->d * c->bulk_cplx();
   c->chi_M = -1;
   TK_HIP(c, c->chi.ensure(chi_bytes));
   tk::PassArgs a = base_args(c, M, seed, iteration, true);
   a.tau_in = c->tau.as<double>();
+  if (unit_weights) {
+    if (c->ones_tau.bytes < 2 * static_cast<size_t>(M) * sizeof(double)) {
+      std::vector<double> ones(2 * static_cast<size_t>(M), 0.0);
+      for (int k = 0; k < M; ++k) ones[2 * k] = 1.0;
+      int rc = upload(c, c->ones_tau, ones.data(), ones.size() * sizeof(double));
+      if (rc) return rc;
+    }
+    a.tau_in = c->ones_tau.as<double>();
+  }
   a.chi = c->chi.p;
   a.rec = c->rec.as<tk_jump>();
   a.rec_cap = cap;
@@ -608,22 +643,55 @@ int run_backward(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t ca
   return TK_OK;
 }
 
-int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap) {
+// Gram matrices P_j = (1/M) sum_k |xi_k(t_j)><xi_k(t_j)| of the stored
+// backward states, [nt][d][64 R] (cross-trajectory update).
+int run_gram(tk_ctx *c, int M) {
+  const int Rp = c->var->R * tk::kWave;
+  TK_HIP(c, c->pmat.ensure(static_cast<size_t>(c->nt) * c->d * Rp * 16));
+  const int nrb = (Rp + 31) / 32, ncb = static_cast<int>((c->d + 31) / 32);
+  const int S = nrb * ncb;
+  const int slots = ((c->nt + 7) / 8) * S;  // blocks of step j sit on XCD j % 8
+  const void *chi = c->chi.p;
+  int nt = c->nt, m = M, d = static_cast<int>(c->d), rp = Rp;
+  double invM = 1.0 / M;
+  void *P = c->pmat.p;
+  void *args[] = {&chi, &nt, &m, &d, &rp, const_cast<int *>(&nrb), const_cast<int *>(&ncb), &invM,
+                  &P};
+  TimedLaunch tl(c, TK_KERNEL_CROSS_GRAM);
+  TK_HIP(c, hipLaunchKernel(tk::cross_gram_kernel(c->precision), dim3(8 * slots), dim3(256), args,
+                            0, c->stream));
+  // algorithmic: d^2 complex products per trajectory and step (8 flops each);
+  // the backward states are read once
+  return tl.finish(static_cast<int64_t>(M) * c->nt,
+                   8.0 * static_cast<double>(c->d) * c->d * M * c->nt,
+                   static_cast<double>(c->nt) * M * c->d * c->bulk_cplx());
+}
+
+int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap,
+               bool cross = false) {
   if (c->chi_M != M) return fail(c, TK_ESTATE, "no costates stored for this M");
+  const void *kern = cross ? tk::cross_kernel(c->precision, c->var->R, c->var->WS, c->var->NC,
+                                              c->var->G)
+                           : c->var->k_krotov;
+  if (!kern) return fail(c, TK_EUNSUPPORTED, "no cross-trajectory kernel for this variant");
   // pulses grow during the pass: one spare term vector; the kernel adds
   // substeps if a step would still need more terms
   const int kbuf = plan_kbuf(c, c->u, 1);
+  auto lds_of = [&](int w, int t) {
+    return cross ? tk::cross_lds_bytes(*c->var, w, kbuf, t)
+                 : tk::block_lds_bytes(*c->var, w, kbuf, t);
+  };
   int tw = 0, wpb = 0, blocks = 0;
   size_t lds = 0;
   for (int t = 1; t <= 64 && !tw; ++t)
     for (int w = c->var->G > 1 ? 1 : tk::kWavesPerBlock; w >= 1; w /= 2) {
       const int b = (M + w * t - 1) / (w * t);
-      const size_t l = tk::block_lds_bytes(*c->var, w, kbuf, t);
+      const size_t l = lds_of(w, t);
       if (b > tk::kMaxBlocks || l > tk::kLdsBytes) continue;
-      TK_HIP(c, hipFuncSetAttribute(c->var->k_krotov, hipFuncAttributeMaxDynamicSharedMemorySize,
+      TK_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     static_cast<int>(l)));
       int occ = 0;
-      TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, c->var->k_krotov, tk::kWave * c->var->G * w,
+      TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, tk::kWave * c->var->G * w,
                                                               l));
       if (occ > 0 && static_cast<int64_t>(occ) * c->n_cu >= b) {
         tw = t;
@@ -658,16 +726,17 @@ int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap)
   a.slots = c->slots.as<unsigned long long>();
   a.traj_per_wave = tw;
   a.kbuf = kbuf;
+  a.pmat = cross ? c->pmat.p : nullptr;
   void *args[] = {&a};
   c->last_wpb = wpb;
   c->last_tw = tw;
   c->last_blocks = blocks;
   TimedLaunch tl(c, TK_KERNEL_KROTOV);
   if (c->cooperative) {
-    TK_HIP(c, hipLaunchCooperativeKernel(c->var->k_krotov, dim3(blocks),
-                                         dim3(tk::kWave * c->var->G * wpb), args, lds, c->stream));
+    TK_HIP(c, hipLaunchCooperativeKernel(kern, dim3(blocks), dim3(tk::kWave * c->var->G * wpb),
+                                         args, lds, c->stream));
   } else {  // occupancy was checked above; a stalled grid ends at the spin limit
-    TK_HIP(c, hipLaunchKernel(c->var->k_krotov, dim3(blocks), dim3(tk::kWave * c->var->G * wpb), args, lds,
+    TK_HIP(c, hipLaunchKernel(kern, dim3(blocks), dim3(tk::kWave * c->var->G * wpb), args, lds,
                               c->stream));
   }
   // new pulses become the current ones
@@ -800,16 +869,172 @@ int run_grad(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec) {
   return TK_OK;
 }
 
-int functional_value(tk_ctx *c, int M, double *J) {
-  // J_T = 1 - (1/M) sum_k |tau_k|^2, reduced on the device in a fixed order
+// J_T = 1 - (1/M) sum_k |tau_k|^2 into the context's device scalar, reduced
+// on the device in a fixed order
+int functional_device(tk_ctx *c, int M) {
   TK_HIP(c, c->jt_dev.ensure(sizeof(double)));
   const double *tp = c->tau.as<double>();
   double *jp = c->jt_dev.as<double>();
   int m = M;
   void *args[] = {&tp, &m, &jp};
   TK_HIP(c, hipLaunchKernel(tk::functional_kernel(), dim3(1), dim3(256), args, 0, c->stream));
-  TK_HIP(c, hipMemcpyAsync(J, jp, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return TK_OK;
+}
+
+// J_T to host memory (J) or to device memory (J_dev); one of them is set
+int functional_out(tk_ctx *c, int M, double *J, double *J_dev) {
+  int rc = functional_device(c, M);
+  if (rc) return rc;
+  if (J_dev) {
+    TK_HIP(c, hipMemcpyAsync(J_dev, c->jt_dev.p, sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    return TK_OK;
+  }
+  TK_HIP(c, hipMemcpyAsync(J, c->jt_dev.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   TK_HIP(c, hipStreamSynchronize(c->stream));
+  return TK_OK;
+}
+
+int functional_value(tk_ctx *c, int M, double *J) { return functional_out(c, M, J, nullptr); }
+
+// The context's stream waits for the work queued so far on a caller's stream
+// (join_in), and the caller's stream for the context's work (join_out).  A
+// null handle is the device's null stream; the context's own stream needs
+// nothing.
+int join_in(tk_ctx *c, hipStream_t s) {
+  if (s == c->stream) return TK_OK;
+  TK_HIP(c, hipEventRecord(c->ev_join, s));
+  TK_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  return TK_OK;
+}
+
+int join_out(tk_ctx *c, hipStream_t s) {
+  if (s == c->stream) return TK_OK;
+  TK_HIP(c, hipEventRecord(c->ev_join, c->stream));
+  TK_HIP(c, hipStreamWaitEvent(s, c->ev_join, 0));
+  return TK_OK;
+}
+
+// Validated pulses into the context: host mirror (planning of the step order
+// and substeps, tk_get_pulses) and the padded [kMaxCtrl][nt] device copies.
+// With `dev`, u, S and lambda are device pointers and the device copies are
+// made device to device.
+int store_pulses(tk_ctx *c, int32_t nt, double T, const double *u, const double *S,
+                 const double *lambda, bool dev) {
+  if (!c->has_system) return fail(c, TK_ESTATE, "no system set");
+  if (nt < 1) return fail(c, TK_EINVAL, "nt must be >= 1");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(c, TK_EINVAL, "T must be positive");
+  const size_t n = static_cast<size_t>(c->n_ctrl) * nt;
+  if (n > 0 && !u) return fail(c, TK_EINVAL, "u is NULL");
+  std::vector<double> uu(n), ss(n, 1.0), ll(c->n_ctrl, 1.0);
+  if (dev) {
+    if (n > 0)
+      TK_HIP(c, hipMemcpyAsync(uu.data(), u, n * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream));
+    if (S && n > 0)
+      TK_HIP(c, hipMemcpyAsync(ss.data(), S, n * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream));
+    if (lambda && c->n_ctrl > 0)
+      TK_HIP(c, hipMemcpyAsync(ll.data(), lambda, c->n_ctrl * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+  } else {
+    if (n > 0) uu.assign(u, u + n);
+    if (S) ss.assign(S, S + n);
+    if (lambda) ll.assign(lambda, lambda + c->n_ctrl);
+  }
+  for (double x : uu)
+    if (!std::isfinite(x)) return fail(c, TK_EINVAL, "non-finite pulse value");
+  for (double x : ss)
+    if (!std::isfinite(x) || x < 0.0 || x > 1.0) return fail(c, TK_EINVAL, "S must be in [0, 1]");
+  for (double x : ll)
+    if (!(x > 0.0) || !std::isfinite(x)) return fail(c, TK_EINVAL, "lambda must be positive");
+  c->nt = nt;
+  c->T = T;
+  c->u = uu;
+  c->S = ss;
+  c->lam = ll;
+  // device copies have kMaxCtrl rows: zero pulses and shapes, lambda 1 past n_ctrl
+  const size_t rows = static_cast<size_t>(tk::kMaxCtrl) * nt;
+  std::vector<double> up(rows, 0.0), sp(rows, 0.0), lp(tk::kMaxCtrl, 1.0);
+  std::copy(uu.begin(), uu.end(), up.begin());
+  std::copy(ss.begin(), ss.end(), sp.begin());
+  std::copy(ll.begin(), ll.end(), lp.begin());
+  int rc = upload(c, c->u_dev, up.data(), up.size() * sizeof(double));
+  if (rc) return rc;
+  if ((rc = upload(c, c->S_dev, sp.data(), sp.size() * sizeof(double)))) return rc;
+  if ((rc = upload(c, c->lam_dev, lp.data(), lp.size() * sizeof(double)))) return rc;
+  if (dev && n > 0) {  // the caller's device values themselves, bit for bit
+    TK_HIP(c, hipMemcpyAsync(c->u_dev.p, u, n * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    if (S)
+      TK_HIP(c, hipMemcpyAsync(c->S_dev.p, S, n * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    if (lambda)
+      TK_HIP(c, hipMemcpyAsync(c->lam_dev.p, lambda, c->n_ctrl * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream));
+  }
+  c->has_pulses = true;
+  c->chi_M = c->tau_M = -1;
+  return TK_OK;
+}
+
+// Krotov iterations (tk_krotov_iterate); J_T values go to host memory (J_out)
+// or, with J_on_device, to device memory.
+int krotov_iterate_impl(tk_ctx *c, int32_t M, uint64_t seed, uint64_t first_iteration,
+                        int32_t n_iter, double *J_out, bool J_on_device, tk_jump *rec,
+                        int64_t cap, int64_t *n_rec, bool cross = false) {
+  if (!rec) cap = 0;
+  if (n_iter < 0) return fail(c, TK_EINVAL, "n_iter must be >= 0");
+  if (!J_out) return fail(c, TK_EINVAL, "J_T_out is NULL");
+  const bool cont_ok = c->tau_M == M && c->tau_seed == seed &&
+                       c->tau_iter == static_cast<int64_t>(first_iteration) - 1;
+  int rc = prepare_pass(c, M, cap);
+  if (rc) return rc;
+  if ((rc = reset_counters(c))) return rc;
+  int out = 0;
+  uint64_t n = first_iteration;
+  auto put_J = [&]() {
+    double *dst = J_out + out++;
+    return functional_out(c, M, J_on_device ? nullptr : dst, J_on_device ? dst : nullptr);
+  };
+  if (first_iteration == 0) {
+    if ((rc = run_forward(c, M, seed, 0, cap))) return rc;
+    if ((rc = check_kernel_errors(c))) return rc;
+    if ((rc = put_J())) return rc;
+    n = 1;
+  } else if (!cont_ok) {
+    return fail(c, TK_ESTATE, "no forward pass of the previous iteration with this M and seed");
+  }
+  const uint64_t last = (first_iteration == 0 ? 0 : first_iteration - 1) + n_iter;
+  for (; n <= last; ++n) {
+    if ((rc = run_backward(c, M, seed, n, cap, cross))) return rc;
+    if ((rc = check_kernel_errors(c))) return rc;
+    if (cross && (rc = run_gram(c, M))) return rc;
+    if ((rc = run_krotov(c, M, seed, n, cap, cross))) return rc;
+    if ((rc = put_J())) return rc;
+  }
+  return fetch_records(c, rec, cap, n_rec);
+}
+
+// Pathwise gradient (tk_grad_pathwise); outputs to host or device memory.
+int grad_impl(tk_ctx *c, int32_t M, const tk_jump *rec, int64_t n_rec, double *J_T,
+              double *tau_out, double *dJdu, bool dev) {
+  if (!J_T || !dJdu) return fail(c, TK_EINVAL, "J_T or dJdu is NULL");
+  int rc = prepare_pass(c, M, 0);
+  if (rc) return rc;
+  if ((rc = reset_counters(c))) return rc;
+  if ((rc = run_grad(c, M, rec, n_rec))) return rc;
+  if ((rc = check_kernel_errors(c))) return rc;
+  if ((rc = functional_out(c, M, dev ? nullptr : J_T, dev ? J_T : nullptr))) return rc;
+  const size_t ng = static_cast<size_t>(c->n_ctrl) * c->nt;
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (ng > 0) TK_HIP(c, hipMemcpyAsync(dJdu, c->dJdu.p, ng * sizeof(double), kind, c->stream));
+  if (tau_out)
+    TK_HIP(c, hipMemcpyAsync(tau_out, c->tau.p, 2 * static_cast<size_t>(M) * sizeof(double),
+                             kind, c->stream));
+  if (!dev) TK_HIP(c, hipStreamSynchronize(c->stream));
+  c->tau_M = -1;  // the overlaps now belong to the replay, not to a forward pass
   return TK_OK;
 }
 
@@ -849,7 +1074,8 @@ int tk_create(tk_ctx **out, int device, int precision) {
   c->cooperative = !(launch && std::strcmp(launch, "plain") == 0);
   c->n_cu = prop.multiProcessorCount;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess ||
-      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
     tk_destroy(c);
     return TK_EHIP;
   }
@@ -863,6 +1089,7 @@ void tk_destroy(tk_ctx *ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -944,6 +1171,9 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   c->wl = wl;
   c->wld = wld;
   c->H_ctrl_host = hc;
+  c->A_host = A;
+  c->L_host = lj;
+  c->rho_ready = false;
 
   const int R = best->R;
   const int lanes = tk::kWave * best->G;
@@ -1009,6 +1239,7 @@ int tk_set_states(tk_ctx *c, const double *psi0, const double *psi_tgt) {
   }
   int rc = upload_vec(c, c->psi0_bulk, p);
   if (rc) return rc;
+  if ((rc = upload(c, c->psi0_64, p.data(), p.size() * sizeof(double)))) return rc;
   if ((rc = upload_vec(c, c->tgt_bulk, t))) return rc;
   if ((rc = upload(c, c->tgt64, t.data(), t.size() * sizeof(double)))) return rc;
   c->has_states = true;
@@ -1019,39 +1250,8 @@ int tk_set_states(tk_ctx *c, const double *psi0, const double *psi_tgt) {
 int tk_set_pulses(tk_ctx *c, int32_t nt, double T, const double *u, const double *S,
                   const double *lambda) {
   if (!c) return TK_EINVAL;
-  if (!c->has_system) return fail(c, TK_ESTATE, "no system set");
-  if (nt < 1) return fail(c, TK_EINVAL, "nt must be >= 1");
-  if (!(T > 0.0) || !std::isfinite(T)) return fail(c, TK_EINVAL, "T must be positive");
-  const size_t n = static_cast<size_t>(c->n_ctrl) * nt;
-  if (n > 0 && !u) return fail(c, TK_EINVAL, "u is NULL");
   TK_HIP(c, hipSetDevice(c->device));
-  std::vector<double> uu(u, u + n), ss(n, 1.0), ll(c->n_ctrl, 1.0);
-  if (S) ss.assign(S, S + n);
-  if (lambda) ll.assign(lambda, lambda + c->n_ctrl);
-  for (double x : uu)
-    if (!std::isfinite(x)) return fail(c, TK_EINVAL, "non-finite pulse value");
-  for (double x : ss)
-    if (!std::isfinite(x) || x < 0.0 || x > 1.0) return fail(c, TK_EINVAL, "S must be in [0, 1]");
-  for (double x : ll)
-    if (!(x > 0.0) || !std::isfinite(x)) return fail(c, TK_EINVAL, "lambda must be positive");
-  c->nt = nt;
-  c->T = T;
-  c->u = uu;
-  c->S = ss;
-  c->lam = ll;
-  // device copies have kMaxCtrl rows: zero pulses and shapes, lambda 1 past n_ctrl
-  std::vector<double> up(static_cast<size_t>(tk::kMaxCtrl) * nt, 0.0), sp(up.size(), 0.0),
-      lp(tk::kMaxCtrl, 1.0);
-  std::copy(uu.begin(), uu.end(), up.begin());
-  std::copy(ss.begin(), ss.end(), sp.begin());
-  std::copy(ll.begin(), ll.end(), lp.begin());
-  int rc = upload(c, c->u_dev, up.data(), up.size() * sizeof(double));
-  if (rc) return rc;
-  if ((rc = upload(c, c->S_dev, sp.data(), sp.size() * sizeof(double)))) return rc;
-  if ((rc = upload(c, c->lam_dev, lp.data(), lp.size() * sizeof(double)))) return rc;
-  c->has_pulses = true;
-  c->chi_M = c->tau_M = -1;
-  return TK_OK;
+  return store_pulses(c, nt, T, u, S, lambda, false);
 }
 
 int tk_get_pulses(const tk_ctx *c, double *u_out) {
@@ -1141,20 +1341,7 @@ int tk_grad_pathwise(tk_ctx *c, int32_t M, const tk_jump *rec, int64_t n_rec, do
                      double *tau_out, double *dJdu) {
   if (!c) return TK_EINVAL;
   TK_HIP(c, hipSetDevice(c->device));
-  if (!J_T || !dJdu) return fail(c, TK_EINVAL, "J_T or dJdu is NULL");
-  int rc = prepare_pass(c, M, 0);
-  if (rc) return rc;
-  if ((rc = reset_counters(c))) return rc;
-  if ((rc = run_grad(c, M, rec, n_rec))) return rc;
-  if ((rc = check_kernel_errors(c))) return rc;
-  if ((rc = functional_value(c, M, J_T))) return rc;
-  const size_t ng = static_cast<size_t>(c->n_ctrl) * c->nt;
-  if (ng > 0) TK_HIP(c, hipMemcpy(dJdu, c->dJdu.p, ng * sizeof(double), hipMemcpyDeviceToHost));
-  if (tau_out)
-    TK_HIP(c, hipMemcpy(tau_out, c->tau.p, 2 * static_cast<size_t>(M) * sizeof(double),
-                        hipMemcpyDeviceToHost));
-  c->tau_M = -1;  // the overlaps now belong to the replay, not to a forward pass
-  return TK_OK;
+  return grad_impl(c, M, rec, n_rec, J_T, tau_out, dJdu, false);
 }
 
 int tk_krotov_iterate(tk_ctx *c, int32_t M, uint64_t seed, uint64_t first_iteration,
@@ -1162,32 +1349,380 @@ int tk_krotov_iterate(tk_ctx *c, int32_t M, uint64_t seed, uint64_t first_iterat
                       int64_t *n_rec) {
   if (!c) return TK_EINVAL;
   TK_HIP(c, hipSetDevice(c->device));
-  if (!rec) cap = 0;
-  if (n_iter < 0) return fail(c, TK_EINVAL, "n_iter must be >= 0");
-  if (!J_T_out) return fail(c, TK_EINVAL, "J_T_out is NULL");
-  const bool cont_ok = c->tau_M == M && c->tau_seed == seed &&
-                       c->tau_iter == static_cast<int64_t>(first_iteration) - 1;
-  int rc = prepare_pass(c, M, cap);
+  return krotov_iterate_impl(c, M, seed, first_iteration, n_iter, J_T_out, false, rec, cap,
+                             n_rec);
+}
+
+int tk_krotov_iterate_cross(tk_ctx *c, int32_t M, uint64_t seed, uint64_t first_iteration,
+                            int32_t n_iter, double *J_T_out, tk_jump *rec, int64_t cap,
+                            int64_t *n_rec) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (c->has_system &&
+      !tk::cross_kernel(c->precision, c->var->R, c->var->WS, c->var->NC, c->var->G))
+    return fail(c, TK_EUNSUPPORTED,
+                "the cross-trajectory update runs one-wave kernel shapes only (d <= 256)");
+  return krotov_iterate_impl(c, M, seed, first_iteration, n_iter, J_T_out, false, rec, cap,
+                             n_rec, true);
+}
+
+// ---- device-pointer variants ---------------------------------------------------
+
+int tk_set_pulses_dev(tk_ctx *c, int32_t nt, double T, const double *u, const double *S,
+                      const double *lambda, tk_stream_t stream) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = join_in(c, s);
+  if (!rc) rc = store_pulses(c, nt, T, u, S, lambda, true);
+  const int rc2 = join_out(c, s);
+  return rc ? rc : rc2;
+}
+
+int tk_get_pulses_dev(const tk_ctx *cc, double *u_out, tk_stream_t stream) {
+  if (!cc) return TK_EINVAL;
+  tk_ctx *c = const_cast<tk_ctx *>(cc);
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!c->has_pulses) return fail(c, TK_ESTATE, "no pulses set");
+  if (!u_out) return fail(c, TK_EINVAL, "u_out is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = join_in(c, s);
   if (rc) return rc;
-  if ((rc = reset_counters(c))) return rc;
-  int out = 0;
-  uint64_t n = first_iteration;
-  if (first_iteration == 0) {
-    if ((rc = run_forward(c, M, seed, 0, cap))) return rc;
-    if ((rc = check_kernel_errors(c))) return rc;
-    if ((rc = functional_value(c, M, &J_T_out[out++]))) return rc;
-    n = 1;
-  } else if (!cont_ok) {
-    return fail(c, TK_ESTATE, "no forward pass of the previous iteration with this M and seed");
+  const size_t n = static_cast<size_t>(c->n_ctrl) * c->nt;
+  if (n > 0)
+    TK_HIP(c, hipMemcpyAsync(u_out, c->u_dev.p, n * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+  return join_out(c, s);
+}
+
+int tk_functional_dev(tk_ctx *c, int32_t M, uint64_t seed, uint64_t iteration, double *J_T,
+                      double *tau_out, tk_stream_t stream) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!J_T) return fail(c, TK_EINVAL, "J_T is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = join_in(c, s);
+  if (!rc) rc = prepare_pass(c, M, 0);
+  if (!rc) rc = reset_counters(c);
+  if (!rc) rc = run_forward(c, M, seed, iteration, 0);
+  if (!rc) rc = check_kernel_errors(c);
+  if (!rc) rc = functional_out(c, M, nullptr, J_T);
+  if (!rc && tau_out) {
+    const hipError_t e = hipMemcpyAsync(tau_out, c->tau.p, 2 * static_cast<size_t>(M) * sizeof(double),
+                                        hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) rc = hip_fail(c, e, "hipMemcpyAsync(tau)");
   }
-  const uint64_t last = (first_iteration == 0 ? 0 : first_iteration - 1) + n_iter;
-  for (; n <= last; ++n) {
-    if ((rc = run_backward(c, M, seed, n, cap))) return rc;
-    if ((rc = check_kernel_errors(c))) return rc;
-    if ((rc = run_krotov(c, M, seed, n, cap))) return rc;
-    if ((rc = functional_value(c, M, &J_T_out[out++]))) return rc;
+  const int rc2 = join_out(c, s);
+  return rc ? rc : rc2;
+}
+
+int tk_krotov_iterate_dev(tk_ctx *c, int32_t M, uint64_t seed, uint64_t first_iteration,
+                          int32_t n_iter, double *J_T_out, tk_stream_t stream) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = join_in(c, s);
+  if (!rc)
+    rc = krotov_iterate_impl(c, M, seed, first_iteration, n_iter, J_T_out, true, nullptr, 0,
+                             nullptr);
+  const int rc2 = join_out(c, s);
+  return rc ? rc : rc2;
+}
+
+int tk_grad_pathwise_dev(tk_ctx *c, int32_t M, const tk_jump *rec, int64_t n_rec, double *J_T,
+                         double *tau_out, double *dJdu, tk_stream_t stream) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = join_in(c, s);
+  if (!rc) rc = grad_impl(c, M, rec, n_rec, J_T, tau_out, dJdu, true);
+  const int rc2 = join_out(c, s);
+  return rc ? rc : rc2;
+}
+
+// ---- pulse-noise measure (Sec. 3.4) ------------------------------------------------
+
+int tk_pulse_noise(tk_ctx *c, int32_t n_ctrl, int32_t nt, double T, const double *u,
+                   double *nu_out) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!nu_out) return fail(c, TK_EINVAL, "nu_out is NULL");
+  const double *src = nullptr;
+  if (!u) {  // the context's current pulses
+    if (!c->has_pulses) return fail(c, TK_ESTATE, "no pulses set");
+    n_ctrl = c->n_ctrl;
+    nt = c->nt;
+    T = c->T;
+    src = c->u_dev.as<double>();
   }
-  return fetch_records(c, rec, cap, n_rec);
+  if (n_ctrl < 1 || n_ctrl > tk::kMaxCtrl) return fail(c, TK_EINVAL, "n_ctrl must be in [1, 8]");
+  if (nt < 5) return fail(c, TK_EINVAL, "the five-point filter needs nt >= 5");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(c, TK_EINVAL, "T must be positive");
+  const size_t n = static_cast<size_t>(n_ctrl) * nt;
+  if (u) {
+    for (size_t q = 0; q < n; ++q)
+      if (!std::isfinite(u[q])) return fail(c, TK_EINVAL, "non-finite pulse value");
+    int rc = upload(c, c->noise_u, u, n * sizeof(double));
+    if (rc) return rc;
+    src = c->noise_u.as<double>();
+  }
+  TK_HIP(c, c->noise_nu.ensure(tk::kMaxCtrl * sizeof(double)));
+  TK_HIP(c, tk::launch_pulse_noise(src, n_ctrl, nt, T / nt, c->noise_nu.as<double>(), c->stream));
+  TK_HIP(c, hipMemcpyAsync(nu_out, c->noise_nu.p, n_ctrl * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  TK_HIP(c, hipStreamSynchronize(c->stream));
+  return TK_OK;
+}
+
+// ---- dense matrix-core step against the sparse step ------------------------------
+
+int tk_step_bench(tk_ctx *c, int32_t method, int32_t M, int32_t K, const double *x, double *y,
+                  int32_t reps, double *ms_per_launch) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!c->has_system || !c->has_pulses) return fail(c, TK_ESTATE, "no system or pulses set");
+  if (method != TK_STEP_SPARSE && method != TK_STEP_DENSE_MFMA)
+    return fail(c, TK_EINVAL, "unknown step method");
+  if (M < 1 || K < 1 || K > tk::kMaxTaylor || reps < 1 || !x)
+    return fail(c, TK_EINVAL, "need M >= 1, 1 <= K <= 40, reps >= 1 and x");
+  const int d = static_cast<int>(c->d);
+  const size_t n = static_cast<size_t>(M) * d;
+  for (size_t q = 0; q < 2 * n; ++q)
+    if (!std::isfinite(x[q])) return fail(c, TK_EINVAL, "non-finite state");
+  const bool fp64 = c->precision == TK_FP64;
+  const size_t cb = c->bulk_cplx();
+  {
+    std::vector<double> xd(x, x + 2 * n);
+    int rc;
+    if (fp64) {
+      rc = upload(c, c->bench_x, xd.data(), 2 * n * sizeof(double));
+    } else {
+      std::vector<float> xf(xd.begin(), xd.end());
+      rc = upload(c, c->bench_x, xf.data(), 2 * n * sizeof(float));
+    }
+    if (rc) return rc;
+  }
+  TK_HIP(c, c->bench_y.ensure(n * cb));
+  const void *kern = nullptr;
+  dim3 grid, block;
+  size_t lds = 0;
+  std::vector<void *> args;
+  tk::PassArgs a;
+  int Kk = K, Dp = (d + 15) / 16 * 16, m = M, dd = d;
+  double tau = c->T / c->nt;
+  const void *xp = c->bench_x.p;
+  void *yp = c->bench_y.p;
+  const void *hp = nullptr;
+  if (method == TK_STEP_SPARSE) {
+    kern = tk::sparse_step_kernel(c->precision, c->var->R, c->var->WS, c->var->NC, c->var->G);
+    if (!kern) return fail(c, TK_EUNSUPPORTED, "the sparse step runs one-wave kernel shapes only");
+    a = base_args(c, M, 0, 0, false);
+    a.kbuf = 2;
+    lds = tk::block_lds_bytes(*c->var, tk::kWavesPerBlock, 2, 0);
+    grid = dim3((M + tk::kWavesPerBlock - 1) / tk::kWavesPerBlock);
+    block = dim3(tk::kWave * tk::kWavesPerBlock);
+    args = {&a, &Kk, &xp, &yp};
+  } else {
+    if (Dp > 256) return fail(c, TK_EUNSUPPORTED, "the dense step takes d <= 256");
+    // dense H_eff(u_0) = H0 - (i/2) sum L^+L + sum_i u_i0 H_i, padded to Dp
+    std::vector<cd> Hd(static_cast<size_t>(Dp) * Dp, cd(0.0, 0.0));
+    for (int64_t r = 0; r < c->A_host.n; ++r)
+      for (int64_t p = c->A_host.ptr[r]; p < c->A_host.ptr[r + 1]; ++p)
+        Hd[static_cast<size_t>(r) * Dp + c->A_host.idx[p]] += c->A_host.val[p];
+    for (int i = 0; i < c->n_ctrl; ++i) {
+      const tkh::Csr &h = c->H_ctrl_host[i];
+      const double ui = c->u[static_cast<size_t>(i) * c->nt];
+      for (int64_t r = 0; r < h.n; ++r)
+        for (int64_t p = h.ptr[r]; p < h.ptr[r + 1]; ++p)
+          Hd[static_cast<size_t>(r) * Dp + h.idx[p]] += ui * h.val[p];
+    }
+    int rc;
+    if (fp64) {
+      rc = upload(c, c->bench_h, Hd.data(), Hd.size() * sizeof(cd));
+    } else {
+      std::vector<float> hf(2 * Hd.size());
+      for (size_t q = 0; q < Hd.size(); ++q) {
+        hf[2 * q] = static_cast<float>(Hd[q].real());
+        hf[2 * q + 1] = static_cast<float>(Hd[q].imag());
+      }
+      rc = upload(c, c->bench_h, hf.data(), hf.size() * sizeof(float));
+    }
+    if (rc) return rc;
+    hp = c->bench_h.p;
+    const int NT = fp64 ? (Dp <= 128 ? 2 : 1) : (Dp <= 128 ? 4 : 2);
+    kern = tk::dense_step_kernel(c->precision, NT);
+    lds = static_cast<size_t>(4) * Dp * 16 * NT * (fp64 ? 8 : 4);
+    grid = dim3((M + 16 * NT - 1) / (16 * NT));
+    block = dim3(256);
+    args = {&hp, &dd, &Dp, &m, &Kk, &tau, &xp, &yp};
+  }
+  TK_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(lds)));
+  TK_HIP(c, hipLaunchKernel(kern, grid, block, args.data(), lds, c->stream));  // warm-up
+  TK_HIP(c, hipEventRecord(c->ev0, c->stream));
+  for (int r = 0; r < reps; ++r)
+    TK_HIP(c, hipLaunchKernel(kern, grid, block, args.data(), lds, c->stream));
+  TK_HIP(c, hipEventRecord(c->ev1, c->stream));
+  TK_HIP(c, hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  TK_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (ms_per_launch) *ms_per_launch = ms / reps;
+  if (y) {
+    std::vector<unsigned char> buf(n * cb);
+    TK_HIP(c, hipMemcpy(buf.data(), c->bench_y.p, n * cb, hipMemcpyDeviceToHost));
+    to_host_cplx(c, buf.data(), n, y);
+  }
+  return TK_OK;
+}
+
+// ---- density-matrix passes (Sec. 2.2) ---------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+// CSR copy of a host operator on the device (int row pointers, complex128 values)
+int upload_csr(tk_ctx *c, const Csr &m, DevBuf *b) {
+  std::vector<int> p(m.ptr.begin(), m.ptr.end());
+  std::vector<int> ix(m.idx.begin(), m.idx.end());
+  if (ix.empty()) ix.push_back(0);
+  std::vector<cd> v(m.val.begin(), m.val.end());
+  if (v.empty()) v.push_back(cd(0.0, 0.0));
+  int rc = upload(c, b[0], p.data(), p.size() * sizeof(int));
+  if (!rc) rc = upload(c, b[1], ix.data(), ix.size() * sizeof(int));
+  if (!rc) rc = upload(c, b[2], v.data(), v.size() * sizeof(cd));
+  return rc;
+}
+
+tk::RhoCsr csr_view(const DevBuf *b) {
+  tk::RhoCsr r;
+  r.ptr = b[0].as<int>();
+  r.idx = b[1].as<int>();
+  r.val = b[2].p;
+  return r;
+}
+
+// Arguments of a density-matrix pass; the operators are uploaded once per
+// system: three buffers each for A, A^+, H_0 .. H_7, L_0 .. L_7, L_0^+ .. L_7^+.
+int rho_args(tk_ctx *c, bool backward, tk::RhoArgs &a) {
+  if (!c->has_system || !c->has_states || !c->has_pulses)
+    return fail(c, TK_ESTATE, "system, states and pulses must be set");
+  std::memset(&a, 0, sizeof(a));
+  const int d = static_cast<int>(c->d);
+  auto slot = [&](int q) { return &c->rho_csr[3 * q]; };
+  constexpr int kH = 2, kL = 2 + tk::kMaxCtrl, kLd = 2 + tk::kMaxCtrl + tk::kMaxJump;
+  if (!c->rho_ready) {
+    int rc = upload_csr(c, c->A_host, slot(0));
+    if (!rc) rc = upload_csr(c, adjoint(c->A_host), slot(1));
+    for (int i = 0; i < c->n_ctrl && !rc; ++i) rc = upload_csr(c, c->H_ctrl_host[i], slot(kH + i));
+    for (int l = 0; l < c->n_jump && !rc; ++l) {
+      rc = upload_csr(c, c->L_host[l], slot(kL + l));
+      if (!rc) rc = upload_csr(c, adjoint(c->L_host[l]), slot(kLd + l));
+    }
+    if (rc) return rc;
+    c->rho_bj = 0.0;
+    for (int l = 0; l < c->n_jump; ++l) {
+      const double nl = norm2_estimate(c->L_host[l]);
+      c->rho_bj += nl * nl;
+    }
+    c->rho_ready = true;
+  }
+  const size_t n2 = static_cast<size_t>(d) * d;
+  const int ny = std::max(c->n_jump, 1);
+  TK_HIP(c, c->rho_work.ensure((4 + ny) * n2 * sizeof(cd)));
+  cd *w = c->rho_work.as<cd>();
+  a.d = d;
+  a.nt = c->nt;
+  a.n_ctrl = c->n_ctrl;
+  a.n_jump = c->n_jump;
+  a.dt = c->T / c->nt;
+  a.B = csr_view(slot(backward ? 1 : 0));
+  for (int i = 0; i < c->n_ctrl; ++i) a.H[i] = csr_view(slot(kH + i));
+  for (int l = 0; l < c->n_jump; ++l) a.J[l] = csr_view(slot((backward ? kLd : kL) + l));
+  a.s = backward ? 1.0 : -1.0;
+  a.gen_b0 = 2.0 * c->b0;
+  for (int i = 0; i < tk::kMaxCtrl; ++i) a.gen_bc[i] = 2.0 * c->bc[i];
+  a.gen_bj = c->rho_bj;
+  std::memcpy(a.ord_x, order_table(TK_FP64), sizeof(a.ord_x));
+  a.kmax = tk::kMaxTaylor;
+  a.u = c->u_dev.as<double>();
+  a.Q0 = w;
+  a.Q1 = w + n2;
+  a.R = w + 2 * n2;
+  a.X = w + 3 * n2;
+  a.Y = w + 4 * n2;
+  a.tgt = c->tgt64.p;
+  a.start = backward ? c->tgt64.p : c->psi0_64.p;
+  a.err = c->err_dev.as<int>();
+  return TK_OK;
+}
+
+int rho_run(tk_ctx *c, const tk::RhoArgs &a, int dir) {
+  TK_HIP(c, tk::launch_rho_pass(a, dir, c->stream));
+  return check_kernel_errors(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tk_density_functional(tk_ctx *c, double *J_T) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!J_T) return fail(c, TK_EINVAL, "J_T is NULL");
+  TK_HIP(c, c->err_dev.ensure(sizeof(int)));
+  TK_HIP(c, c->jt_dev.ensure(sizeof(double)));
+  TK_HIP(c, hipMemsetAsync(c->err_dev.p, 0, sizeof(int), c->stream));
+  tk::RhoArgs a;
+  int rc = rho_args(c, false, a);
+  if (rc) return rc;
+  a.J_out = c->jt_dev.as<double>();
+  if ((rc = rho_run(c, a, 0))) return rc;
+  TK_HIP(c, hipMemcpy(J_T, c->jt_dev.p, sizeof(double), hipMemcpyDeviceToHost));
+  return TK_OK;
+}
+
+int tk_density_krotov_iterate(tk_ctx *c, int32_t n_iter, double *J_T_out) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!J_T_out) return fail(c, TK_EINVAL, "J_T_out is NULL");
+  if (n_iter < 0) return fail(c, TK_EINVAL, "n_iter must be >= 0");
+  TK_HIP(c, c->err_dev.ensure(sizeof(int)));
+  TK_HIP(c, c->jt_dev.ensure(sizeof(double)));
+  TK_HIP(c, hipMemsetAsync(c->err_dev.p, 0, sizeof(int), c->stream));
+  int rc = tk_density_functional(c, &J_T_out[0]);
+  if (rc) return rc;
+  const size_t n2 = static_cast<size_t>(c->d) * c->d;
+  TK_HIP(c, c->rho_P.ensure(static_cast<size_t>(c->nt) * n2 * sizeof(cd)));
+  TK_HIP(c, c->u_new_dev.ensure(static_cast<size_t>(tk::kMaxCtrl) * c->nt * sizeof(double)));
+  for (int n = 1; n <= n_iter; ++n) {
+    tk::RhoArgs b;
+    if ((rc = rho_args(c, true, b))) return rc;
+    b.store = c->rho_P.p;
+    if ((rc = rho_run(c, b, 1))) return rc;
+    tk::RhoArgs f;
+    if ((rc = rho_args(c, false, f))) return rc;
+    f.P = c->rho_P.p;
+    f.u_old = c->u_dev.as<double>();
+    f.S = c->S_dev.as<double>();
+    f.lam = c->lam_dev.as<double>();
+    f.u_new = c->u_new_dev.as<double>();
+    f.J_out = c->jt_dev.as<double>();
+    TK_HIP(c, hipMemcpyAsync(c->u_new_dev.p, c->u_dev.p,
+                             static_cast<size_t>(tk::kMaxCtrl) * c->nt * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = rho_run(c, f, 0))) return rc;
+    TK_HIP(c, hipMemcpy(&J_T_out[n], c->jt_dev.p, sizeof(double), hipMemcpyDeviceToHost));
+    // the updated pulses become the current ones (device and host mirror)
+    TK_HIP(c, hipMemcpyAsync(c->u_dev.p, c->u_new_dev.p,
+                             static_cast<size_t>(tk::kMaxCtrl) * c->nt * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    if (!c->u.empty())
+      TK_HIP(c, hipMemcpy(c->u.data(), c->u_new_dev.p, c->u.size() * sizeof(double),
+                          hipMemcpyDeviceToHost));
+    c->chi_M = c->tau_M = -1;
+  }
+  return TK_OK;
 }
 
 int tk_set_timing(tk_ctx *c, int enable) {

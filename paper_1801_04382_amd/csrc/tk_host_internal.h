@@ -78,6 +78,8 @@ struct tk_ctx {
   double bc[tk::kMaxCtrl] = {};
   int64_t nnz_heff = 0;
   std::vector<tkh::Csr> H_ctrl_host;
+  tkh::Csr A_host;  // H0 - (i/2) sum_l L_l^+ L_l
+  std::vector<tkh::Csr> L_host;  // jump operators
 
   tkh::DevBuf f_scol, f_sval, f_ccol, f_cval, b_scol, b_sval, b_ccol, b_cval, lcol, lval;
   tkh::DevBuf ldcol, ldval;  // L_l^+ (pathwise gradient)
@@ -91,6 +93,15 @@ struct tk_ctx {
 
   tkh::DevBuf chi, tau, psiT, slots, rec, rec_count, err_dev, jt_dev;
   tkh::DevBuf path_off, path_step, path_t, path_op, ckpt, stash, gk, dJdu;
+  tkh::DevBuf noise_u, noise_nu;  // pulse-noise measure
+  tkh::DevBuf pmat, ones_tau;      // cross-trajectory update: Gram matrices, unit weights
+  tkh::DevBuf bench_x, bench_y, bench_h;  // step comparison (tk_step_bench)
+  // density-matrix passes: CSR copies (complex128) of A, A^+, H_i, L_l, L_l^+,
+  // work matrices, the stored P(t_j) and psi0 in FP64
+  bool rho_ready = false;
+  tkh::DevBuf rho_csr[3 * (2 + tk::kMaxCtrl + 2 * tk::kMaxJump)];
+  tkh::DevBuf rho_work, rho_P, psi0_64;
+  double rho_bj = 0.0;
   int chi_M = -1;
   int tau_M = -1;
   uint64_t tau_seed = 0;
@@ -98,6 +109,7 @@ struct tk_ctx {
 
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev_join = nullptr;  // orders the context's stream with a caller's stream
   tk_kernel_timing tstat[TK_KERNEL_COUNT] = {};
   int last_wpb = 0, last_tw = 0, last_blocks = 0;
   bool cooperative = true;  // launch the Krotov pass with hipLaunchCooperativeKernel

@@ -103,6 +103,8 @@ struct PassArgs {
   const double *lam;        // [kMaxCtrl] lambda_i
   unsigned long long *slots;  // [nt][kMaxBlocks][NC] per-block partial sums
   int traj_per_wave;        // trajectories owned by one wave
+  const void *pmat;         // cross-trajectory update: P_j = (1/M) sum_k |xi_k><xi_k|,
+                            // complex128 [nt][d][64 R] (column c, padded rows)
   long long spin_limit;     // polls before a step reduction gives up
   // pathwise gradient with the jump record fixed
   const int *a_scol;        // adjoint operator H_eff^+: static slots
@@ -176,6 +178,56 @@ const Variant *variants(int *count);
 
 // Kernel reducing J_T = 1 - (1/M) sum |tau_k|^2 (one block of 256 threads).
 const void *functional_kernel();
+
+// Cross-trajectory update (tk_cross.hip): the sequential pass of a one-wave
+// variant (null for multi-wave ones), the kernel forming the Gram matrices
+// P_j of the backward states, and the LDS bytes of a block of the pass.
+const void *cross_kernel(int precision, int R, int WS, int NC, int G);
+const void *cross_gram_kernel(int precision);
+size_t cross_lds_bytes(const Variant &v, int teams, int kbuf, int traj_per_wave);
+
+// One Taylor step of M states, dense on the matrix cores (NT = 1, 2 or 4
+// tiles of 16 trajectories a block) or with the passes' sparse series
+// (one-wave variants) -- tk_dense.hip.
+const void *dense_step_kernel(int precision, int NT);
+const void *sparse_step_kernel(int precision, int R, int WS, int NC, int G);
+
+// Density-matrix passes (tk_rho.hip): one workgroup propagates a d x d
+// matrix with the Liouvillian (forward) or its adjoint (backward).
+struct RhoCsr {       // device CSR, complex128 values
+  const int *ptr;     // [d + 1]
+  const int *idx;
+  const void *val;
+};
+struct RhoArgs {
+  int d, nt, n_ctrl, n_jump;
+  double dt;
+  RhoCsr B;                 // A = H0 - (i/2) sum L^+L (forward) or A^+ (backward)
+  RhoCsr H[kMaxCtrl];       // control Hamiltonians
+  RhoCsr J[kMaxJump];       // L_l (forward) or L_l^+ (backward)
+  double s;                 // -1 forward, +1 backward
+  double gen_b0;            // 2 ||A||
+  double gen_bc[kMaxCtrl];  // 2 ||H_i||
+  double gen_bj;            // sum_l ||L_l||^2
+  double ord_x[kMaxTaylor + 1];
+  int kmax;
+  const double *u;          // [kMaxCtrl][nt] pulses of a plain pass
+  void *Q0, *Q1, *R, *X, *Y;  // complex128 work matrices d^2 each (Y: n_jump of them)
+  void *store;              // backward: P(t_j), [nt][d][d]; may be null
+  const void *P;            // forward with the update: P(t_j) [nt][d][d]; null: plain pass
+  const double *u_old, *S, *lam;
+  double *u_new;            // [kMaxCtrl][nt]
+  const void *tgt;          // [d] complex128, normalised
+  const void *start;        // [d]: the pass starts from |start><start|
+  double *J_out;            // forward: 1 - <tgt|rho(T)|tgt>
+  int *err;
+};
+hipError_t launch_rho_pass(const RhoArgs &a, int dir, hipStream_t stream);
+
+// Noise measure of the pulses u_dev [n_ctrl][nt] (Sec. 3.4) into nu_dev
+// [n_ctrl]: one block per control (tk_post.hip).
+hipError_t launch_pulse_noise(const double *u_dev, int n_ctrl, int nt, double dt, double *nu_dev,
+                              hipStream_t stream);
 
 // Gradient kernel of a variant (defined in tk_grad.hip), and the kernel that
 // reduces the per-trajectory terms: one 64-thread block per pulse value.

@@ -79,39 +79,6 @@ __global__ void k_fill_slots(unsigned long long *slots, long long n, int nblk, i
   }
 }
 
-// One batch of agent-scope loads of the slots of blocks lane + 64 q.
-template <int NCX>
-__device__ __forceinline__ void poll_slots(const unsigned long long *row, int lane,
-                                           unsigned long long (&bits)[kPollPerLane][NCX]) {
-#pragma unroll
-  for (int q = 0; q < kPollPerLane; ++q)
-#pragma unroll
-    for (int c = 0; c < NCX; ++c)
-      bits[q][c] = __hip_atomic_load(&row[(lane + kWave * q) * NCX + c], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// True when every slot of a batch holds a partial; then acc = their sum per
-// lane (in the batch's fixed order).
-template <int NCX>
-__device__ __forceinline__ bool slots_complete(const unsigned long long (&bits)[kPollPerLane][NCX],
-                                               double (&acc)[NCX]) {
-  int missing = 0;
-#pragma unroll
-  for (int q = 0; q < kPollPerLane; ++q)
-#pragma unroll
-    for (int c = 0; c < NCX; ++c) missing |= bits[q][c] == kSlotEmpty;
-  if (__any(missing)) return false;
-#pragma unroll
-  for (int c = 0; c < NCX; ++c) {
-    acc[c] = 0.0;
-#pragma unroll
-    for (int q = 0; q < kPollPerLane; ++q)
-      acc[c] += __longlong_as_double(static_cast<long long>(bits[q][c]));
-  }
-  return true;
-}
-
 // ---- sequential Krotov forward pass (cooperative launch) ---------------------
 template <typename real, int R, int WS, int NC, int G>
 __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_krotov(

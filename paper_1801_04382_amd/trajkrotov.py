@@ -39,6 +39,10 @@ TK_KERNEL_FORWARD = 0
 TK_KERNEL_BACKWARD = 1
 TK_KERNEL_KROTOV = 2
 TK_KERNEL_GRAD = 3
+TK_KERNEL_CROSS_GRAM = 4
+
+TK_STEP_SPARSE = 0
+TK_STEP_DENSE_MFMA = 1
 
 STATUS_NAMES = {
     0: "TK_OK", -1: "TK_EINVAL", -2: "TK_EDIM", -3: "TK_ENOMEM", -4: "TK_EHIP",
@@ -112,8 +116,28 @@ _SIGNATURES = {
     "tk_krotov_iterate": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64,
                                          ctypes.c_uint64, ctypes.c_int32, _dp, _P(tk_jump),
                                          ctypes.c_int64, _P(ctypes.c_int64)]),
+    "tk_krotov_iterate_cross": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64,
+                                               ctypes.c_uint64, ctypes.c_int32, _dp, _P(tk_jump),
+                                               ctypes.c_int64, _P(ctypes.c_int64)]),
     "tk_grad_pathwise": (ctypes.c_int, [_ctx_p, ctypes.c_int32, _P(tk_jump), ctypes.c_int64,
                                         _dp, _dp, _dp]),
+    "tk_set_pulses_dev": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tk_get_pulses_dev": (ctypes.c_int, [_ctx_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tk_functional_dev": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tk_krotov_iterate_dev": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64,
+                                             ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "tk_grad_pathwise_dev": (ctypes.c_int, [_ctx_p, ctypes.c_int32, _P(tk_jump), ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
+    "tk_pulse_noise": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                      _dp, _dp]),
+    "tk_step_bench": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     _dp, _dp, ctypes.c_int32, _dp]),
+    "tk_density_functional": (ctypes.c_int, [_ctx_p, _dp]),
+    "tk_density_krotov_iterate": (ctypes.c_int, [_ctx_p, ctypes.c_int32, _dp]),
     "tk_batch_create": (ctypes.c_int, [_P(_ctx_p), ctypes.c_int, ctypes.c_int]),
     "tk_batch_destroy": (None, [_ctx_p]),
     "tk_batch_last_error": (ctypes.c_char_p, [_ctx_p]),
@@ -146,6 +170,14 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libtrajkrotov not built ({path}); run "
                           "`python -m paper_1801_04382_amd.build`")
+    # One HIP runtime per process: PyTorch ships its own copy of the runtime
+    # (same soname, libamdhip64.so.7).  Loaded first, it is the one this
+    # library binds to, so torch tensors and the library share a runtime; a
+    # second copy loaded after this library would find the device taken.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         fn = getattr(lib, name)
@@ -322,6 +354,18 @@ def tk_krotov_iterate(ctx: int, M: int, seed: int, n_iter: int, first_iteration:
     return J[:nout], records_array(buf, min(n.value, rec_cap)), n.value
 
 
+def tk_krotov_iterate_cross(ctx: int, M: int, seed: int, n_iter: int, first_iteration: int = 0,
+                            rec_cap: int = 0):
+    nout = n_iter + 1 if first_iteration == 0 else n_iter
+    J = np.zeros(max(nout, 1))
+    buf, bp = _rec_buffer(rec_cap)
+    n = ctypes.c_int64(0)
+    _check(ctx, _lib.tk_krotov_iterate_cross(ctx, M, seed, first_iteration, n_iter, _dptr(J),
+                                             bp if rec_cap > 0 else None, rec_cap,
+                                             ctypes.byref(n)))
+    return J[:nout], records_array(buf, min(n.value, rec_cap)), n.value
+
+
 def tk_grad_pathwise(ctx: int, M: int, records: np.ndarray, n_ctrl: int, nt: int):
     """J_T, overlaps and dJ_T/du [n_ctrl, nt] of the replay with the records fixed."""
     rec = np.ascontiguousarray(records, dtype=JUMP_DTYPE)
@@ -332,6 +376,75 @@ def tk_grad_pathwise(ctx: int, M: int, records: np.ndarray, n_ctrl: int, nt: int
                                       rec.size, ctypes.byref(J), _dptr(tau.view(np.float64)),
                                       _dptr(g)))
     return J.value, tau, g[:n_ctrl * nt].reshape(n_ctrl, nt)
+
+
+# device-pointer variants: array arguments are device addresses (ints, e.g.
+# torch's tensor.data_ptr()), `stream` a HIP stream handle (int, 0 = the
+# context's own stream)
+
+def tk_set_pulses_dev(ctx: int, nt: int, T: float, u_ptr: int, S_ptr: int = 0,
+                      lam_ptr: int = 0, stream: int = 0) -> None:
+    _check(ctx, _lib.tk_set_pulses_dev(ctx, nt, float(T), u_ptr or None, S_ptr or None,
+                                       lam_ptr or None, stream or None))
+
+
+def tk_get_pulses_dev(ctx: int, u_ptr: int, stream: int = 0) -> None:
+    _check(ctx, _lib.tk_get_pulses_dev(ctx, u_ptr, stream or None))
+
+
+def tk_functional_dev(ctx: int, M: int, seed: int, iteration: int, J_ptr: int, tau_ptr: int = 0,
+                      stream: int = 0) -> None:
+    _check(ctx, _lib.tk_functional_dev(ctx, M, seed, iteration, J_ptr, tau_ptr or None,
+                                       stream or None))
+
+
+def tk_krotov_iterate_dev(ctx: int, M: int, seed: int, first_iteration: int, n_iter: int,
+                          J_ptr: int, stream: int = 0) -> None:
+    _check(ctx, _lib.tk_krotov_iterate_dev(ctx, M, seed, first_iteration, n_iter, J_ptr,
+                                           stream or None))
+
+
+def tk_grad_pathwise_dev(ctx: int, M: int, records: np.ndarray, J_ptr: int, tau_ptr: int,
+                         g_ptr: int, stream: int = 0) -> None:
+    rec = np.ascontiguousarray(records, dtype=JUMP_DTYPE)
+    _check(ctx, _lib.tk_grad_pathwise_dev(ctx, M, rec.ctypes.data_as(_P(tk_jump)) if rec.size
+                                          else None, rec.size, J_ptr, tau_ptr or None, g_ptr,
+                                          stream or None))
+
+
+def tk_pulse_noise(ctx: int, u: Optional[np.ndarray] = None, T: float = 0.0) -> np.ndarray:
+    """nu_i of pulses u [n_ctrl, nt] on [0, T] (None: the context's current pulses)."""
+    if u is None:
+        nu = np.zeros(8)
+        _check(ctx, _lib.tk_pulse_noise(ctx, 0, 0, 0.0, None, _dptr(nu)))
+        return nu
+    u = np.ascontiguousarray(np.atleast_2d(u), dtype=np.float64)
+    nu = np.zeros(u.shape[0])
+    _check(ctx, _lib.tk_pulse_noise(ctx, u.shape[0], u.shape[1], float(T), _dptr(u), _dptr(nu)))
+    return nu
+
+
+def tk_step_bench(ctx: int, method: int, x: np.ndarray, K: int, reps: int = 1):
+    """One K-term step of the states x [M, d] by `method`; returns (y [M, d], ms per launch)."""
+    xs = np.ascontiguousarray(x, dtype=np.complex128)
+    M, d = xs.shape
+    y = np.zeros_like(xs)
+    ms = ctypes.c_double(0.0)
+    _check(ctx, _lib.tk_step_bench(ctx, method, M, K, _dptr(xs.view(np.float64)),
+                                   _dptr(y.view(np.float64)), reps, ctypes.byref(ms)))
+    return y, ms.value
+
+
+def tk_density_functional(ctx: int) -> float:
+    J = ctypes.c_double(0.0)
+    _check(ctx, _lib.tk_density_functional(ctx, ctypes.byref(J)))
+    return J.value
+
+
+def tk_density_krotov_iterate(ctx: int, n_iter: int) -> np.ndarray:
+    J = np.zeros(n_iter + 1)
+    _check(ctx, _lib.tk_density_krotov_iterate(ctx, n_iter, _dptr(J)))
+    return J
 
 
 def tk_set_timing(ctx: int, enable: bool) -> None:
@@ -432,8 +545,45 @@ class Context:
         cap = (8 * M + 64) * (n_iter + 1) if rec_cap is None else rec_cap
         return tk_krotov_iterate(self.h, M, seed, n_iter, first_iteration, cap)
 
+    def krotov_iterate_cross(self, M, seed, n_iter, first_iteration=0, rec_cap=None):
+        cap = (8 * M + 64) * (n_iter + 1) if rec_cap is None else rec_cap
+        return tk_krotov_iterate_cross(self.h, M, seed, n_iter, first_iteration, cap)
+
     def grad_pathwise(self, M, records):
         return tk_grad_pathwise(self.h, M, records, self.n_ctrl, self.nt)
+
+    # device-pointer variants (addresses and stream handles as ints)
+    def set_pulses_dev(self, nt, T, u_ptr, S_ptr=0, lam_ptr=0, stream=0):
+        tk_set_pulses_dev(self.h, nt, T, u_ptr, S_ptr, lam_ptr, stream)
+        self.nt = nt
+        self.T = float(T)
+
+    def get_pulses_dev(self, u_ptr, stream=0):
+        tk_get_pulses_dev(self.h, u_ptr, stream)
+
+    def functional_dev(self, M, seed, iteration, J_ptr, tau_ptr=0, stream=0):
+        tk_functional_dev(self.h, M, seed, iteration, J_ptr, tau_ptr, stream)
+
+    def krotov_iterate_dev(self, M, seed, n_iter, J_ptr, first_iteration=0, stream=0):
+        tk_krotov_iterate_dev(self.h, M, seed, first_iteration, n_iter, J_ptr, stream)
+
+    def grad_pathwise_dev(self, M, records, J_ptr, tau_ptr, g_ptr, stream=0):
+        tk_grad_pathwise_dev(self.h, M, records, J_ptr, tau_ptr, g_ptr, stream)
+
+    def pulse_noise(self, u=None, T=None):
+        """Noise measure nu_i (Sec. 3.4) of u [n_ctrl, nt], or of the current pulses."""
+        if u is None:
+            return tk_pulse_noise(self.h)[:self.n_ctrl]
+        return tk_pulse_noise(self.h, u, self.T if T is None else T)
+
+    def step_bench(self, method, x, K, reps=1):
+        return tk_step_bench(self.h, method, x, K, reps)
+
+    def density_functional(self):
+        return tk_density_functional(self.h)
+
+    def density_krotov_iterate(self, n_iter):
+        return tk_density_krotov_iterate(self.h, n_iter)
 
     def set_timing(self, enable=True):
         tk_set_timing(self.h, enable)
