@@ -324,6 +324,24 @@ TK_API int tk_krotov_iterate_dev(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t
 TK_API int tk_grad_pathwise_dev(tk_ctx *ctx, int32_t M, const tk_jump *rec, int64_t n_rec,
                                 double *J_T, double *tau_out, double *dJdu, tk_stream_t stream);
 
+/* ---- entry point that allocates nothing --------------------------------------- */
+
+/* tk_functional_dev for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): it calls no hipMalloc, hipFree or other allocating routine.
+ * The pass's error bits, record counter and the overlaps tau_k live in a fixed
+ * device array of 1 MiB per device (set up when a context is first created on
+ * the device, held until the process ends), so M is at most 65504
+ * (TK_EINVAL beyond).  No jump records and no final states are produced.
+ * J_T [1] and tau_out [2M] (may be NULL) are device pointers; stream as in the
+ * *_dev calls.  The context's system, states and pulses must be set (those
+ * calls do allocate).  Every call on a device shares that device's array and
+ * leaves its contents behind: calls that overlap on one device (from several
+ * host threads or contexts) race.  Errors: TK_ESTATE, TK_EINVAL, TK_ENUMERIC,
+ * TK_EHIP, TK_EUNSUPPORTED. */
+TK_API int tk_functional_dev_noalloc(tk_ctx *ctx, int32_t M, uint64_t seed, uint64_t iteration,
+                                     double *J_T, double *tau_out, tk_stream_t stream);
+
 /* ---- batched form: many optimisation instances at once --------------------- */
 
 /* A batch holds independent optimisation instances -- each a full problem as

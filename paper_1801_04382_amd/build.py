@@ -20,7 +20,7 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIBNAME = "libtrajkrotov.so"
 
 SOURCES = ["tk_kernels.hip", "tk_grad.hip", "tk_batch.hip", "tk_cross.hip", "tk_dense.hip",
-           "tk_post.hip", "tk_rho.hip", "tk_host.cpp", "tk_batch_host.cpp"]
+           "tk_noalloc.hip", "tk_post.hip", "tk_rho.hip", "tk_host.cpp", "tk_batch_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

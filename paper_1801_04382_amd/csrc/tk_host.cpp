@@ -1075,7 +1075,8 @@ int tk_create(tk_ctx **out, int device, int precision) {
   c->n_cu = prop.multiProcessorCount;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      tk::scratch_setup(device) != hipSuccess) {
     tk_destroy(c);
     return TK_EHIP;
   }
@@ -1436,6 +1437,47 @@ int tk_grad_pathwise_dev(tk_ctx *c, int32_t M, const tk_jump *rec, int64_t n_rec
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   int rc = join_in(c, s);
   if (!rc) rc = grad_impl(c, M, rec, n_rec, J_T, tau_out, dJdu, true);
+  const int rc2 = join_out(c, s);
+  return rc ? rc : rc2;
+}
+
+// ---- the entry point that allocates nothing --------------------------------------
+
+int tk_functional_dev_noalloc(tk_ctx *c, int32_t M, uint64_t seed, uint64_t iteration,
+                              double *J_T, double *tau_out, tk_stream_t stream) {
+  if (!c) return TK_EINVAL;
+  TK_HIP(c, hipSetDevice(c->device));
+  if (!c->has_system) return fail(c, TK_ESTATE, "no system set");
+  if (!c->has_states) return fail(c, TK_ESTATE, "no states set");
+  if (!c->has_pulses) return fail(c, TK_ESTATE, "no pulses set");
+  if (!J_T) return fail(c, TK_EINVAL, "J_T is NULL");
+  if (M < 1) return fail(c, TK_EINVAL, "M must be >= 1");
+  if (M > tk::kScratchMaxTraj)
+    return fail(c, TK_EINVAL, "M exceeds the fixed scratch of the no-allocation call (at most " +
+                                  std::to_string(tk::kScratchMaxTraj) + " trajectories)");
+  unsigned char *base = static_cast<unsigned char *>(tk::scratch_base(c->device));
+  if (!base) return fail(c, TK_EHIP, "device scratch not set up");
+  FixedBuffers fb;
+  fb.err = reinterpret_cast<int *>(base + tk::kScratchErrOffset);
+  fb.rec_count = reinterpret_cast<unsigned long long *>(base + tk::kScratchCountOffset);
+  fb.rec = reinterpret_cast<tk_jump *>(base + tk::kScratchRecOffset);
+  fb.tau = reinterpret_cast<double *>(base + tk::kScratchTauOffset);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = join_in(c, s);
+  if (rc) return rc;
+  TK_HIP(c, tk::scratch_clear(base, c->stream));
+  if ((rc = run_forward(c, M, seed, iteration, 0, &fb))) return rc;
+  {  // J_T = 1 - (1/M) sum |tau_k|^2 straight into the caller's memory
+    const double *tp = fb.tau;
+    double *jp = J_T;
+    int m = M;
+    void *args[] = {&tp, &m, &jp};
+    TK_HIP(c, hipLaunchKernel(tk::functional_kernel(), dim3(1), dim3(256), args, 0, c->stream));
+  }
+  if (tau_out)
+    TK_HIP(c, hipMemcpyAsync(tau_out, fb.tau, 2 * static_cast<size_t>(M) * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+  rc = check_kernel_errors(c, fb.err);
   const int rc2 = join_out(c, s);
   return rc ? rc : rc2;
 }

@@ -37,6 +37,16 @@ constexpr uint64_t kSlotEmpty = 0xFFF7DEADBEEF5A5Aull;
 // costates of a segment from its checkpoint before it needs them.
 constexpr int kSegment = 64;
 
+// Fixed device scratch of the entry point that allocates nothing: error bits,
+// record counter, a record slot and the overlaps of up to kScratchMaxTraj
+// trajectories (tk_noalloc.hip).
+constexpr size_t kScratchBytes = size_t(1) << 20;
+constexpr size_t kScratchErrOffset = 0;
+constexpr size_t kScratchCountOffset = 8;
+constexpr size_t kScratchRecOffset = 64;
+constexpr size_t kScratchTauOffset = 512;
+constexpr int kScratchMaxTraj = static_cast<int>((kScratchBytes - kScratchTauOffset) / 16);
+
 struct TrajMeta {
   double nrm2;  // squared norm of the unnormalised state
   double r;     // current threshold
@@ -178,6 +188,14 @@ const Variant *variants(int *count);
 
 // Kernel reducing J_T = 1 - (1/M) sum |tau_k|^2 (one block of 256 threads).
 const void *functional_kernel();
+
+// Fixed device scratch of the no-allocation entry point (tk_noalloc.hip):
+// scratch_setup looks the array's address up on `device` (once; at context
+// creation), scratch_base returns it (null before setup), scratch_clear zeroes
+// its error bits and record counter on `stream`.
+hipError_t scratch_setup(int device);
+void *scratch_base(int device);
+hipError_t scratch_clear(void *base, hipStream_t stream);
 
 // Cross-trajectory update (tk_cross.hip): the sequential pass of a one-wave
 // variant (null for multi-wave ones), the kernel forming the Gram matrices

@@ -132,6 +132,9 @@ _SIGNATURES = {
     "tk_grad_pathwise_dev": (ctypes.c_int, [_ctx_p, ctypes.c_int32, _P(tk_jump), ctypes.c_int64,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p]),
+    "tk_functional_dev_noalloc": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_uint64,
+                                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p]),
     "tk_pulse_noise": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                       _dp, _dp]),
     "tk_step_bench": (ctypes.c_int, [_ctx_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -396,6 +399,12 @@ def tk_functional_dev(ctx: int, M: int, seed: int, iteration: int, J_ptr: int, t
                       stream: int = 0) -> None:
     _check(ctx, _lib.tk_functional_dev(ctx, M, seed, iteration, J_ptr, tau_ptr or None,
                                        stream or None))
+
+
+def tk_functional_dev_noalloc(ctx: int, M: int, seed: int, iteration: int, J_ptr: int,
+                              tau_ptr: int = 0, stream: int = 0) -> None:
+    _check(ctx, _lib.tk_functional_dev_noalloc(ctx, M, seed, iteration, J_ptr, tau_ptr or None,
+                                               stream or None))
 
 
 def tk_krotov_iterate_dev(ctx: int, M: int, seed: int, first_iteration: int, n_iter: int,
