@@ -354,24 +354,19 @@ def bench_cross(workload: str, steps: int) -> dict:
                                  "symmetry not used)"}}
 
 
-def bench_noise_scaling(workload: str, Ms, iterations: int) -> dict:
-    """Pulse-noise measure nu_i (Sec. 3.4) of pulses optimised with M trajectories
-    (independent update, `iterations` iterations, same guess), and the fitted
-    exponent of nu against M (the paper finds about -1/2)."""
-    import numpy as np
-    from paper_1801_04382_amd import trajkrotov as tk
-    from workloads import config_workload
-    nus = []
-    for M in Ms:
-        w = config_workload(workload, M=M)
-        with tk.Context(precision="fp64") as ctx:
-            ctx.load(w)
-            ctx.krotov_iterate(M, w.seed, iterations, rec_cap=0)
-            nus.append(ctx.pulse_noise().tolist())
-    nu = np.array(nus)
-    slopes = [float(np.polyfit(np.log(Ms), np.log(nu[:, i]), 1)[0]) for i in range(nu.shape[1])]
-    return {"workload": workload, "M": list(Ms), "iterations": iterations, "nu": nus,
-            "fitted_exponent_per_control": slopes}
+def bench_paper_model(Ms, n_iter: int) -> dict:
+    """The paper's two-node network (Sec. 3.2-3.4): density-matrix, independent
+    and cross-trajectory optimisations from a smooth Blackman guess; the
+    density-matrix error of each run's pulses and the fitted exponent of the
+    pulse noise nu_i against M (the paper finds about -1/2)."""
+    from paper_1801_04382_amd.experiments import convergence_study
+    t0 = time.perf_counter()
+    out = convergence_study(2, Ms, n_iter, every=max(1, n_iter // 4))
+    out["seconds"] = time.perf_counter() - t0
+    out["final_J_rho"] = {f"{r['method']}_M{r['M']}": r["J_rho"][-1] for r in out["runs"]}
+    out["guess_J_rho"] = out["runs"][0]["J_rho"][0]
+    out.pop("runs")
+    return out
 
 
 def bench_step_methods(cases, M: int, reps: int) -> dict:
@@ -419,6 +414,30 @@ def copy_probe(mib: int, reps: int) -> int:
     return 0
 
 
+FORMS = {
+    "batched": ("batched_fp32", lambda a: bench_batched(
+        a.batch_instances, a.batch_steps, [int(x) for x in a.batch_nodes.split(",")], 2)),
+    # the same draw restricted to chains of 2 and 3 nodes (d = 36, 216)
+    "batched23": ("batched_fp32_chains_2_3", lambda a: bench_batched(
+        a.batch_instances, a.batch_steps, [2, 3], 2)),
+    "grad": ("grad_fp64", lambda a: bench_grad(a.workload, 3)),
+    "precision": ("precision_fp32_vs_fp64", lambda a: bench_precision("chain3_fock2")),
+    "grad_large": ("grad_fp32_d1296", lambda a: bench_grad_large("chain4_fock2")),
+    "cross": ("cross_trajectory_fp64", lambda a: bench_cross(a.workload, 2)),
+    "paper": ("paper_model_N2", lambda a: bench_paper_model([4, 16, 64, 256], 40)),
+    "step": ("step_dense_mfma_vs_sparse", lambda a: bench_step_methods(
+        ["chain2_fock2", "chain2_fock3", "chain3_fock2"], 1024, 20)),
+}
+
+
+def run_forms(args, names) -> dict:
+    out = {}
+    for key, (label, fn) in FORMS.items():
+        if names is None or key in names:
+            out[label] = fn(args)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,6 +455,9 @@ def main() -> int:
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--batch-nodes", default="2,3,4")
+    ap.add_argument("--only-forms", default="", metavar="NAMES",
+                    help="run only these forms (comma-separated: batched, batched23, grad, "
+                         "precision, grad_large, cross, paper, step) and print them")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
@@ -448,6 +470,10 @@ def main() -> int:
 
     if args.copy_probe:
         return copy_probe(args.copy_probe, args.steps)
+    if args.only_forms:
+        print(json.dumps({"forms": run_forms(args, set(args.only_forms.split(",")))},
+                         default=float), flush=True)
+        return 0
 
     from paper_1801_04382_amd import trajkrotov as tk
     from workloads import CONFIGS, config_workload
@@ -513,21 +539,7 @@ def main() -> int:
     }
     ctx.close()
     if not args.no_forms:
-        out["forms"] = {
-            "batched_fp32": bench_batched(args.batch_instances, args.batch_steps,
-                                          [int(x) for x in args.batch_nodes.split(",")], 2),
-            # the same draw restricted to chains of 2 and 3 nodes (d = 36, 216): the
-            # per-step work of those instances is comparable to the plain form's
-            "batched_fp32_chains_2_3": bench_batched(args.batch_instances, args.batch_steps,
-                                                     [2, 3], 2),
-            "grad_fp64": bench_grad(args.workload, 3),
-            "precision_fp32_vs_fp64": bench_precision("chain3_fock2"),
-            "grad_fp32_d1296": bench_grad_large("chain4_fock2"),
-            "cross_trajectory_fp64": bench_cross(args.workload, 2),
-            "pulse_noise_vs_M": bench_noise_scaling("chain2_fock2", [16, 64, 256, 1024], 5),
-            "step_dense_mfma_vs_sparse": bench_step_methods(
-                ["chain2_fock2", "chain2_fock3", "chain3_fock2"], 1024, 20),
-        }
+        out["forms"] = run_forms(args, None)
         # the target figure: the batching workload as configured (chains of 2-4
         # nodes) against the plain FP64 form; trajectory-steps of different d
         # are counted alike, so d = 1296 steps (~29x the work of a d = 81 step)

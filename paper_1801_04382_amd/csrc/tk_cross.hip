@@ -127,7 +127,28 @@ __device__ __forceinline__ void cross_costate(const PassArgs &a, int j, const cx
 #pragma unroll
     for (int m = 0; m < R; ++m) acc[q][m] = cx<double>{0.0, 0.0};
   const cx<double> *Pj = static_cast<const cx<double> *>(a.pmat) + static_cast<size_t>(j) * a.d * Rp;
-  for (int c = c_lo; c < c_hi; ++c) {
+  // columns in groups of kCols: the group's loads are all issued before its
+  // multiply-adds, so their latencies overlap (a column slice is read from L2)
+  constexpr int kCols = R >= 4 ? 2 : 8 / R;
+  int c = c_lo;
+  for (; c + kCols <= c_hi; c += kCols) {
+    cx<double> pc[kCols][R];
+#pragma unroll
+    for (int u = 0; u < kCols; ++u)
+#pragma unroll
+      for (int m = 0; m < R; ++m) pc[u][m] = gld(Pj, static_cast<size_t>(c + u) * Rp + lane + kL * m);
+#pragma unroll
+    for (int u = 0; u < kCols; ++u)
+#pragma unroll
+      for (int q = 0; q < kWavesPerBlock; ++q) {
+        if (q < tpb) {
+          const cx<double> x = xhat[q * Rp + c + u];
+#pragma unroll
+          for (int m = 0; m < R; ++m) cfma(acc[q][m], pc[u][m], x);
+        }
+      }
+  }
+  for (; c < c_hi; ++c) {
     cx<double> pc[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) pc[m] = gld(Pj, static_cast<size_t>(c) * Rp + lane + kL * m);
