@@ -27,31 +27,25 @@ PEAK = {"fp64": 78.6, "fp32": 157.3}  # published MI355X vector peaks, TFLOP/s
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
 # each scaled by what the counter reads for a device copy of known size
 # (a 1 GiB copy reads FETCH_SIZE 524300 KiB and WRITE_SIZE 1048576 KiB, hence
-# factors 2.0 and 1.0).  Keyed by kernel, workload and the hash of the kernel
-# sources the counters were taken with; a different hash reports null.
+# factors 2.0 and 1.0).  Keyed by kernel and workload, and valid for the build
+# the counters were taken with (the library's build id, a digest of all its
+# sources and flags); any other build reports null.
 TRAFFIC = {
     ("krotov", "chain2_fock3", "fp64", 1024, 2000): {
-        "sources": "a1f6c42e71870dda", "fetch_kib": 1463539, "write_kib": 17371,
+        "build": "abb905daa807508a", "fetch_kib": 1459000, "write_kib": 17370,
         "fetch_scale": 2.0, "write_scale": 1.0},
 }
-KERNEL_SOURCES = ["paper_1801_04382_amd/csrc/tk_kernels.hip",
-                  "paper_1801_04382_amd/csrc/tk_device.h",
-                  "paper_1801_04382_amd/csrc/tk_internal.h"]
 
 
 def sources_hash() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1801_04382_amd.build import source_hash
+    return source_hash()
 
 
 def measured_traffic(kernel: str, workload: str, prec: str, M: int, nt: int):
     """HBM bytes per launch of `kernel` from the stored counters, or None."""
     t = TRAFFIC.get((kernel, workload, prec, M, nt))
-    if t is None or t["sources"] != sources_hash():
+    if t is None or t["build"] != sources_hash():
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
