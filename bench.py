@@ -115,6 +115,18 @@ def alg_flops_per_traj_step(w, u, prec: str):
     return 8.0 * K * nnz + 8.0 * K * w.dim + 4.0 * w.dim, K
 
 
+def grad_alg_flops(w, u, prec: str) -> float:
+    """Algorithmic flops of one pathwise gradient: the replay, the segment
+    recompute, each unit's forward series and its costate series (4
+    pass-equivalents at the step's order K), plus the pairs of the two series
+    per step: the weighted sums of the kept forward terms (K(K+1)/2 real-by-
+    complex multiply-adds per row) and one imaginary part of a product per
+    control and costate term (2 multiply-adds per row)."""
+    f, K = alg_flops_per_traj_step(w, u, prec)
+    pairs = 2.0 * K * (K + 1) * w.dim + 4.0 * len(w.H_ctrl) * K * w.dim
+    return w.M * float((4.0 * f + pairs).sum())
+
+
 def roofline_entry(flops: float, seconds: float, prec: str, **extra) -> dict:
     achieved = flops / seconds / 1e12
     out = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK[prec],
@@ -250,15 +262,12 @@ def bench_grad(workload: str, reps: int) -> dict:
         el = time.perf_counter() - t0
         t = ctx.timing(tk.TK_KERNEL_GRAD)
     avg = t["ms_total"] / t["launches"]
-    f, _ = alg_flops_per_traj_step(w, w.u0, "fp64")
-    # replay, segment recompute, costate sweep and the augmented series (1 +
-    # n_ctrl chains): 4 + n_ctrl pass-equivalents
-    flops = (4.0 + len(w.H_ctrl)) * w.M * float(f.sum())
+    flops = grad_alg_flops(w, w.u0, "fp64")
     return {"workload": workload, "d": w.dim, "M": w.M, "nt": w.nt, "records": int(n),
             "ms_per_gradient": 1e3 * el / reps, "kernel_ms": avg,
             "value": w.M * w.nt * reps / el, "unit": "trajectory-steps/s (replay + reverse sweep)",
             "roofline": roofline_entry(flops, avg * 1e-3, "fp64", kernel="k_grad",
-                                       pass_equivalents=4 + len(w.H_ctrl))}
+                                       pass_equivalents=4)}
 
 
 def bench_precision(workload: str) -> dict:
@@ -304,13 +313,12 @@ def bench_grad_large(workload: str) -> dict:
         el = time.perf_counter() - t0
         t = ctx.timing(tk.TK_KERNEL_GRAD)
         variant = ctx.launch_info()["variant"]
-    f, _ = alg_flops_per_traj_step(w, w.u0, "fp32")
-    flops = (4.0 + len(w.H_ctrl)) * w.M * float(f.sum())
+    flops = grad_alg_flops(w, w.u0, "fp32")
     return {"workload": workload, "d": w.dim, "M": w.M, "nt": w.nt, "records": int(n),
             "variant": variant, "s_per_gradient": el, "kernel_ms": t["ms_total"],
             "value": w.M * w.nt / el, "unit": "trajectory-steps/s (replay + reverse sweep)",
             "roofline": roofline_entry(flops, t["ms_total"] * 1e-3, "fp32", kernel="k_grad",
-                                       pass_equivalents=4 + len(w.H_ctrl))}
+                                       pass_equivalents=4)}
 
 
 def bench_cross(workload: str, steps: int) -> dict:

@@ -15,14 +15,18 @@
 //      the segment's step-start states from its checkpoint into a per-wave
 //      stash, then walk its steps backward.  For every propagator unit of a
 //      step (a piece between jumps, cut into substeps no longer than the
-//      MCWF step plan's), the state at the unit's start is recomputed from the
-//      step's stashed start, and an augmented Taylor series gives both
-//      X = exp(-i H tau) x and Y_i = d X / d u_i (the top-right block of
-//      exp(tau [[-iH, -iH_i], [0, -iH]]), Van Loan 1978).  Then
+//      MCWF step plan's), the state x at the unit's start is recomputed from
+//      the step's stashed start and the unit's series is run keeping its
+//      terms s_k = (-i h H)^k x / k!.  Then
 //        lambda <- c L_l^+ lambda   for the jump that ends the piece
 //                                   (c = 1 / ||L_l X||, as in the forward map),
-//        g_ij   += Re <lambda|Y_i>,
-//        lambda <- exp(+i H^+ tau) lambda.
+//      and the costate series t_m = (i h H^+)^m lambda / m! both advances
+//      lambda <- exp(+i H^+ h) lambda and gives the unit's derivative: the
+//      top-right block of exp(h [[-iH, -iH_i], [0, -iH]]) (Van Loan 1978),
+//      expanded in powers of h, pairs the two series as
+//        Re <lambda|dX/du_i> = h Im sum_{m+k<K} m! k! / (m+k+1)! <t_m|H_i|s_k>,
+//      added to g_ij.  The forward and costate operators are loaded for the
+//      phase that uses them, so only one of them holds registers at a time.
 //   3. dJ_T/du_ij = -(2/M) sum_k g_kij, summed over k in a fixed order.
 #include <hip/hip_runtime.h>
 
@@ -64,7 +68,7 @@ __device__ void propagate_piece(const LaneOp<real, R, WS, NC, G> &op, const Pass
   for (int s = 0; s < n; ++s) {
     cx<real> out[R];
     tm.sync();
-    taylor_pingpong<real, R, WS, NC, G, -1, false>(op, a, T, psi, out, hs, p.K, tm);
+    taylor_pingpong<real, R, WS, NC, G, -1>(op, a, T, psi, out, hs, p.K, tm);
     copy_state(out, psi);
   }
 }
@@ -112,116 +116,196 @@ __device__ void replay_step(const LaneOp<real, R, WS, NC, G> &op, const PassArgs
   }
 }
 
-// Augmented Taylor series over tau (forward direction):
-//   x_n = (tau/n)(-i) H x_{n-1},  y_{i,n} = (tau/n)(-i)(H y_{i,n-1} + H_i x_{n-1}),
-// X = sum x_n, Y_i = sum y_{i,n} for the controls i < n_ctrl.  Term vectors are
-// double-buffered in LDS: buffer b holds x in T[b (1 + NCX)] and y_i in
-// T[b (1 + NCX) + 1 + i].
-template <typename real, int R, int WS, int NC, int G>
-__device__ void taylor_aug(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
-                           const Terms<real, R, G> &T, const cx<real> (&x0)[R], cx<real> (&X)[R],
-                           cx<real> (&Y)[NC > 0 ? NC : 1][R], double tau, int K, const Team<G> &tm) {
+// Control of slot c (c / wc), by comparisons
+template <int NC>
+__device__ __forceinline__ int slot_ctrl(int c, int wc) {
+  int i = 0;
+#pragma unroll
+  for (int ii = 1; ii < NC; ++ii)
+    if (c >= ii * wc) i = ii;
+  return i;
+}
+
+// v = sum_{k=0}^{Kg-1-m} beta_{m,k} s_k over the lane's rows, for the kept
+// forward terms s_k at fown + k kLen; beta_{m,k} = m! k! / (m + k + 1)!, from
+// beta_{m,0} = 1 / (m + 1) and beta_{m,k+1} = beta_{m,k} (k + 1) / (m + k + 2).
+template <typename real, int R, int G>
+__device__ __forceinline__ void pair_weights(const PassArgs &a, const cx<real> *fown, int m,
+                                             int Kg, cx<real> (&v)[R]) {
+  constexpr int kLen = Terms<real, R, G>::kLen;
+  constexpr int kL = Team<G>::kLanes;
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = cx<real>{0, 0};
+  double beta = a.inv_n[m + 1];
+#pragma unroll 2
+  for (int k = 0; k + m < Kg; ++k) {
+    const real bk = static_cast<real>(beta);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const cx<real> s = fown[k * kLen + kL * r];
+      v[r] = cx<real>{fma(bk, s.x, v[r].x), fma(bk, s.y, v[r].y)};
+    }
+    beta *= static_cast<double>(k + 1) * a.inv_n[m + k + 2];
+  }
+}
+
+// One term of the costate series together with the gradient pairs of its
+// input: gathers t_m (the term vector at the bound addresses plus OFF),
+// leaves t_{m+1} = (i h / (m + 1)) H^+ t_m in t (added to inc), and adds
+// Im <H_i^+ t_m | v> over the lane's rows to gp[i].  op.cv holds the unscaled
+// control elements (of H_i^+); us[c] is the pulse value of slot c.
+template <typename real, int R, int WS, int NC, int G, int OFF>
+__device__ __forceinline__ void costate_term(const LaneOp<real, R, WS, NC, G> &op,
+                                             const real (&us)[NC > 0 ? NC : 1], int wc, real cf,
+                                             const cx<real> (&v)[R], cx<real> (&t)[R],
+                                             cx<real> (&inc)[R], real (&gp)[NC > 0 ? NC : 1]) {
   constexpr int NCX = NC > 0 ? NC : 1;
-  const int nctl = a.n_ctrl;
-  cx<real> incX[R];
+  constexpr int H = (WS + 1) / 2;
+  cx<real> y[R];
 #pragma unroll
-  for (int m = 0; m < R; ++m) incX[m] = cx<real>{0, 0};
+  for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+  gather_fma<real, R, WS, NC, G, OFF, 0, H>(op, 0, y);
+  if constexpr (H < WS) gather_fma<real, R, WS, NC, G, OFF, H, WS>(op, 0, y);
+  if constexpr (NC > 0) {
+    cx<real> b[NC][R];
 #pragma unroll
-  for (int i = 0; i < NCX; ++i)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int m = 0; m < R; ++m) Y[i][m] = cx<real>{0, 0};
-  tm.sync();
-  store_lds(T[0], x0, tm);
-#pragma unroll
-  for (int i = 0; i < NCX; ++i)
-    if (i < nctl) store_lds(T[1 + i], Y[i], tm);
-  int cur = 0;
-  for (int n = 1; n <= K; ++n) {
-    tm.sync();
-    constexpr int kLen = Terms<real, R, G>::kLen;
-    const int xshift = cur * (1 + NCX) * kLen;  // x_{n-1}: term vector cur (1 + NCX)
-    // gathers of x_{n-1}: H x and the unscaled H_i x from the same loads.
-    // Eight-wave teams (short of registers) gather the static slots, multiply
-    // them, then gather the control slots; the others issue all gathers first.
-    constexpr bool kHalves = G >= 4;
-    cx<real> b[WS + NCX][R];
-#pragma unroll
-    for (int s = 0; s < WS; ++s)
-#pragma unroll
-      for (int m = 0; m < R; ++m) b[s][m] = op.sp[s][m][xshift];
-    if constexpr (!kHalves) {
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int m = 0; m < R; ++m) b[WS + c][m] = op.cp[c][m][xshift];
-    }
+      for (int m = 0; m < R; ++m) b[c][m] = op.cp[c][m][OFF];
     __builtin_amdgcn_sched_barrier(0);
-    cx<real> hx[R], hix[NCX][R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) hx[m] = cx<real>{0, 0};
-#pragma unroll
-    for (int i = 0; i < NCX; ++i)
-#pragma unroll
-      for (int m = 0; m < R; ++m) hix[i][m] = cx<real>{0, 0};
-#pragma unroll
-    for (int s = 0; s < WS; ++s)
-#pragma unroll
-      for (int m = 0; m < R; ++m) cfma(hx[m], op.sval[s][m], b[s][m]);
-    if constexpr (kHalves) {
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int m = 0; m < R; ++m) b[WS + c][m] = op.cp[c][m][xshift];
-      __builtin_amdgcn_sched_barrier(0);
-    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      int i = 0;  // control of slot c: c / wc, by comparisons
-#pragma unroll
-      for (int ii = 1; ii < NC; ++ii)
-        if (c >= ii * a.wc) i = ii;
+      const int i = slot_ctrl<NC>(c, wc);
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        cfma(hx[m], op.cv[c][m], b[WS + c][m]);
-        const cx<real> q = op.cval_at(c, m);
+        const cx<real> q = op.cv[c][m];
+        const cx<real> pr{q.x * b[c][m].x - q.y * b[c][m].y, q.x * b[c][m].y + q.y * b[c][m].x};
+        y[m] = cx<real>{fma(us[c], pr.x, y[m].x), fma(us[c], pr.y, y[m].y)};
+        const real im = pr.x * v[m].y - pr.y * v[m].x;  // Im(conj(pr) v)
 #pragma unroll
         for (int ii = 0; ii < NCX; ++ii)
-          if (ii == i) cfma(hix[ii][m], q, b[WS + c][m]);
+          if (ii == i) gp[ii] += im;
       }
     }
-    const real cf = static_cast<real>(tau * a.inv_n[n]);
-    const int nxt = cur ^ 1;
-    cx<real> t[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      t[m] = cx<real>{cf * hx[m].y, -cf * hx[m].x};  // (tau/n)(-i) H x
-      incX[m].x += t[m].x;
-      incX[m].y += t[m].y;
-    }
-    // y_i terms (the gathers of y_{i,n-1} read the current buffer)
-    cx<real> ty[NCX][R];
-#pragma unroll
-    for (int i = 0; i < NCX; ++i) {
-      if (i < nctl) {
-        cx<real> hy[R];
-        op.apply_at((cur * (1 + NCX) + 1 + i) * kLen, hy);
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-          const real sx = hy[m].x + hix[i][m].x, sy = hy[m].y + hix[i][m].y;
-          ty[i][m] = cx<real>{cf * sy, -cf * sx};
-          Y[i][m].x += ty[i][m].x;
-          Y[i][m].y += ty[i][m].y;
-        }
-      }
-    }
-    store_lds(T[nxt * (1 + NCX)], t, tm);
-#pragma unroll
-    for (int i = 0; i < NCX; ++i)
-      if (i < nctl) store_lds(T[nxt * (1 + NCX) + 1 + i], ty[i], tm);
-    cur = nxt;
   }
 #pragma unroll
-  for (int m = 0; m < R; ++m) X[m] = cx<real>{x0[m].x + incX[m].x, x0[m].y + incX[m].y};
+  for (int m = 0; m < R; ++m) {
+    t[m] = cx<real>{-cf * y[m].y, cf * y[m].x};
+    inc[m].x += t[m].x;
+    inc[m].y += t[m].y;
+  }
+}
+
+// Costate series over one propagator unit of length h with the gradient of
+// the unit.  With the forward terms s_k = (-i h H)^k x / k! of the unit kept
+// in Tf[0 .. Kg] and the costate terms t_m = (i h H^+)^m lambda / m!, the
+// derivative of the unit's propagator along H_i (the top-right block of Van
+// Loan's block exponential, truncated at order Kg) satisfies
+//   <lambda| dX/du_i = -i h sum_{m+k<=Kg-1} beta_{m,k} <t_m| H_i |s_k>,
+// so Re <lambda|dX/du_i> = h Im(...), added to gl[i].  The costate advances
+// as lambda <- sum_{m<=Kg} t_m = exp(+i H^+ h) lambda; its terms alternate
+// between Tc[0] and Tc[1], where the gathers of op are bound.
+template <typename real, int R, int WS, int NC, int G>
+__device__ void costate_grad(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                             const Terms<real, R, G> &Tc, const Terms<real, R, G> &Tf,
+                             const real (&us)[NC > 0 ? NC : 1], cx<real> (&lam)[R], double h,
+                             int Kg, double (&gl)[NC > 0 ? NC : 1], const Team<G> &tm) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  constexpr int kLen = Terms<real, R, G>::kLen;
+  constexpr int kL = Team<G>::kLanes;
+  cx<real> *own = Tc.base + tm.gl;
+  const cx<real> *fown = Tf.base + tm.gl;
+  cx<real> t[R], inc[R];
+  real gp[NCX];
+#pragma unroll
+  for (int i = 0; i < NCX; ++i) gp[i] = 0;
+  tm.sync();  // every gather of the previous use of Tc[0] is done
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    t[m] = lam[m];
+    inc[m] = cx<real>{0, 0};
+    own[kL * m] = t[m];
+  }
+  for (int n = 0; n < Kg; n += 2) {  // t_{n+1}, t_{n+2} from t_n (Tc[0]), t_{n+1} (Tc[1])
+    cx<real> v[R];
+    pair_weights<real, R, G>(a, fown, n, Kg, v);
+    tm.sync();
+    costate_term<real, R, WS, NC, G, 0>(op, us, a.wc, static_cast<real>(h * a.inv_n[n + 1]), v,
+                                        t, inc, gp);
+#pragma unroll
+    for (int m = 0; m < R; ++m) own[kLen + kL * m] = t[m];
+    if (n + 2 > Kg) break;
+    pair_weights<real, R, G>(a, fown, n + 1, Kg, v);
+    tm.sync();
+    costate_term<real, R, WS, NC, G, kLen>(op, us, a.wc, static_cast<real>(h * a.inv_n[n + 2]),
+                                           v, t, inc, gp);
+#pragma unroll
+    for (int m = 0; m < R; ++m) own[kL * m] = t[m];
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) lam[m] = cx<real>{lam[m].x + inc[m].x, lam[m].y + inc[m].y};
+#pragma unroll
+  for (int i = 0; i < NCX; ++i) gl[i] = fma(h, static_cast<double>(gp[i]), gl[i]);
+}
+
+// A pointer the compiler cannot follow across this point: loads through it
+// stay where they are written instead of being hoisted out of the sweep's
+// loops, which would keep both operators in registers for the whole sweep.
+template <typename T>
+__device__ __forceinline__ const T *opaque(const T *p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+// the same for a lane index: the per-lane addresses derived from it are
+// formed where the loads are, not kept in registers across the sweep
+__device__ __forceinline__ int opaque_lane(int gl) {
+  asm volatile("" : "+v"(gl));
+  return gl;
+}
+
+// The forward operator (H_eff at the pulses uj) or the costate operator
+// (H_eff^+, unit pulses: the costate series applies them itself), with its
+// gathers bound to t0
+template <typename real, int R, int WS, int NC, int G>
+__device__ __forceinline__ void load_forward(LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                                             const cx<real> *t0,
+                                             const double (&uj)[NC > 0 ? NC : 1], int gl) {
+  op.load(opaque(a.scol), opaque(static_cast<const cx<real> *>(a.sval)), opaque(a.ccol),
+          opaque(static_cast<const cx<real> *>(a.cval)), opaque_lane(gl));
+  op.bind(t0);
+  op.set_pulses(uj, a.wc);
+}
+
+template <typename real, int R, int WS, int NC, int G>
+__device__ __forceinline__ void load_costate(LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
+                                             const cx<real> *t0, int gl) {
+  constexpr int NCX = NC > 0 ? NC : 1;
+  double ones[NCX];
+#pragma unroll
+  for (int i = 0; i < NCX; ++i) ones[i] = 1.0;
+  op.load(opaque(a.a_scol), opaque(static_cast<const cx<real> *>(a.a_sval)), opaque(a.a_ccol),
+          opaque(static_cast<const cx<real> *>(a.a_cval)), opaque_lane(gl));
+  op.bind(t0);
+  op.set_pulses(ones, a.wc);
+}
+
+// lambda <- c L_l^+ lambda with c = 1 / ||L_l x|| (the adjoint of the forward
+// jump map at x); Tc[0] is scratch
+template <typename real, int R, int G>
+__device__ void jump_adjoint(const PassArgs &a, const Terms<real, R, G> &Tc, int l,
+                             const cx<real> (&x)[R], cx<real> (&lam)[R], const Team<G> &tm) {
+  cx<real> y[R];
+  tm.sync();
+  store_lds(Tc[0], x, tm);
+  tm.sync();
+  apply_jump<real, R, G>(a, l, Tc[0], y, tm);
+  const double c = 1.0 / sqrt(norm2(y, tm));  // the team sum orders the gathers above
+  store_lds(Tc[0], lam, tm);
+  tm.sync();
+  apply_packed<real, R, G>(a.ldcol, a.ldval, a.wld, l, Tc[0], y, tm);
+#pragma unroll
+  for (int m = 0; m < R; ++m)
+    lam[m] = cx<real>{static_cast<real>(c * y[m].x), static_cast<real>(c * y[m].y)};
 }
 
 template <typename real, int R, int WS, int NC, int G>
@@ -235,20 +319,25 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / kL);
   const int tpb = blockDim.x / kL;
   const Team<G> tm = make_team<G>(team_red);
-  const int nbuf = max(a.kbuf, 2 * (1 + NCX));
-  // LDS: per team nbuf term vectors; the unscaled control values of both
-  // operators are read from global memory (they are small and cached)
+  const int nbuf = a.kbuf;
+  // LDS per team: nbuf term vectors.  The replay passes use vectors 0 and 1
+  // (T); the reverse sweep keeps a unit's forward terms in vectors 2 ..
+  // nbuf - 1 (Tf) and runs the costate series in vectors 0 and 1 (Tc).
   Terms<real, R, G> T;
   T.base = reinterpret_cast<cx<real> *>(smem_raw) + static_cast<size_t>(team) * nbuf * kLen;
+  Terms<real, R, G> Tf;
+  Tf.base = T.base + 2 * kLen;
+  const Terms<real, R, G> &Tc = T;
+  const int kg_max = nbuf - 3;  // largest order whose kept terms fit Tf
   if (tm.gl < nbuf) T[tm.gl][R * kL] = cx<real>{0, 0};
   __syncthreads();
-  // the forward operator stays in registers; the costate operator is loaded
-  // where it is used (one series per substep of the reverse sweep), so the two
-  // slices never hold registers at once
-  LaneOp<real, R, WS, NC, G> opf;
-  opf.load(a.scol, a.sval, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
-  opf.bind(T[0]);
+  // Each phase loads the operator it uses (from global memory, where every
+  // team reads the same slices) and drops it afterwards, so the forward and
+  // costate operators never hold registers at the same time.
 
+  double zeros[NCX];
+#pragma unroll
+  for (int i = 0; i < NCX; ++i) zeros[i] = 0.0;
   const int nseg = (a.nt + kGradCheckpoint - 1) / kGradCheckpoint;
   const int wave = blockIdx.x * tpb + team;  // global team index
   const int nwaves = gridDim.x * tpb;
@@ -263,18 +352,22 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
     // ---- 1. forward replay with checkpoints ----
     cx<real> psi[R];
     get_rows(start, psi, tm);
-    int q = q_first;
-    for (int j = 0; j < a.nt; ++j) {
-      if (j % kGradCheckpoint == 0) put_rows(ck + (j / kGradCheckpoint) * R * kL, psi, tm);
-      int nj = 0;
-      while (q + nj < q_last && a.path_step[q + nj] == j) ++nj;
-      double uj[NCX];
+    {
+      LaneOp<real, R, WS, NC, G> opf;
+      load_forward(opf, a, T[0], zeros, tm.gl);  // pulses set per step
+      int q = q_first;
+      for (int j = 0; j < a.nt; ++j) {
+        if (j % kGradCheckpoint == 0) put_rows(ck + (j / kGradCheckpoint) * R * kL, psi, tm);
+        int nj = 0;
+        while (q + nj < q_last && a.path_step[q + nj] == j) ++nj;
+        double uj[NCX];
 #pragma unroll
-      for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
-      opf.set_pulses(uj, a.wc);
-      const StepPlan p = plan_step(a, uj, khint);
-      replay_step<real, R, WS, NC, G>(opf, a, T, psi, j, q, nj, p, tm);
-      q += nj;
+        for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
+        opf.set_pulses(uj, a.wc);
+        const StepPlan p = plan_step(a, uj, khint);
+        replay_step<real, R, WS, NC, G>(opf, a, T, psi, j, q, nj, p, tm);
+        q += nj;
+      }
     }
     // ---- functional and adjoint seed ----
     const double nrm2 = norm2(psi, tm);
@@ -310,21 +403,25 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       const int j0 = sg * kGradCheckpoint;
       const int j1 = min(a.nt, j0 + kGradCheckpoint);
       // recompute the segment's step-start states
-      get_rows(ck + sg * R * kL, psi, tm);
-      int qr = q_first;
-      while (qr < q_last && a.path_step[qr] < j0) ++qr;
-      for (int j = j0; j < j1; ++j) {
-        put_rows(stash + (j - j0) * R * kL, psi, tm);
-        if (j + 1 == j1) break;  // the last step's end state is not needed
-        int nj = 0;
-        while (qr + nj < q_last && a.path_step[qr + nj] == j) ++nj;
-        double uj[NCX];
+      {
+        LaneOp<real, R, WS, NC, G> opf;
+        load_forward(opf, a, T[0], zeros, tm.gl);  // pulses set per step
+        get_rows(ck + sg * R * kL, psi, tm);
+        int qr = q_first;
+        while (qr < q_last && a.path_step[qr] < j0) ++qr;
+        for (int j = j0; j < j1; ++j) {
+          put_rows(stash + (j - j0) * R * kL, psi, tm);
+          if (j + 1 == j1) break;  // the last step's end state is not needed
+          int nj = 0;
+          while (qr + nj < q_last && a.path_step[qr + nj] == j) ++nj;
+          double uj[NCX];
 #pragma unroll
-        for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
-        opf.set_pulses(uj, a.wc);
-        const StepPlan p = plan_step(a, uj, khint);
-        replay_step<real, R, WS, NC, G>(opf, a, T, psi, j, qr, nj, p, tm);
-        qr += nj;
+          for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
+          opf.set_pulses(uj, a.wc);
+          const StepPlan p = plan_step(a, uj, khint);
+          replay_step<real, R, WS, NC, G>(opf, a, T, psi, j, qr, nj, p, tm);
+          qr += nj;
+        }
       }
       for (int j = j1 - 1; j >= j0; --j) {
         int qs = qe;
@@ -333,96 +430,69 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
         double uj[NCX];
 #pragma unroll
         for (int i = 0; i < NCX; ++i) uj[i] = a.u[static_cast<size_t>(i) * a.nt + j];
-        opf.set_pulses(uj, a.wc);
         const StepPlan p = plan_step(a, uj, khint);
+        // order of the unit derivatives: the bound ||H_eff|| + max_i ||H_i||
+        // of Van Loan's block generator
         double bnd = a.b0;
 #pragma unroll
         for (int i = 0; i < NCX; ++i) bnd += fabs(uj[i]) * a.bc[i];
-        int Kaug = taylor_order(a, (bnd + a.bc_max) * p.h, p.K);
-        if (Kaug < 0) {
+        int Kg = taylor_order(a, (bnd + a.bc_max) * p.h, p.K);
+        if (Kg < 0 || Kg > kg_max) {
           if (tm.leader()) atomicOr(a.err, kErrTaylorOrder);
-          Kaug = a.kmax;
+          Kg = kg_max;
         }
-        double gl[NCX];  // lane partials of Re <lambda|Y_i> over the step's units
+        real us[NCX];  // pulse value of each control slot
+#pragma unroll
+        for (int c = 0; c < NCX; ++c) {
+          double u = uj[0];
+#pragma unroll
+          for (int i = 1; i < NCX; ++i)
+            if (c >= i * a.wc) u = uj[i];
+          us[c] = static_cast<real>(u);
+        }
+        double gl[NCX];  // lane partials of Re <lambda|dX/du_i> over the step's units
 #pragma unroll
         for (int i = 0; i < NCX; ++i) gl[i] = 0.0;
         for (int pc = nj; pc >= 0; --pc) {
           const double tau = fmax(piece_end(a, j, qs, pc, nj) - piece_start(a, j, qs, pc), 0.0);
-          // state at the start of piece pc
-          cx<real> ps[R];
-          get_rows(stash + (j - j0) * R * kL, ps, tm);
-          for (int qq = 0; qq < pc; ++qq) {
-            const double tq = fmax(piece_end(a, j, qs, qq, nj) - piece_start(a, j, qs, qq), 0.0);
-            propagate_piece<real, R, WS, NC, G>(opf, a, T, ps, tq, p, tm);
-            jump_map<real, R, G>(a, T, a.path_op[qs + qq], ps, tm);
-          }
-          if (!(tau > 0.0)) {
-            // zero-length piece: only the jump that ends it (if any) acts
-            if (pc < nj) {
-              cx<real> y[R];
-              tm.sync();
-              store_lds(T[0], ps, tm);
-              tm.sync();
-              apply_jump<real, R, G>(a, a.path_op[qs + pc], T[0], y, tm);
-              const double c = 1.0 / sqrt(norm2(y, tm));
-              tm.sync();
-              store_lds(T[0], lam, tm);
-              tm.sync();
-              apply_packed<real, R, G>(a.ldcol, a.ldval, a.wld, a.path_op[qs + pc], T[0], y, tm);
-#pragma unroll
-              for (int m = 0; m < R; ++m)
-                lam[m] = cx<real>{static_cast<real>(c * y[m].x), static_cast<real>(c * y[m].y)};
-            }
-            continue;
-          }
-          const int n = max(1, static_cast<int>(ceil(tau / p.h)));
-          const double hs = tau / n;
+          const int n = tau > 0.0 ? max(1, static_cast<int>(ceil(tau / p.h))) : 1;
+          const double hs = tau > 0.0 ? tau / n : 0.0;
           for (int s = n - 1; s >= 0; --s) {
-            // state at the start of substep s of this piece
-            cx<real> xs[R];
-            copy_state(ps, xs);
-            for (int ss = 0; ss < s; ++ss) {
-              cx<real> out[R];
-              tm.sync();
-              taylor_pingpong<real, R, WS, NC, G, -1, false>(opf, a, T, xs, out, hs, p.K, tm);
-              copy_state(out, xs);
-            }
-            cx<real> X[R], Y[NCX][R];
-            taylor_aug<real, R, WS, NC, G>(opf, a, T, xs, X, Y, hs, Kaug, tm);
-            if (s == n - 1 && pc < nj) {
-              // adjoint of the jump map that ends the piece: lambda <- c L^+ lambda
-              cx<real> y[R];
-              tm.sync();
-              store_lds(T[0], X, tm);
-              tm.sync();
-              apply_jump<real, R, G>(a, a.path_op[qs + pc], T[0], y, tm);
-              const double c = 1.0 / sqrt(norm2(y, tm));
-              tm.sync();
-              store_lds(T[0], lam, tm);
-              tm.sync();
-              apply_packed<real, R, G>(a.ldcol, a.ldval, a.wld, a.path_op[qs + pc], T[0], y, tm);
-#pragma unroll
-              for (int m = 0; m < R; ++m)
-                lam[m] = cx<real>{static_cast<real>(c * y[m].x), static_cast<real>(c * y[m].y)};
-            }
-#pragma unroll
-            for (int i = 0; i < NCX; ++i)
-#pragma unroll
-              for (int m = 0; m < R; ++m) {
-                gl[i] = fma(static_cast<double>(lam[m].x), static_cast<double>(Y[i][m].x), gl[i]);
-                gl[i] = fma(static_cast<double>(lam[m].y), static_cast<double>(Y[i][m].y), gl[i]);
-              }
-            // lambda <- exp(+i H^+ hs) lambda
-            cx<real> out[R];
+            cx<real> X[R];  // the unit's end state
             {
-              LaneOp<real, R, WS, NC, G> opb;
-              opb.load(a.a_scol, a.a_sval, a.a_ccol, static_cast<const cx<real> *>(a.a_cval), tm.gl);
-              opb.bind(T[0]);
-              opb.set_pulses(uj, a.wc);
-              tm.sync();
-              taylor_pingpong<real, R, WS, NC, G, 1, false>(opb, a, T, lam, out, hs, p.K, tm);
+              // forward: the state at the start of substep s of piece pc,
+              // then the unit's series keeping its terms in Tf
+              LaneOp<real, R, WS, NC, G> opf;
+              load_forward(opf, a, Tf[0], uj, tm.gl);
+              cx<real> xs[R];
+              get_rows(stash + (j - j0) * R * kL, xs, tm);
+              for (int qq = 0; qq < pc; ++qq) {
+                const double tq =
+                    fmax(piece_end(a, j, qs, qq, nj) - piece_start(a, j, qs, qq), 0.0);
+                propagate_piece<real, R, WS, NC, G>(opf, a, Tf, xs, tq, p, tm);
+                jump_map<real, R, G>(a, Tf, a.path_op[qs + qq], xs, tm);
+              }
+              if (!(tau > 0.0)) {
+                copy_state(xs, X);  // zero-length piece: only its jump acts
+              } else {
+                for (int ss = 0; ss < s; ++ss) {
+                  cx<real> out[R];
+                  tm.sync();
+                  taylor_pingpong<real, R, WS, NC, G, -1>(opf, a, Tf, xs, out, hs, p.K, tm);
+                  copy_state(out, xs);
+                }
+                tm.sync();
+                taylor_keep<real, R, WS, NC, G, -1>(opf, a, Tf, xs, X, hs, Kg, tm);
+              }
             }
-            copy_state(out, lam);
+            if (s == n - 1 && pc < nj) jump_adjoint<real, R, G>(a, Tc, a.path_op[qs + pc], X, lam, tm);
+            if (!(tau > 0.0)) continue;
+            {
+              // costate: lambda <- exp(+i H^+ hs) lambda with the unit's pairs
+              LaneOp<real, R, WS, NC, G> opb;
+              load_costate(opb, a, Tc[0], tm.gl);
+              costate_grad<real, R, WS, NC, G>(opb, a, Tc, Tf, us, lam, hs, Kg, gl, tm);
+            }
           }
         }
 #pragma unroll
@@ -476,9 +546,7 @@ const void *grad_reduce_kernel() { return reinterpret_cast<const void *>(&k_grad
 
 size_t grad_lds_bytes(const Variant &v, int teams, int kbuf) {
   const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
-  const size_t ncx = v.NC > 0 ? v.NC : 1;
-  const size_t nbuf = std::max<size_t>(kbuf, 2 * (1 + ncx));
-  return static_cast<size_t>(teams) * nbuf * (static_cast<size_t>(v.R) * kWave * v.G + 1) * cplx;
+  return static_cast<size_t>(teams) * kbuf * (static_cast<size_t>(v.R) * kWave * v.G + 1) * cplx;
 }
 
 }  // namespace tk

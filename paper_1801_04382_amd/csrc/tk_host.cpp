@@ -404,6 +404,25 @@ int plan_kbuf(const tk_ctx *c, const std::vector<double> &u, int margin) {
   return std::min(kmax + 1 + margin, tk::kMaxTaylor + 1);
 }
 
+// Term vectors of the gradient's reverse sweep: the kept terms t_0 .. t_Kg of
+// a propagator unit, Kg the order for the bound ||H_eff|| + max_i ||H_i|| of
+// Van Loan's block generator (at least the step's own order), plus two for
+// the costate series.
+int plan_kbuf_grad(const tk_ctx *c, const std::vector<double> &u, double bc_max) {
+  int kg = 1;
+  for (int j = 0; j < c->nt; ++j) {
+    int n_sub, K;
+    plan_step_host(c, u, j, &n_sub, &K);
+    double b = c->b0;
+    for (int i = 0; i < c->n_ctrl; ++i)
+      b += std::fabs(u[static_cast<size_t>(i) * c->nt + j]) * c->bc[i];
+    const double h = n_sub == 1 ? c->T / c->nt : (c->T / c->nt) / n_sub;
+    const int Kg = taylor_order_host((b + bc_max) * h, order_table(c->precision), tk::kMaxTaylor);
+    kg = std::max(kg, std::max(K, Kg));
+  }
+  return std::min(kg + 3, tk::kMaxTaylor + 1);
+}
+
 double pass_flops(const tk_ctx *c, const std::vector<double> &u, int M) {
   double f = 0.0;
   for (int j = 0; j < c->nt; ++j) {
@@ -817,6 +836,9 @@ int run_grad(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec) {
   const void *kern = c->var->k_grad;
   if (!kern) return fail(c, TK_EUNSUPPORTED, "no gradient kernel for this variant");
   tk::PassArgs a = base_args(c, M, 0, 0, false);
+  a.bc_max = 0.0;
+  for (int i = 0; i < c->n_ctrl; ++i) a.bc_max = std::max(a.bc_max, c->bc[i]);
+  a.kbuf = plan_kbuf_grad(c, c->u, a.bc_max);
   int wpb = 0;
   for (int w = c->var->G > 1 ? 1 : tk::kWavesPerBlock; w >= 1 && !wpb; w /= 2)
     if (tk::grad_lds_bytes(*c->var, w, a.kbuf) <= tk::kLdsBytes) wpb = w;
@@ -838,8 +860,6 @@ int run_grad(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec) {
   a.ldcol = c->ldcol.as<int>();
   a.ldval = c->ldval.p;
   a.wld = c->wld;
-  a.bc_max = 0.0;
-  for (int i = 0; i < c->n_ctrl; ++i) a.bc_max = std::max(a.bc_max, c->bc[i]);
   a.path_off = c->path_off.as<int>();
   a.path_step = c->path_step.as<int>();
   a.path_t = c->path_t.as<double>();
@@ -853,12 +873,13 @@ int run_grad(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec) {
   TimedLaunch tl(c, TK_KERNEL_GRAD);
   TK_HIP(c, hipLaunchKernel(kern, dim3(blocks), dim3(tk::kWave * c->var->G * wpb), args, lds,
                             c->stream));
-  // replay, recompute and adjoint sweeps (3 plain passes) plus the augmented
-  // series (1 + n_ctrl chains); bytes: checkpoints and the stash, written and
-  // read once, and the per-trajectory terms
+  // replay, segment recompute, the units' kept forward series and the
+  // costate series (4 plain passes; the pairs of the two series are not
+  // counted); bytes: checkpoints and the stash, written and read once, and
+  // the per-trajectory terms
   const double bytes = 2.0 * M * nseg * c->d * c->bulk_cplx() +
                        2.0 * M * c->nt * c->d * c->bulk_cplx() + 8.0 * ng * M;
-  rc = tl.finish(static_cast<int64_t>(M) * c->nt, (4.0 + c->n_ctrl) * pass_flops(c, c->u, M), bytes);
+  rc = tl.finish(static_cast<int64_t>(M) * c->nt, 4.0 * pass_flops(c, c->u, M), bytes);
   if (rc) return rc;
   if (ng > 0) {
     const double *gp = c->gk.as<double>();

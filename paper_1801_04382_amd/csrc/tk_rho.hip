@@ -69,6 +69,10 @@ __device__ void rho_interval(const RhoArgs &a, const double *uj, int d) {
   for (int c = 0; c < a.n_ctrl; ++c) b += fabs(uj[c]) * a.gen_bc[c];
   const double x = b * a.dt;
   int n_sub = x > kMaxStepNorm ? static_cast<int>(ceil(x / kMaxStepNorm)) : 1;
+  if (n_sub > kMaxSubsteps) {  // a generator far too large for the time step
+    if (threadIdx.x == 0) atomicOr(a.err, kErrTaylorOrder);
+    n_sub = kMaxSubsteps;
+  }
   const double h = a.dt / n_sub;
   int K = 1;
   while (K < a.kmax && b * h > a.ord_x[K]) ++K;
