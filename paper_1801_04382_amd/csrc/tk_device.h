@@ -309,6 +309,26 @@ __device__ __forceinline__ void cfma(cx<real> &y, const cx<real> &a, const cx<re
   y.y = fma(a.y, b.x, y.y);
 }
 
+// Values the compiler cannot follow across this point.  A load whose address
+// derives from one stays where it is written: the compiler neither hoists it
+// out of an enclosing loop nor keeps its 64-bit address in registers from an
+// earlier iteration (with one address per operator element, those held
+// addresses alone can push a kernel into scratch spills).
+template <typename T>
+__device__ __forceinline__ const T *opaque(const T *p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+__device__ __forceinline__ int opaque_lane(int gl) {
+  asm volatile("" : "+v"(gl));
+  return gl;
+}
+template <typename T>
+__device__ __forceinline__ const T *opaque_lane_ptr(const T *p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
 // ---- per-lane operator slice ------------------------------------------------
 template <typename real, int R, int WS, int NC, int G>
 struct LaneOp {
@@ -329,6 +349,7 @@ struct LaneOp {
   // global memory); gl is the lane within the team
   __device__ void load(const int *scol_g, const void *sval_g, const int *ccol_g,
                        const cx<real> *cval_src, int gl) {
+    gl = opaque_lane(gl);
     const cx<real> *sv = static_cast<const cx<real> *>(sval_g);
 #pragma unroll
     for (int s = 0; s < WS; ++s)
@@ -360,17 +381,19 @@ struct LaneOp {
       for (int m = 0; m < R; ++m) cp[c][m] = t0 + ccol[c][m];
   }
 
-  // unscaled control element of slot c, row slot m
-  __device__ __forceinline__ cx<real> cval_at(int c, int m) const {
+  // unscaled control element of slot c, row slot m (from the lane's elements at base)
+  __device__ __forceinline__ cx<real> cval_at(int c, int m, const cx<real> *base) const {
     // one-wave teams read a copy in LDS, G-wave teams global memory
     if constexpr (G > 1)
-      return gld(cval, (c * R + m) * kL);
+      return gld(base, (c * R + m) * kL);
     else
-      return cval[(c * R + m) * kL];
+      return base[(c * R + m) * kL];
   }
+  __device__ __forceinline__ cx<real> cval_at(int c, int m) const { return cval_at(c, m, cval); }
 
   // cv = u_{c / wc} * cval for the pulse values uj[0 .. NCX) (zero past n_ctrl)
   __device__ void set_pulses(const double (&uj)[NCX], int wc) {
+    const cx<real> *base = opaque_lane_ptr(cval);  // addresses formed here, per call
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       // control c / wc (< NC, hence a valid index), by comparisons: the slot
@@ -382,7 +405,7 @@ struct LaneOp {
       const real ui = static_cast<real>(u);
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const cx<real> q = cval_at(c, m);
+        const cx<real> q = cval_at(c, m, base);
         cv[c][m] = cx<real>{ui * q.x, ui * q.y};
       }
     }

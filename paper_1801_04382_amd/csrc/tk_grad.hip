@@ -248,21 +248,6 @@ __device__ void costate_grad(const LaneOp<real, R, WS, NC, G> &op, const PassArg
   for (int i = 0; i < NCX; ++i) gl[i] = fma(h, static_cast<double>(gp[i]), gl[i]);
 }
 
-// A pointer the compiler cannot follow across this point: loads through it
-// stay where they are written instead of being hoisted out of the sweep's
-// loops, which would keep both operators in registers for the whole sweep.
-template <typename T>
-__device__ __forceinline__ const T *opaque(const T *p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
-// the same for a lane index: the per-lane addresses derived from it are
-// formed where the loads are, not kept in registers across the sweep
-__device__ __forceinline__ int opaque_lane(int gl) {
-  asm volatile("" : "+v"(gl));
-  return gl;
-}
-
 // The forward operator (H_eff at the pulses uj) or the costate operator
 // (H_eff^+, unit pulses: the costate series applies them itself), with its
 // gathers bound to t0
@@ -271,7 +256,7 @@ __device__ __forceinline__ void load_forward(LaneOp<real, R, WS, NC, G> &op, con
                                              const cx<real> *t0,
                                              const double (&uj)[NC > 0 ? NC : 1], int gl) {
   op.load(opaque(a.scol), opaque(static_cast<const cx<real> *>(a.sval)), opaque(a.ccol),
-          opaque(static_cast<const cx<real> *>(a.cval)), opaque_lane(gl));
+          opaque(static_cast<const cx<real> *>(a.cval)), gl);
   op.bind(t0);
   op.set_pulses(uj, a.wc);
 }
@@ -284,7 +269,7 @@ __device__ __forceinline__ void load_costate(LaneOp<real, R, WS, NC, G> &op, con
 #pragma unroll
   for (int i = 0; i < NCX; ++i) ones[i] = 1.0;
   op.load(opaque(a.a_scol), opaque(static_cast<const cx<real> *>(a.a_sval)), opaque(a.a_ccol),
-          opaque(static_cast<const cx<real> *>(a.a_cval)), opaque_lane(gl));
+          opaque(static_cast<const cx<real> *>(a.a_cval)), gl);
   op.bind(t0);
   op.set_pulses(ones, a.wc);
 }
