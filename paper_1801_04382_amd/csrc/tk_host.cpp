@@ -698,31 +698,45 @@ int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap,
   // pulses grow during the pass: one spare term vector; the kernel adds
   // substeps if a step would still need more terms
   const int kbuf = plan_kbuf(c, c->u, 1);
-  auto lds_of = [&](int w, int t) {
+  auto lds_of = [&](int w, int t, bool in_lds) {
     return cross ? tk::cross_lds_bytes(*c->var, w, kbuf, t)
-                 : tk::block_lds_bytes(*c->var, w, kbuf, t);
+                 : tk::block_lds_bytes(*c->var, w, kbuf, t, in_lds);
   };
+  // States in LDS where they fit; otherwise (the independent-trajectory
+  // update only) in global memory, each team reading back its own rows.
+  // TK_KROTOV_STATES=global takes the global-memory form at any M (tests
+  // compare the two forms).
+  const char *st_env = std::getenv("TK_KROTOV_STATES");
+  const bool force_global = !cross && st_env && std::strcmp(st_env, "global") == 0;
   int tw = 0, wpb = 0, blocks = 0;
   size_t lds = 0;
-  for (int t = 1; t <= 64 && !tw; ++t)
-    for (int w = c->var->G > 1 ? 1 : tk::kWavesPerBlock; w >= 1; w /= 2) {
-      const int b = (M + w * t - 1) / (w * t);
-      const size_t l = lds_of(w, t);
-      if (b > tk::kMaxBlocks || l > tk::kLdsBytes) continue;
-      TK_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    static_cast<int>(l)));
-      int occ = 0;
-      TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, tk::kWave * c->var->G * w,
-                                                              l));
-      if (occ > 0 && static_cast<int64_t>(occ) * c->n_cu >= b) {
-        tw = t;
-        wpb = w;
-        blocks = b;
-        lds = l;
-        break;
+  bool in_lds = true;
+  for (int pass = force_global ? 1 : 0; pass < (cross ? 1 : 2) && !tw; ++pass) {
+    in_lds = pass == 0;
+    for (int t = 1; t <= 64 && !tw; ++t)
+      for (int w = c->var->G > 1 ? 1 : tk::kWavesPerBlock; w >= 1; w /= 2) {
+        const int b = (M + w * t - 1) / (w * t);
+        const size_t l = lds_of(w, t, in_lds);
+        if (b > tk::kMaxBlocks || l > tk::kLdsBytes) continue;
+        TK_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      static_cast<int>(l)));
+        int occ = 0;
+        TK_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &occ, kern, tk::kWave * c->var->G * w, l));
+        if (occ > 0 && static_cast<int64_t>(occ) * c->n_cu >= b) {
+          tw = t;
+          wpb = w;
+          blocks = b;
+          lds = l;
+          break;
+        }
       }
-    }
+  }
   if (!tw) return fail(c, TK_EUNSUPPORTED, "too many trajectories for one cooperative launch");
+  if (!in_lds) {
+    const size_t vec = static_cast<size_t>(c->var->R) * tk::kWave * c->var->G * c->bulk_cplx();
+    TK_HIP(c, c->kstates.ensure(static_cast<size_t>(blocks) * wpb * tw * vec));
+  }
   const int ncx = std::max(c->var->NC, 1);
   const size_t nslot = static_cast<size_t>(c->nt) * tk::kMaxBlocks * ncx;
   TK_HIP(c, c->slots.ensure(nslot * sizeof(unsigned long long)));
@@ -746,6 +760,7 @@ int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap,
   a.lam = c->lam_dev.as<double>();
   a.slots = c->slots.as<unsigned long long>();
   a.traj_per_wave = tw;
+  a.kstates = in_lds ? nullptr : c->kstates.p;
   a.kbuf = kbuf;
   a.pmat = cross ? c->pmat.p : nullptr;
   void *args[] = {&a};

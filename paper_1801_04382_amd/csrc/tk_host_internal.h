@@ -92,6 +92,7 @@ struct tk_ctx {
   tkh::DevBuf u_dev, u_new_dev, S_dev, lam_dev;
 
   tkh::DevBuf chi, tau, psiT, slots, rec, rec_count, err_dev, jt_dev;
+  tkh::DevBuf kstates;  // Krotov-pass states when they do not fit in LDS
   tkh::DevBuf path_off, path_step, path_t, path_op, ckpt, stash, gk, dJdu;
   tkh::DevBuf noise_u, noise_nu;  // pulse-noise measure
   tkh::DevBuf pmat, ones_tau;      // cross-trajectory update: Gram matrices, unit weights

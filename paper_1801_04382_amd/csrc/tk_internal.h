@@ -113,6 +113,9 @@ struct PassArgs {
   const double *lam;        // [kMaxCtrl] lambda_i
   unsigned long long *slots;  // [nt][kMaxBlocks][NC] per-block partial sums
   int traj_per_wave;        // trajectories owned by one wave
+  void *kstates;            // null: the Krotov pass keeps its states in LDS; else
+                            // [teams][traj_per_wave][64 G R] states in global memory
+                            // (bulk), for more trajectories than the LDS holds
   const void *pmat;         // cross-trajectory update: P_j = (1/M) sum_k |xi_k><xi_k|,
                             // complex128 [nt][d][64 R] (column c, padded rows)
   long long spin_limit;     // polls before a step reduction gives up
@@ -272,8 +275,9 @@ size_t grad_lds_bytes(const Variant &v, int teams, int kbuf);
 
 // LDS bytes of one block of `teams` teams (G waves each): the block's copy of
 // the control slots (one-wave teams only), then per team `kbuf` term vectors of 64 G R + 1 elements
-// and, for the Krotov pass, `traj_per_wave` state vectors and their
-// bookkeeping.
-size_t block_lds_bytes(const Variant &v, int teams, int kbuf, int traj_per_wave);
+// and, for the Krotov pass, `traj_per_wave` state vectors (unless they are
+// kept in global memory) and their bookkeeping.
+size_t block_lds_bytes(const Variant &v, int teams, int kbuf, int traj_per_wave,
+                       bool states_in_lds = true);
 
 }  // namespace tk

@@ -98,15 +98,40 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   const int Tw = a.traj_per_wave;
   const int tglob = blockIdx.x * tpb + team;
   // LDS per team: term vectors, then Tw state vectors, then Tw bookkeeping
+  // (the states and their bookkeeping live in global memory instead when
+  // a.kstates is set: more trajectories per team than the LDS holds)
+  // (the state vectors live in global memory instead when a.kstates is set:
+  // more trajectories per team than the LDS holds; each lane reads back only
+  // the rows it wrote)
+  const bool states_in_lds = a.kstates == nullptr;
   const size_t tb = terms_bytes<real, R, G>(a.kbuf);
+  const size_t sb = states_in_lds ? static_cast<size_t>(Tw) * R * kL * sizeof(cx<real>) : 0;
   // (rounded to 16 bytes: every team's vectors keep the alignment of cx<real>)
-  const size_t team_bytes = (tb + static_cast<size_t>(Tw) * R * kL * sizeof(cx<real>) +
-                             static_cast<size_t>(Tw) * sizeof(TrajMeta) + 15) / 16 * 16;
+  const size_t team_bytes = (tb + sb + static_cast<size_t>(Tw) * sizeof(TrajMeta) + 15) / 16 * 16;
   LaneOp<real, R, WS, NC, G> op;
   const Terms<real, R, G> T =
       block_setup<real, R, WS, NC, G>(a, smem_raw, team, tm, team_bytes, op);
-  cx<real> *states = reinterpret_cast<cx<real> *>(reinterpret_cast<unsigned char *>(T.base) + tb);
-  TrajMeta *meta = reinterpret_cast<TrajMeta *>(states + static_cast<size_t>(Tw) * R * kL);
+  cx<real> *states =
+      states_in_lds
+          ? reinterpret_cast<cx<real> *>(reinterpret_cast<unsigned char *>(T.base) + tb)
+          : static_cast<cx<real> *>(a.kstates) + static_cast<size_t>(tglob) * Tw * R * kL;
+  TrajMeta *meta = reinterpret_cast<TrajMeta *>(reinterpret_cast<unsigned char *>(T.base) + tb + sb);
+  auto load_state = [&](int t, cx<real>(&p)[R]) {
+    if (states_in_lds) {
+      load_lds(states + static_cast<size_t>(t) * R * kL, p, tm);
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) p[m] = gld(states, static_cast<size_t>(t) * R * kL + tm.gl + kL * m);
+    }
+  };
+  auto store_state = [&](int t, const cx<real>(&p)[R]) {
+    if (states_in_lds) {
+      store_lds(states + static_cast<size_t>(t) * R * kL, p, tm);
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) gst(states, static_cast<size_t>(t) * R * kL + tm.gl + kL * m, p[m]);
+    }
+  };
   cx<real> *v = T[0];  // scratch vector for the update's gathers
   const cx<real> *start = static_cast<const cx<real> *>(a.psi_start);
   if (threadIdx.x == 0) s_abort = 0;
@@ -121,7 +146,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
     cx<real> p[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) p[m] = start[tm.gl + kL * m];
-    store_lds(states + t * R * kL, p, tm);
+    store_state(t, p);
     const double n = norm2(p, tm);
     TrajMeta st;
     st.nrm2 = n;
@@ -226,16 +251,15 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
     for (int t = 0; t < Tw; ++t) {
       const int k = tglob * Tw + t;
       if (k >= a.M) break;
-      cx<real> *sv = states + t * R * kL;
       cx<real> ch[R];
       if (j + 1 < a.nt) load_costate<real, R, G>(a, j + 1, k, tm, ch);
       cx<real> psi[R];
-      load_lds(sv, psi, tm);
+      load_state(t, psi);
       TrajMeta st = meta[t];
       const Stream rng = make_stream(a, k, 0);
       advance_step<real, R, WS, NC, G, 0, true>(op, a, T, psi, st, rng, j, p, k, tm);
       tm.sync();
-      store_lds(sv, psi, tm);
+      store_state(t, psi);
       if (tm.leader()) meta[t] = st;
       if (j + 1 < a.nt) {
         store_lds(v, psi, tm);
@@ -251,13 +275,14 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   for (int t = 0; t < Tw; ++t) {
     const int k = tglob * Tw + t;
     if (k >= a.M) break;
-    const cx<real> *sv = states + t * R * kL;
     const double inv = 1.0 / sqrt(meta[t].nrm2);
+    cx<real> ps[R];
+    load_state(t, ps);
     double tr = 0.0, ti = 0.0;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int row = tm.gl + kL * m;
-      const cx<real> q = sv[row];
+      const cx<real> q = ps[m];
       const double px = q.x * inv, py = q.y * inv;
       const double gx = a.tgt[2 * row], gy = a.tgt[2 * row + 1];
       tr = fma(gx, px, fma(gy, py, tr));
@@ -331,12 +356,13 @@ const Variant *variants(int *count) {
 
 const void *functional_kernel() { return reinterpret_cast<const void *>(&k_functional); }
 
-size_t block_lds_bytes(const Variant &v, int teams, int kbuf, int traj_per_wave) {
+size_t block_lds_bytes(const Variant &v, int teams, int kbuf, int traj_per_wave,
+                       bool states_in_lds) {
   const size_t cplx = v.precision == TK_FP64 ? 16 : 8;
   const size_t ncx = v.NC > 0 ? v.NC : 1;
   const size_t rows = static_cast<size_t>(v.R) * kWave * v.G;
   const size_t per_team = (static_cast<size_t>(kbuf) * (rows + 1) * cplx +
-                           static_cast<size_t>(traj_per_wave) * rows * cplx +
+                           (states_in_lds ? static_cast<size_t>(traj_per_wave) * rows * cplx : 0) +
                            static_cast<size_t>(traj_per_wave) * sizeof(TrajMeta) + 15) / 16 * 16;
   // one-wave teams share a block copy of the control values; G-wave teams read them
   // from global memory

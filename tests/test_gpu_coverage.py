@@ -247,3 +247,41 @@ def test_gradient_d1296_segments_against_central_differences(tk):
     assert abs(J - float(g["J"])) <= 1e-5
     assert max_abs(grad, g["g"]) <= 1e-4 * scale
     assert max_abs(fd_gpu, g["fd"]) <= 1e-4 * scale
+
+
+# ---------------------------------------------------------------------------
+# Krotov pass with its states in global memory (more trajectories than LDS holds)
+# ---------------------------------------------------------------------------
+
+def _krotov_run(tk, w, precision, n_iter):
+    with tk.Context(precision=precision) as ctx:
+        ctx.load(w)
+        J, rec, n = ctx.krotov_iterate(w.M, w.seed, n_iter)
+        return J, ctx.get_pulses(), gpu_records(rec), ctx.launch_info()
+
+
+def test_krotov_states_in_global_memory_fp64_against_oracle(tk, monkeypatch):
+    """d = 36, M = 1100 with the states in global memory (forced): the stored
+    oracle values to 1e-10, and the same bits as the LDS form."""
+    g = golden("krotov_chain2_fock2_M1100_nt60")
+    w = config_workload("chain2_fock2", M=1100, nt=60)
+    J0, u0, r0, _ = _krotov_run(tk, w, "fp64", 2)
+    monkeypatch.setenv("TK_KROTOV_STATES", "global")
+    J1, u1, r1, info = _krotov_run(tk, w, "fp64", 2)
+    say("krotov states in global memory d", w.dim, "M", w.M, "launch", info)
+    assert max_abs(J1, g["J"]) <= 1e-10
+    assert max_abs(u1, g["u"][-1]) <= 1e-10
+    compare_records(r1, golden_records(g), 1e-10 * w.dt)
+    assert np.array_equal(J0, J1) and np.array_equal(u0, u1) and r0 == r1
+
+
+def test_krotov_states_in_global_memory_eight_wave_same_bits(tk, monkeypatch):
+    """d = 1296 (eight-wave teams), M = 16: the global-memory form gives the
+    bits of the LDS form."""
+    w = config_workload("chain4_fock2", M=16, nt=20, T=0.25)
+    J0, u0, r0, _ = _krotov_run(tk, w, "fp32", 2)
+    monkeypatch.setenv("TK_KROTOV_STATES", "global")
+    J1, u1, r1, _ = _krotov_run(tk, w, "fp32", 2)
+    say("eight-wave global states: J", J0.tolist(), J1.tolist(), "records", len(r0))
+    assert np.array_equal(J0, J1) and np.array_equal(u0, u1) and r0 == r1
+
