@@ -323,11 +323,6 @@ __device__ __forceinline__ int opaque_lane(int gl) {
   asm volatile("" : "+v"(gl));
   return gl;
 }
-template <typename T>
-__device__ __forceinline__ const T *opaque_lane_ptr(const T *p) {
-  asm volatile("" : "+v"(p));
-  return p;
-}
 
 // ---- per-lane operator slice ------------------------------------------------
 template <typename real, int R, int WS, int NC, int G>
@@ -393,7 +388,7 @@ struct LaneOp {
 
   // cv = u_{c / wc} * cval for the pulse values uj[0 .. NCX) (zero past n_ctrl)
   __device__ void set_pulses(const double (&uj)[NCX], int wc) {
-    const cx<real> *base = opaque_lane_ptr(cval);  // addresses formed here, per call
+    const cx<real> *base = cval + opaque_lane(0);  // addresses formed here, per call
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       // control c / wc (< NC, hence a valid index), by comparisons: the slot
@@ -804,6 +799,7 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     double s = flo / (flo - fhi);
     if (!(s > lo && s < hi)) s = 0.5;
     cx<real> pt[R], dp[R];
+    double s_prev = -1.0, fp_prev = 0.0;
     for (int it = 0; it < 64; ++it) {
       dense_output<real, R, G>(T, Kc, static_cast<real>(s), pt, dp, tm);
       double f = 0.0, g = 0.0;  // ||p||^2 and Re <p|dp/ds>, reduced together
@@ -824,12 +820,24 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
         hi = s;
       if (fabs(f) <= a.ftol * st.r || (hi - lo) <= 4.0 * eps_real) break;
       double sn = s - f / fp;
-      if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
-      if (fabs(sn - s) <= 2.0 * eps_real) {
+      const bool inside = sn > lo && sn < hi;
+      if (!inside) sn = 0.5 * (lo + hi);
+      // A Newton step from s leaves an error of about |f''/(2 f')| (sn - s)^2;
+      // with f'' estimated from the derivatives at the last two points, the
+      // step is taken without evaluating f again once that is below
+      // kRootAccept (of the unit interval).
+      bool accept = fabs(sn - s) <= 2.0 * eps_real;
+      if (!accept && inside && s_prev >= 0.0 && s != s_prev && fp != 0.0) {
+        const double c = fabs((fp - fp_prev) / (s - s_prev)) / (2.0 * fabs(fp));
+        accept = c * (sn - s) * (sn - s) <= kRootAccept;
+      }
+      if (accept) {
         s = sn;
         dense_output<real, R, G>(T, Kc, static_cast<real>(s), pt, dp, tm);
         break;
       }
+      s_prev = s;
+      fp_prev = fp;
       s = sn;
     }
     const double tau = s * tau_rem;

@@ -691,10 +691,11 @@ int run_gram(tk_ctx *c, int M) {
 int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap,
                bool cross = false) {
   if (c->chi_M != M) return fail(c, TK_ESTATE, "no costates stored for this M");
-  const void *kern = cross ? tk::cross_kernel(c->precision, c->var->R, c->var->WS, c->var->NC,
-                                              c->var->G)
-                           : c->var->k_krotov;
-  if (!kern) return fail(c, TK_EUNSUPPORTED, "no cross-trajectory kernel for this variant");
+  const void *kern_lds = cross ? tk::cross_kernel(c->precision, c->var->R, c->var->WS,
+                                                  c->var->NC, c->var->G)
+                               : c->var->k_krotov;
+  if (!kern_lds) return fail(c, TK_EUNSUPPORTED, "no cross-trajectory kernel for this variant");
+  const void *kern = kern_lds;
   // pulses grow during the pass: one spare term vector; the kernel adds
   // substeps if a step would still need more terms
   const int kbuf = plan_kbuf(c, c->u, 1);
@@ -713,6 +714,7 @@ int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap,
   bool in_lds = true;
   for (int pass = force_global ? 1 : 0; pass < (cross ? 1 : 2) && !tw; ++pass) {
     in_lds = pass == 0;
+    kern = in_lds ? kern_lds : c->var->k_krotov_gs;
     for (int t = 1; t <= 64 && !tw; ++t)
       for (int w = c->var->G > 1 ? 1 : tk::kWavesPerBlock; w >= 1; w /= 2) {
         const int b = (M + w * t - 1) / (w * t);

@@ -22,6 +22,9 @@ constexpr int kMaxBlocks = kWave * kPollPerLane;  // blocks of one Krotov launch
 constexpr int kGradCheckpoint = 64;   // steps between forward checkpoints (gradient)
 
 // error bits a kernel may raise (device int, OR-ed)
+// predicted error (fraction of the substep) below which the jump-time Newton
+// iteration takes its last step without evaluating the norm again
+constexpr double kRootAccept = 1e-12;
 constexpr int kErrNoJumpWeight = 1;  // jump with all ||L_l psi||^2 == 0
 constexpr int kErrTaylorOrder = 2;   // step too long for kMaxTaylor terms
 constexpr int kErrSyncTimeout = 4;   // grid-wide step reduction did not complete
@@ -113,9 +116,8 @@ struct PassArgs {
   const double *lam;        // [kMaxCtrl] lambda_i
   unsigned long long *slots;  // [nt][kMaxBlocks][NC] per-block partial sums
   int traj_per_wave;        // trajectories owned by one wave
-  void *kstates;            // null: the Krotov pass keeps its states in LDS; else
-                            // [teams][traj_per_wave][64 G R] states in global memory
-                            // (bulk), for more trajectories than the LDS holds
+  void *kstates;            // Krotov pass with its states in global memory (the
+                            // k_krotov_gs kernels): [teams][traj_per_wave][64 G R] (bulk)
   const void *pmat;         // cross-trajectory update: P_j = (1/M) sum_k |xi_k><xi_k|,
                             // complex128 [nt][d][64 R] (column c, padded rows)
   long long spin_limit;     // polls before a step reduction gives up
@@ -182,6 +184,7 @@ struct Variant {
   const void *k_forward;
   const void *k_backward;
   const void *k_krotov;
+  const void *k_krotov_gs;  // the same with the states in global memory
   const void *k_fill;  // slot initialisation
   const void *k_grad;  // pathwise gradient (replay + reverse sweep)
 };

@@ -80,7 +80,10 @@ __global__ void k_fill_slots(unsigned long long *slots, long long n, int nblk, i
 }
 
 // ---- sequential Krotov forward pass (cooperative launch) ---------------------
-template <typename real, int R, int WS, int NC, int G>
+// GS: the trajectories' states live in global memory (a.kstates), for more
+// trajectories than the LDS holds; a separate instantiation, so that the LDS
+// form keeps its own register allocation.
+template <typename real, int R, int WS, int NC, int G, bool GS>
 __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_krotov(
     PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -100,10 +103,10 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   // LDS per team: term vectors, then Tw state vectors, then Tw bookkeeping
   // (the states and their bookkeeping live in global memory instead when
   // a.kstates is set: more trajectories per team than the LDS holds)
-  // (the state vectors live in global memory instead when a.kstates is set:
-  // more trajectories per team than the LDS holds; each lane reads back only
-  // the rows it wrote)
-  const bool states_in_lds = a.kstates == nullptr;
+  // (the state vectors live in global memory instead with GS: more
+  // trajectories per team than the LDS holds; each lane reads back only the
+  // rows it wrote)
+  constexpr bool states_in_lds = !GS;
   const size_t tb = terms_bytes<real, R, G>(a.kbuf);
   const size_t sb = states_in_lds ? static_cast<size_t>(Tw) * R * kL * sizeof(cx<real>) : 0;
   // (rounded to 16 bytes: every team's vectors keep the alignment of cx<real>)
@@ -111,25 +114,27 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   LaneOp<real, R, WS, NC, G> op;
   const Terms<real, R, G> T =
       block_setup<real, R, WS, NC, G>(a, smem_raw, team, tm, team_bytes, op);
-  cx<real> *states =
-      states_in_lds
-          ? reinterpret_cast<cx<real> *>(reinterpret_cast<unsigned char *>(T.base) + tb)
-          : static_cast<cx<real> *>(a.kstates) + static_cast<size_t>(tglob) * Tw * R * kL;
+  cx<real> *states_lds =
+      reinterpret_cast<cx<real> *>(reinterpret_cast<unsigned char *>(T.base) + tb);
+  cx<real> *states_glb =
+      GS ? static_cast<cx<real> *>(a.kstates) + static_cast<size_t>(tglob) * Tw * R * kL : nullptr;
   TrajMeta *meta = reinterpret_cast<TrajMeta *>(reinterpret_cast<unsigned char *>(T.base) + tb + sb);
   auto load_state = [&](int t, cx<real>(&p)[R]) {
-    if (states_in_lds) {
-      load_lds(states + static_cast<size_t>(t) * R * kL, p, tm);
+    if constexpr (states_in_lds) {
+      load_lds(states_lds + static_cast<size_t>(t) * R * kL, p, tm);
     } else {
 #pragma unroll
-      for (int m = 0; m < R; ++m) p[m] = gld(states, static_cast<size_t>(t) * R * kL + tm.gl + kL * m);
+      for (int m = 0; m < R; ++m)
+        p[m] = gld(states_glb, static_cast<size_t>(t) * R * kL + tm.gl + kL * m);
     }
   };
   auto store_state = [&](int t, const cx<real>(&p)[R]) {
-    if (states_in_lds) {
-      store_lds(states + static_cast<size_t>(t) * R * kL, p, tm);
+    if constexpr (states_in_lds) {
+      store_lds(states_lds + static_cast<size_t>(t) * R * kL, p, tm);
     } else {
 #pragma unroll
-      for (int m = 0; m < R; ++m) gst(states, static_cast<size_t>(t) * R * kL + tm.gl + kL * m, p[m]);
+      for (int m = 0; m < R; ++m)
+        gst(states_glb, static_cast<size_t>(t) * R * kL + tm.gl + kL * m, p[m]);
     }
   };
   cx<real> *v = T[0];  // scratch vector for the update's gathers
@@ -326,7 +331,8 @@ Variant make_variant(const char *name) {
   v.G = G;
   v.k_forward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, G, 0>);
   v.k_backward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, G, 1>);
-  v.k_krotov = reinterpret_cast<const void *>(&k_krotov<real, R, WS, NC, G>);
+  v.k_krotov = reinterpret_cast<const void *>(&k_krotov<real, R, WS, NC, G, false>);
+  v.k_krotov_gs = reinterpret_cast<const void *>(&k_krotov<real, R, WS, NC, G, true>);
   v.k_fill = reinterpret_cast<const void *>(&k_fill_slots);
   v.k_grad = grad_kernel(v.precision, R, WS, NC, G);
   return v;

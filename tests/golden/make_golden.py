@@ -14,9 +14,9 @@ d = 1296), so the GPU tests load the results instead of recomputing them:
   than one cooperative launch holds one to a wave), nt = 60 on T = 50.
 * ``krotov_chain3_fock2_M1100_nt40``: d = 216, M = 1100, nt = 40 on T = 2,
   with the guess pass's overlaps and final states of sampled trajectories.
-* ``krotov_chain4_fock2_M1100_nt8``: four nodes (d = 1296), M = 1100 (more
-  trajectories than the eight-wave Krotov pass holds in LDS), nt = 8 on
-  T = 0.1, one Krotov iteration.
+* ``krotov_chain4_fock2_M1100_nt80``: four nodes (d = 1296), M = 1100 (more
+  trajectories than the eight-wave Krotov pass holds in LDS), nt = 80 on
+  T = 10, lambda = 0.05, one Krotov iteration.
 * ``cross_chain2_fock2_M1100_nt60``: the same d = 36 case with the
   cross-trajectory update of Sec. 2.3 (eq. cross_traj_update): J_T and pulses.
 * ``batch_seed0_inst1_2``: instances 1 and 2 (d = 36) of the eight-instance
@@ -105,9 +105,9 @@ def case_krotov_chain3_fock2_M1100_nt40():
                      keep_guess_states=[0, 1, 517, 1098, 1099])
 
 
-def case_krotov_chain4_fock2_M1100_nt8():
+def case_krotov_chain4_fock2_M1100_nt80():
     from workloads import config_workload
-    return _optimise(config_workload("chain4_fock2", M=1100, nt=8, T=0.1), 1)
+    return _optimise(config_workload("chain4_fock2", M=1100, nt=80, T=10.0, lam=0.05), 1)
 
 
 def case_cross_chain2_fock2_M1100_nt60():

@@ -285,3 +285,22 @@ def test_krotov_states_in_global_memory_eight_wave_same_bits(tk, monkeypatch):
     say("eight-wave global states: J", J0.tolist(), J1.tolist(), "records", len(r0))
     assert np.array_equal(J0, J1) and np.array_equal(u0, u1) and r0 == r1
 
+
+
+def test_krotov_d1296_more_trajectories_than_lds_holds(tk):
+    """d = 1296, M = 1100 (the LDS form holds about a thousand): one Krotov
+    iteration against the stored oracle values (FP32 bars; the pulse update is
+    checked relative to its own size)."""
+    g = golden("krotov_chain4_fock2_M1100_nt80")
+    w = config_workload("chain4_fock2", M=1100, nt=80, T=10.0, lam=0.05)
+    J, u, rec, info = _krotov_run(tk, w, "fp32", 1)
+    du_ref = g["u"][-1] - g["u"][0]
+    say("krotov d=1296 M=1100: launch", info, "J gpu", J.tolist(), "oracle", g["J"].tolist(),
+        "records", len(rec), "max |du| oracle", float(np.max(np.abs(du_ref))),
+        "max |u - u_ref|", max_abs(u, g["u"][-1]))
+    assert "G=8" in info["variant"]
+    assert info["traj_per_wave"] * info["blocks"] >= w.M and info["traj_per_wave"] >= 5
+    assert np.max(np.abs(du_ref)) > 1e-4
+    assert max_abs(J, g["J"]) <= 1e-4
+    assert max_abs(u, g["u"][-1]) <= 1e-3 * float(np.max(np.abs(du_ref)))
+    compare_records(rec, golden_records(g), 1e-2 * w.dt)
