@@ -450,7 +450,7 @@ def main() -> int:
     ap.add_argument("--M", type=int, default=None)
     ap.add_argument("--nt", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched FP32 and gradient forms")

@@ -107,7 +107,13 @@ def norm2(psi: np.ndarray) -> float:
 
 @dataclasses.dataclass(frozen=True)
 class Jump:
-    """One quantum jump: trajectory, 0-based step, operator, ordinal, direction, time."""
+    """One quantum jump: trajectory, 0-based step, operator, ordinal, direction, time.
+
+    ``rate`` is a diagnostic beside the record: the relative rate at which the
+    norm falls at the crossing, sum_l ||L_l psi||^2 / ||psi||^2.  A relative
+    error e in the propagated state moves the crossing by about e / rate, so
+    comparisons of jump times use it to scale their bar.
+    """
 
     traj: int
     step: int
@@ -115,6 +121,7 @@ class Jump:
     ordinal: int
     direction: int
     t: float
+    rate: float = float("nan")
 
 
 def jump_time(H_eff, psi: np.ndarray, tau_rem: float, r: float, direction: int) -> float:
@@ -204,8 +211,9 @@ class Ensemble:
                 # MCWF step 4: instantaneous jump with operator l
                 l = choose_operator(psi, self.sys.L_jump, stream.choice(n))
                 elapsed = (dt - tau_rem) + tau
+                rate = sum(norm2(L @ psi) for L in self.sys.L_jump) / norm2(psi)
                 self.records.append(Jump(k, step, l, n, self.direction,
-                                         t_start + sign * elapsed))
+                                         t_start + sign * elapsed, rate))
                 psi = self.sys.L_jump[l] @ psi
                 psi = psi / np.sqrt(norm2(psi))
                 # MCWF step 5: new random number, continue within the step

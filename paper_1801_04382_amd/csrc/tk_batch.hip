@@ -37,12 +37,14 @@
 namespace tk {
 namespace {
 
-// Kernel shapes of the batch, in the order of variants() within a precision.
-#define TK_BATCH_SHAPES(X) \
-  X(0, 1, 4, 2)            \
-  X(1, 2, 4, 2)            \
-  X(2, 4, 6, 3)            \
-  X(3, 4, 8, 4)
+// One-wave kernel shapes of the batch: (index, R, WS layout code, NC).
+#define TK_BATCH_SHAPES(X)   \
+  X(0, 1, 4, 2)              \
+  X(1, 2, 4, 2)              \
+  X(2, 4, 6, 3)              \
+  X(3, 4, 8, 4)              \
+  X(4, 2, ws_code(4, 2), 2)  \
+  X(5, 4, ws_code(6, 4), 3)
 
 // ---- plain passes ------------------------------------------------------------
 template <typename real, int R, int WS, int NC, int DIR>
@@ -399,13 +401,15 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArg
 }
 
 // ---- instances of multi-wave shapes (one G-wave team per block) --------------------
-// Kernel shapes with G > 1, in the order of variants() within a precision
-// (indices continue those of TK_BATCH_SHAPES); the d = 1296 shape exists in
-// FP32 only.
-#define TK_BATCH_WIDE_SHAPES(X) \
-  X(4, 1, 4, 2, 2)              \
-  X(5, 2, 6, 3, 2)
-#define TK_BATCH_WIDE_SHAPES_FP32(X) X(6, 3, 9, 4, 8)
+// Kernel shapes with G > 1 (indices continue those of TK_BATCH_SHAPES); the
+// d = 1296 shapes exist in FP32 only.
+#define TK_BATCH_WIDE_SHAPES(X)  \
+  X(6, 1, 4, 2, 2)               \
+  X(7, 2, 6, 3, 2)               \
+  X(8, 2, ws_code(6, 3), 3, 2)
+#define TK_BATCH_WIDE_SHAPES_FP32(X) \
+  X(9, 3, 9, 4, 8)                   \
+  X(10, 3, ws_code(9, 5), 4, 8)
 
 // Term vectors of the block's team at the start of dynamic LDS, trailing
 // zero elements set.
@@ -770,6 +774,21 @@ __global__ __launch_bounds__(256) void k_batch_finish(BatchArgs b, int copy_puls
 }
 
 }  // namespace
+
+int batch_shape_index(int precision, int R, int wsc, int NC, int G) {
+#define TK_CASE(idx, r, ws, nc) \
+  if (G == 1 && R == r && wsc == (ws) && NC == nc) return idx;
+  TK_BATCH_SHAPES(TK_CASE)
+#undef TK_CASE
+#define TK_CASE(idx, r, ws, nc, g) \
+  if (G == g && R == r && wsc == (ws) && NC == nc) return idx;
+  TK_BATCH_WIDE_SHAPES(TK_CASE)
+  if (precision == TK_FP32) {
+    TK_BATCH_WIDE_SHAPES_FP32(TK_CASE)
+  }
+#undef TK_CASE
+  return -1;
+}
 
 BatchKernels batch_kernels(int precision) {
   BatchKernels k;

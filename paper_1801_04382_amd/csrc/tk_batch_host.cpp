@@ -115,15 +115,7 @@ int bhip(tk_batch *b, hipError_t e, const char *what) {
   } while (0)
 
 int shape_index(const tk::Variant *v) {
-  int nv = 0;
-  const tk::Variant *vs = tk::variants(&nv);
-  int idx = 0;
-  for (int k = 0; k < nv; ++k) {
-    if (vs[k].precision != v->precision) continue;
-    if (&vs[k] == v) return idx;
-    ++idx;
-  }
-  return -1;
+  return tk::batch_shape_index(v->precision, v->R, v->ws_code, v->NC, v->G);
 }
 
 size_t cplx_bytes(int precision) { return precision == TK_FP64 ? 16 : 8; }
@@ -496,7 +488,7 @@ int finalize(tk_batch *b) {
     m.kbuf_fw = plan_kbuf(c, c->u, 1);
     m.kbuf_bw = plan_kbuf(c, c->u, 0);
     // relative cost of one trajectory-step: gathers per Taylor term times terms
-    m.step_cost = static_cast<double>(m.kbuf_fw) * v.R * (v.WS + v.NC);
+    m.step_cost = static_cast<double>(m.kbuf_fw) * (v.WS + (v.R - 1) * v.WSB + v.R * v.NC);
     tk::BatchInstance &I = b->inst[i];
     I.fw = base_args(c, m.M, m.seed, 0, false);
     I.bw = base_args(c, m.M, m.seed, 0, true);
@@ -822,10 +814,8 @@ int tk_batch_add(tk_batch *b, uint32_t instance_id, int64_t d, const tk_csr *H0,
       (rc = tk_set_pulses(m->c, nt, T, u, S, lambda)))
     return bfail(b, rc, std::string("instance: ") + tk_last_error(m->c));
   {
-    const int si = shape_index(m->c->var), G = m->c->var->G;
-    const bool ok = (G == 1 && si >= 0 && si <= 3) || (G == 2 && (si == 4 || si == 5)) ||
-                    (G == 8 && si == 6 && b->precision == TK_FP32);
-    if (!ok) return bfail(b, TK_EUNSUPPORTED, "kernel shape not available in the batched kernels");
+    if (shape_index(m->c->var) < 0)
+      return bfail(b, TK_EUNSUPPORTED, "kernel shape not available in the batched kernels");
   }
   m->id = instance_id;
   m->M = M;

@@ -329,14 +329,17 @@ template <typename real, int R, int WS, int NC, int G>
 struct LaneOp {
   static constexpr int kL = kWave * G;  // lanes of the team
   static constexpr int NCX = NC > 0 ? NC : 1;
-  int scol[WS][R];
-  cx<real> sval[WS][R];
+  static constexpr int W0 = ws_first(WS);  // static slots of row slot 0 (the most)
+  // slot s of row slot m is used (unrolled loops fold this to a constant)
+  static constexpr bool live(int s, int m) { return s < ws_at(WS, m); }
+  int scol[W0][R];
+  cx<real> sval[W0][R];
   int ccol[NCX][R];
   cx<real> cv[NCX][R];   // control matrix elements scaled by the current pulses
   const cx<real> *cval;  // unscaled control elements of this lane, [c][m][team lane]
   // LDS addresses of the gathered elements within term vector 0 (see bind);
   // term n lies n vector lengths further on, a constant offset
-  const cx<real> *sp[WS][R];
+  const cx<real> *sp[W0][R];
   const cx<real> *cp[NCX][R];
 
   // static slots (scol_g, sval_g) and control columns (ccol_g) from global
@@ -347,9 +350,10 @@ struct LaneOp {
     gl = opaque_lane(gl);
     const cx<real> *sv = static_cast<const cx<real> *>(sval_g);
 #pragma unroll
-    for (int s = 0; s < WS; ++s)
+    for (int s = 0; s < W0; ++s)
 #pragma unroll
       for (int m = 0; m < R; ++m) {
+        if (!live(s, m)) continue;
         const int idx = (s * R + m) * kL + gl;
         scol[s][m] = gmem(scol_g)[idx];
         sval[s][m] = gld(sv, idx);
@@ -367,9 +371,10 @@ struct LaneOp {
   // addresses of the lane's gathers in the term vector t0 (once per team)
   __device__ void bind(const cx<real> *t0) {
 #pragma unroll
-    for (int s = 0; s < WS; ++s)
+    for (int s = 0; s < W0; ++s)
 #pragma unroll
-      for (int m = 0; m < R; ++m) sp[s][m] = t0 + scol[s][m];
+      for (int m = 0; m < R; ++m)
+        if (live(s, m)) sp[s][m] = t0 + scol[s][m];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -413,35 +418,37 @@ struct LaneOp {
   // same either way.
   __device__ void apply_at(int shift, cx<real> (&y)[R]) const {
     constexpr bool kHalves = G >= 4;
-    cx<real> b[WS + NC][R];
+    cx<real> b[W0 + NC][R];
 #pragma unroll
-    for (int s = 0; s < WS; ++s)
+    for (int s = 0; s < W0; ++s)
 #pragma unroll
-      for (int m = 0; m < R; ++m) b[s][m] = sp[s][m][shift];
+      for (int m = 0; m < R; ++m)
+        if (live(s, m)) b[s][m] = sp[s][m][shift];
     if constexpr (!kHalves) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int m = 0; m < R; ++m) b[WS + c][m] = cp[c][m][shift];
+        for (int m = 0; m < R; ++m) b[W0 + c][m] = cp[c][m][shift];
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
 #pragma unroll
-    for (int s = 0; s < WS; ++s)
+    for (int s = 0; s < W0; ++s)
 #pragma unroll
-      for (int m = 0; m < R; ++m) cfma(y[m], sval[s][m], b[s][m]);
+      for (int m = 0; m < R; ++m)
+        if (live(s, m)) cfma(y[m], sval[s][m], b[s][m]);
     if constexpr (kHalves) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int m = 0; m < R; ++m) b[WS + c][m] = cp[c][m][shift];
+        for (int m = 0; m < R; ++m) b[W0 + c][m] = cp[c][m][shift];
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int m = 0; m < R; ++m) cfma(y[m], cv[c][m], b[WS + c][m]);
+      for (int m = 0; m < R; ++m) cfma(y[m], cv[c][m], b[W0 + c][m]);
   }
 
 };
@@ -553,19 +560,26 @@ __device__ void taylor(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
 template <typename real, int R, int WS, int NC, int G, int OFF, int S0, int S1>
 __device__ __forceinline__ void gather_fma(const LaneOp<real, R, WS, NC, G> &op, int shift,
                                            cx<real> (&y)[R]) {
+  constexpr int W0 = LaneOp<real, R, WS, NC, G>::W0;
+  using Op = LaneOp<real, R, WS, NC, G>;
   cx<real> b[S1 - S0][R];
 #pragma unroll
   for (int s = S0; s < S1; ++s)
 #pragma unroll
-    for (int m = 0; m < R; ++m)
-      b[s - S0][m] = s < WS ? (op.sp[s < WS ? s : 0][m] + shift)[OFF]
-                            : (op.cp[s < WS ? 0 : s - WS][m] + shift)[OFF];
+    for (int m = 0; m < R; ++m) {
+      if (s < W0 && !Op::live(s, m)) continue;
+      b[s - S0][m] = s < W0 ? (op.sp[s < W0 ? s : 0][m] + shift)[OFF]
+                            : (op.cp[s < W0 ? 0 : s - W0][m] + shift)[OFF];
+    }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int s = S0; s < S1; ++s)
 #pragma unroll
-    for (int m = 0; m < R; ++m)
-      cfma(y[m], s < WS ? op.sval[s < WS ? s : 0][m] : op.cv[s < WS ? 0 : s - WS][m], b[s - S0][m]);
+    for (int m = 0; m < R; ++m) {
+      if (s < W0 && !Op::live(s, m)) continue;
+      cfma(y[m], s < W0 ? op.sval[s < W0 ? s : 0][m] : op.cv[s < W0 ? 0 : s - W0][m],
+           b[s - S0][m]);
+    }
 }
 
 // One term of the series from the term vector at the bound gather addresses
@@ -580,7 +594,7 @@ template <typename real, int R, int WS, int NC, int G, int SGN, int OFF, bool SP
 __device__ __forceinline__ void series_term(const LaneOp<real, R, WS, NC, G> &op, real cf,
                                             cx<real> (&t)[R], cx<real> (&inc)[R],
                                             int shift = 0) {
-  constexpr int NS = WS + NC;
+  constexpr int NS = LaneOp<real, R, WS, NC, G>::W0 + NC;
   constexpr int H = (SPLIT && NS * R > 16) ? (NS + 1) / 2 : NS;
   cx<real> y[R];
 #pragma unroll

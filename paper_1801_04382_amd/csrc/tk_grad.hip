@@ -160,12 +160,13 @@ __device__ __forceinline__ void costate_term(const LaneOp<real, R, WS, NC, G> &o
                                              const cx<real> (&v)[R], cx<real> (&t)[R],
                                              cx<real> (&inc)[R], real (&gp)[NC > 0 ? NC : 1]) {
   constexpr int NCX = NC > 0 ? NC : 1;
-  constexpr int H = (WS + 1) / 2;
+  constexpr int W0 = LaneOp<real, R, WS, NC, G>::W0;
+  constexpr int H = (W0 + 1) / 2;
   cx<real> y[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
   gather_fma<real, R, WS, NC, G, OFF, 0, H>(op, 0, y);
-  if constexpr (H < WS) gather_fma<real, R, WS, NC, G, OFF, H, WS>(op, 0, y);
+  if constexpr (H < W0) gather_fma<real, R, WS, NC, G, OFF, H, W0>(op, 0, y);
   if constexpr (NC > 0) {
     cx<real> b[NC][R];
 #pragma unroll
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(kWave) void k_grad_reduce(const double *gk, int M, 
 
 }  // namespace
 
-const void *grad_kernel(int precision, int R, int WS, int NC, int G) {
+const void *grad_kernel(int precision, int R, int WS, int NC, int G) {  // WS: layout code
 #define TK_GRAD_CASE(real, r, ws, nc, g)                                                   \
   if (precision == (sizeof(real) == 8 ? TK_FP64 : TK_FP32) && R == r && WS == ws && NC == nc && \
       G == g)                                                                               \
@@ -523,6 +524,12 @@ const void *grad_kernel(int precision, int R, int WS, int NC, int G) {
   TK_GRAD_CASE(float, 1, 4, 2, 2)
   TK_GRAD_CASE(float, 2, 6, 3, 2)
   TK_GRAD_CASE(float, 3, 9, 4, 8)
+  TK_GRAD_CASE(double, 2, ws_code(4, 2), 2, 1)
+  TK_GRAD_CASE(double, 2, ws_code(6, 3), 3, 2)
+  TK_GRAD_CASE(float, 2, ws_code(4, 2), 2, 1)
+  TK_GRAD_CASE(float, 4, ws_code(6, 4), 3, 1)
+  TK_GRAD_CASE(float, 2, ws_code(6, 3), 3, 2)
+  TK_GRAD_CASE(float, 3, ws_code(9, 5), 4, 8)
 #undef TK_GRAD_CASE
   return nullptr;
 }

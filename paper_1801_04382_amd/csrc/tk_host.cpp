@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -236,7 +237,10 @@ bool hermitian(const Csr &h) {
 // gathered elements over the LDS bank groups (element c lies in group
 // c mod n_bank_groups), which keeps the gathers of one instruction from
 // colliding in the same banks.
-void pack_group(const Csr *a, int W, int first, int R, int lanes, int n_bank_groups,
+// Row slots m >= 1 use only the first W_rest of the W slots (shapes whose
+// basis order puts the rows with the most non-zeros in row slot 0).  Returns
+// false if a row has more non-zeros than its slots.
+bool pack_group(const Csr *a, int W, int W_rest, int first, int R, int lanes, int n_bank_groups,
                 int32_t dummy, std::vector<int32_t> &col, std::vector<double> &val) {
   std::vector<std::vector<std::pair<int32_t, cd>>> left(static_cast<size_t>(R) * lanes);
   for (int m = 0; m < R; ++m)
@@ -255,7 +259,7 @@ void pack_group(const Csr *a, int W, int first, int R, int lanes, int n_bank_gro
         for (int lane = g0; lane < g0 + 16; ++lane) {
           auto &l = left[static_cast<size_t>(m) * lanes + lane];
           const size_t slot = (static_cast<size_t>(first + w) * R + m) * lanes + lane;
-          if (l.empty()) {
+          if (l.empty() || (m > 0 && w >= W_rest)) {
             col[slot] = dummy;
             val[2 * slot] = val[2 * slot + 1] = 0.0;
             if (!dummy_used) load[dummy % n_bank_groups]++;
@@ -274,34 +278,66 @@ void pack_group(const Csr *a, int W, int first, int R, int lanes, int n_bank_gro
           l.erase(l.begin() + static_cast<long>(best));
         }
       }
+  for (const auto &l : left)
+    if (!l.empty()) return false;
+  return true;
 }
 
 // Operators ops[g], each in W slots: layout [g][w][m][lane], `lanes` lanes
 // (64 G) per row slot m.
-void pack(const std::vector<const Csr *> &ops, int W, int R, int lanes, int n_bank_groups,
-          Ell &out) {
+bool pack(const std::vector<const Csr *> &ops, int W, int R, int lanes, int n_bank_groups,
+          Ell &out, int W_rest = -1) {
   const size_t n = ops.size() * static_cast<size_t>(W) * R * lanes;
   out.col.assign(n, 0);
   out.val.assign(2 * n, 0.0);
   const int32_t dummy = R * lanes;
+  bool ok = true;
   for (size_t g = 0; g < ops.size(); ++g)
-    pack_group(ops[g], W, static_cast<int>(g) * W, R, lanes, n_bank_groups, dummy, out.col,
-               out.val);
+    ok = pack_group(ops[g], W, W_rest < 0 ? W : W_rest, static_cast<int>(g) * W, R, lanes,
+                    n_bank_groups, dummy, out.col, out.val) &&
+         ok;
+  return ok;
 }
 
 // Control operators: slots c = i * wc .. i * wc + wc - 1 hold H_i; slots past
 // n_ctrl * wc are padding.
-void pack_ctrl(const std::vector<Csr> &H, int wc, int NC, int R, int lanes, int n_bank_groups,
+bool pack_ctrl(const std::vector<Csr> &H, int wc, int NC, int R, int lanes, int n_bank_groups,
                Ell &out) {
   const size_t n = static_cast<size_t>(NC) * R * lanes;
   out.col.assign(n, 0);
   out.val.assign(2 * n, 0.0);
   const int32_t dummy = R * lanes;
+  bool ok = true;
   for (int i = 0; i * wc < NC; ++i) {
     const Csr *a = i < static_cast<int>(H.size()) ? &H[i] : nullptr;
-    pack_group(a, std::min(wc, NC - i * wc), i * wc, R, lanes, n_bank_groups, dummy, out.col,
-               out.val);
+    const int w = std::min(wc, NC - i * wc);
+    ok = pack_group(a, w, w, i * wc, R, lanes, n_bank_groups, dummy, out.col, out.val) && ok;
   }
+  return ok;
+}
+
+// Rows and columns of a in device order: device row q is basis row perm[q]
+// (inv is the inverse map).
+Csr permute(const Csr &a, const std::vector<int32_t> &perm, const std::vector<int32_t> &inv) {
+  Csr out;
+  out.n = a.n;
+  out.ptr.push_back(0);
+  std::vector<std::pair<int32_t, cd>> row;
+  for (int64_t q = 0; q < a.n; ++q) {
+    const int64_t r = perm[q];
+    row.clear();
+    for (int64_t p = a.ptr[r]; p < a.ptr[r + 1]; ++p) row.push_back({inv[a.idx[p]], a.val[p]});
+    std::sort(row.begin(), row.end(),
+              [](const std::pair<int32_t, cd> &x, const std::pair<int32_t, cd> &y) {
+                return x.first < y.first;
+              });
+    for (const auto &e : row) {
+      out.idx.push_back(e.first);
+      out.val.push_back(e.second);
+    }
+    out.ptr.push_back(static_cast<int64_t>(out.idx.size()));
+  }
+  return out;
 }
 
 }  // namespace
@@ -557,6 +593,37 @@ void to_host_cplx(const tk_ctx *c, const void *dev_copy, size_t n, double *out) 
   }
 }
 
+// n_states states of d complex values each, from the device basis order back
+// to the basis order (in place)
+void states_to_basis(const tk_ctx *c, double *x, size_t n_states) {
+  if (c->perm.empty()) return;
+  const size_t d = static_cast<size_t>(c->d);
+  std::vector<double> tmp(2 * d);
+  for (size_t k = 0; k < n_states; ++k) {
+    double *v = x + 2 * d * k;
+    std::copy(v, v + 2 * d, tmp.begin());
+    for (size_t q = 0; q < d; ++q) {
+      v[2 * static_cast<size_t>(c->perm[q])] = tmp[2 * q];
+      v[2 * static_cast<size_t>(c->perm[q]) + 1] = tmp[2 * q + 1];
+    }
+  }
+}
+
+// the same from the basis order to the device order
+void states_to_device(const tk_ctx *c, double *x, size_t n_states) {
+  if (c->perm.empty()) return;
+  const size_t d = static_cast<size_t>(c->d);
+  std::vector<double> tmp(2 * d);
+  for (size_t k = 0; k < n_states; ++k) {
+    double *v = x + 2 * d * k;
+    std::copy(v, v + 2 * d, tmp.begin());
+    for (size_t q = 0; q < d; ++q) {
+      v[2 * q] = tmp[2 * static_cast<size_t>(c->perm[q])];
+      v[2 * q + 1] = tmp[2 * static_cast<size_t>(c->perm[q]) + 1];
+    }
+  }
+}
+
 struct TimedLaunch {
   tk_ctx *c;
   int kind;
@@ -691,7 +758,7 @@ int run_gram(tk_ctx *c, int M) {
 int run_krotov(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, int64_t cap,
                bool cross = false) {
   if (c->chi_M != M) return fail(c, TK_ESTATE, "no costates stored for this M");
-  const void *kern_lds = cross ? tk::cross_kernel(c->precision, c->var->R, c->var->WS,
+  const void *kern_lds = cross ? tk::cross_kernel(c->precision, c->var->R, c->var->ws_code,
                                                   c->var->NC, c->var->G)
                                : c->var->k_krotov;
   if (!kern_lds) return fail(c, TK_EUNSUPPORTED, "no cross-trajectory kernel for this variant");
@@ -1161,11 +1228,24 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   // static part of H_eff: A = H0 - (i/2) sum_l L_l^+ L_l
   Csr A = h0;
   for (int l = 0; l < n_jump; ++l) A = axpy(A, cd(0.0, -0.5), multiply(adjoint(lj[l]), lj[l]));
-  const Csr Ad = adjoint(A);
+  Csr Ad = adjoint(A);
   std::vector<Csr> hcd(n_ctrl);
   for (int i = 0; i < n_ctrl; ++i) hcd[i] = adjoint(hc[i]);
 
   const int ws = std::max(A.max_row(), Ad.max_row());
+  // static non-zeros of each basis row in the forward or the costate operator,
+  // and the basis in decreasing order of them (stable): shapes with fewer
+  // static slots in row slots m >= 1 take the first 64 G rows of this order
+  // as row slot 0
+  std::vector<int> cnt(static_cast<size_t>(d));
+  for (int64_t r = 0; r < d; ++r)
+    cnt[r] = static_cast<int>(std::max(A.ptr[r + 1] - A.ptr[r], Ad.ptr[r + 1] - Ad.ptr[r]));
+  std::vector<int32_t> order(static_cast<size_t>(d));
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return cnt[x] > cnt[y]; });
+  // the most static non-zeros of a row outside the first `lanes` rows of the order
+  auto rest_width = [&](int64_t lanes) { return d > lanes ? cnt[order[lanes]] : 0; };
   int wc = 1;
   for (int i = 0; i < n_ctrl; ++i) wc = std::max({wc, hc[i].max_row(), hcd[i].max_row()});
   int wl = 1, wld = 1;
@@ -1178,7 +1258,7 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   const int nc = n_ctrl * wc;
   // the compiled variant with the fewest rows 64 G R >= d; among those, FP64
   // shapes with 4 rows per lane come last (they spill registers), then one-wave
-  // teams, then the narrowest slots.
+  // teams, then the fewest static slots per lane, then the narrowest.
   // TK_VARIANT=<name> picks one by name instead.
   const char *want = std::getenv("TK_VARIANT");
   int nv = 0;
@@ -1186,12 +1266,12 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   const tk::Variant *best = nullptr;
   auto key = [](const tk::Variant &v) {
     const int spills = v.precision == TK_FP64 && v.R >= 4 ? 1 : 0;
-    return std::make_tuple(v.R * v.G, spills, v.G, v.WS, v.NC);
+    return std::make_tuple(v.R * v.G, spills, v.G, v.WS + (v.R - 1) * v.WSB, v.WS, v.NC);
   };
   for (int k = 0; k < nv; ++k) {
     const tk::Variant &v = vs[k];
     if (v.precision != c->precision || static_cast<int64_t>(v.R) * tk::kWave * v.G < d ||
-        v.WS < ws || v.NC < nc)
+        v.WS < ws || v.NC < nc || (v.R > 1 && v.WSB < rest_width(int64_t{tk::kWave} * v.G)))
       continue;
     if (want && *want) {
       if (std::strcmp(want, v.name) == 0) best = &v;
@@ -1204,6 +1284,31 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
                 "no compiled kernel variant for d=" + std::to_string(d) + " static width " +
                     std::to_string(ws) + " control slots " + std::to_string(nc) +
                     (want && *want ? std::string(" named ") + want : std::string()));
+  // norm bounds of the step plan, from the operators in the basis order (the
+  // estimate's start vector is fixed in that order)
+  const double b0 = norm2_estimate(A);
+  double bc[tk::kMaxCtrl];
+  for (int i = 0; i < tk::kMaxCtrl; ++i) bc[i] = i < n_ctrl ? norm2_estimate(hc[i]) : 0.0;
+  // device basis order: the order above for shapes with fewer static slots in
+  // row slots m >= 1, else the basis itself; operators and states are
+  // permuted once here and in tk_set_states, states going out are put back
+  c->perm.clear();
+  c->inv_perm.clear();
+  if (best->WSB < best->WS) {
+    c->perm = order;
+    c->inv_perm.assign(static_cast<size_t>(d), 0);
+    for (int64_t q = 0; q < d; ++q) c->inv_perm[order[q]] = static_cast<int32_t>(q);
+    A = permute(A, c->perm, c->inv_perm);
+    Ad = permute(Ad, c->perm, c->inv_perm);
+    for (int i = 0; i < n_ctrl; ++i) {
+      hc[i] = permute(hc[i], c->perm, c->inv_perm);
+      hcd[i] = permute(hcd[i], c->perm, c->inv_perm);
+    }
+    for (int l = 0; l < n_jump; ++l) {
+      lj[l] = permute(lj[l], c->perm, c->inv_perm);
+      ljd[l] = permute(ljd[l], c->perm, c->inv_perm);
+    }
+  }
   c->var = best;
   c->d = d;
   c->n_ctrl = n_ctrl;
@@ -1221,27 +1326,28 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   // LDS bank groups of one complex element (32 banks of 4 bytes)
   const int nbg = c->precision == TK_FP64 ? 8 : 16;
   Ell e;
-  pack({&A}, best->WS, R, lanes, nbg, e);
+  const char *packing = "a row has more non-zeros than its slots";
+  if (!pack({&A}, best->WS, R, lanes, nbg, e, best->WSB)) return fail(c, TK_EINVAL, packing);
   if ((rc = upload_ell(c, e, c->f_scol, c->f_sval))) return rc;
-  pack({&Ad}, best->WS, R, lanes, nbg, e);
+  if (!pack({&Ad}, best->WS, R, lanes, nbg, e, best->WSB)) return fail(c, TK_EINVAL, packing);
   if ((rc = upload_ell(c, e, c->b_scol, c->b_sval))) return rc;
-  pack_ctrl(hc, wc, best->NC, R, lanes, nbg, e);
+  if (!pack_ctrl(hc, wc, best->NC, R, lanes, nbg, e)) return fail(c, TK_EINVAL, packing);
   if ((rc = upload_ell(c, e, c->f_ccol, c->f_cval))) return rc;
-  pack_ctrl(hcd, wc, best->NC, R, lanes, nbg, e);
+  if (!pack_ctrl(hcd, wc, best->NC, R, lanes, nbg, e)) return fail(c, TK_EINVAL, packing);
   if ((rc = upload_ell(c, e, c->b_ccol, c->b_cval))) return rc;
   std::vector<const Csr *> lp;
   for (int l = 0; l < n_jump; ++l) lp.push_back(&lj[l]);
   if (lp.empty()) lp.push_back(nullptr);
-  pack(lp, wl, R, lanes, nbg, e);
+  if (!pack(lp, wl, R, lanes, nbg, e)) return fail(c, TK_EINVAL, packing);
   if ((rc = upload_ell(c, e, c->lcol, c->lval))) return rc;
   std::vector<const Csr *> ldp;
   for (int l = 0; l < n_jump; ++l) ldp.push_back(&ljd[l]);
   if (ldp.empty()) ldp.push_back(nullptr);
-  pack(ldp, wld, R, lanes, nbg, e);
+  if (!pack(ldp, wld, R, lanes, nbg, e)) return fail(c, TK_EINVAL, packing);
   if ((rc = upload_ell(c, e, c->ldcol, c->ldval))) return rc;
 
-  c->b0 = norm2_estimate(A);
-  for (int i = 0; i < tk::kMaxCtrl; ++i) c->bc[i] = i < n_ctrl ? norm2_estimate(hc[i]) : 0.0;
+  c->b0 = b0;
+  for (int i = 0; i < tk::kMaxCtrl; ++i) c->bc[i] = bc[i];
   // algorithmic non-zeros of H_eff: union of the static and control patterns
   Csr pat = A;
   for (int i = 0; i < n_ctrl; ++i) {
@@ -1274,9 +1380,12 @@ int tk_set_states(tk_ctx *c, const double *psi0, const double *psi_tgt) {
   if (!(nt > 0.0)) return fail(c, TK_EINVAL, "target is zero");
   const double inv = 1.0 / std::sqrt(nt);
   std::vector<double> p(2 * dpad, 0.0), t(2 * dpad, 0.0);
-  for (int64_t i = 0; i < 2 * d; ++i) {
-    p[i] = psi0[i];
-    t[i] = psi_tgt[i] * inv;
+  for (int64_t q = 0; q < d; ++q) {
+    const int64_t r = c->perm.empty() ? q : c->perm[q];  // device row q holds basis row r
+    p[2 * q] = psi0[2 * r];
+    p[2 * q + 1] = psi0[2 * r + 1];
+    t[2 * q] = psi_tgt[2 * r] * inv;
+    t[2 * q + 1] = psi_tgt[2 * r + 1] * inv;
   }
   int rc = upload_vec(c, c->psi0_bulk, p);
   if (rc) return rc;
@@ -1320,6 +1429,7 @@ int tk_propagate_forward(tk_ctx *c, int32_t M, uint64_t seed, uint64_t iteration
     std::vector<unsigned char> buf(static_cast<size_t>(M) * c->d * c->bulk_cplx());
     TK_HIP(c, hipMemcpy(buf.data(), c->psiT.p, buf.size(), hipMemcpyDeviceToHost));
     to_host_cplx(c, buf.data(), static_cast<size_t>(M) * c->d, psiT_out);
+    states_to_basis(c, psiT_out, static_cast<size_t>(M));
   }
   return fetch_records(c, rec, cap, n_rec);
 }
@@ -1358,6 +1468,7 @@ int tk_get_costate(const tk_ctx *cc, int32_t j, double *chi_out) {
   const unsigned char *src = c->chi.as<unsigned char>() + static_cast<size_t>(j) * buf.size();
   TK_HIP(c, hipMemcpy(buf.data(), src, buf.size(), hipMemcpyDeviceToHost));
   to_host_cplx(c, buf.data(), n, chi_out);
+  states_to_basis(c, chi_out, static_cast<size_t>(c->chi_M));
   return TK_OK;
 }
 
@@ -1400,7 +1511,7 @@ int tk_krotov_iterate_cross(tk_ctx *c, int32_t M, uint64_t seed, uint64_t first_
   if (!c) return TK_EINVAL;
   TK_HIP(c, hipSetDevice(c->device));
   if (c->has_system &&
-      !tk::cross_kernel(c->precision, c->var->R, c->var->WS, c->var->NC, c->var->G))
+      !tk::cross_kernel(c->precision, c->var->R, c->var->ws_code, c->var->NC, c->var->G))
     return fail(c, TK_EUNSUPPORTED,
                 "the cross-trajectory update runs one-wave kernel shapes only (d <= 256)");
   return krotov_iterate_impl(c, M, seed, first_iteration, n_iter, J_T_out, false, rec, cap,
@@ -1575,6 +1686,7 @@ int tk_step_bench(tk_ctx *c, int32_t method, int32_t M, int32_t K, const double 
   const size_t cb = c->bulk_cplx();
   {
     std::vector<double> xd(x, x + 2 * n);
+    states_to_device(c, xd.data(), static_cast<size_t>(M));
     int rc;
     if (fp64) {
       rc = upload(c, c->bench_x, xd.data(), 2 * n * sizeof(double));
@@ -1596,7 +1708,8 @@ int tk_step_bench(tk_ctx *c, int32_t method, int32_t M, int32_t K, const double 
   void *yp = c->bench_y.p;
   const void *hp = nullptr;
   if (method == TK_STEP_SPARSE) {
-    kern = tk::sparse_step_kernel(c->precision, c->var->R, c->var->WS, c->var->NC, c->var->G);
+    kern = tk::sparse_step_kernel(c->precision, c->var->R, c->var->ws_code, c->var->NC,
+                                  c->var->G);
     if (!kern) return fail(c, TK_EUNSUPPORTED, "the sparse step runs one-wave kernel shapes only");
     a = base_args(c, M, 0, 0, false);
     a.kbuf = 2;
@@ -1653,6 +1766,7 @@ int tk_step_bench(tk_ctx *c, int32_t method, int32_t M, int32_t K, const double 
     std::vector<unsigned char> buf(n * cb);
     TK_HIP(c, hipMemcpy(buf.data(), c->bench_y.p, n * cb, hipMemcpyDeviceToHost));
     to_host_cplx(c, buf.data(), n, y);
+    states_to_basis(c, y, static_cast<size_t>(M));
   }
   return TK_OK;
 }

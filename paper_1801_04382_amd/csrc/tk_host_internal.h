@@ -93,6 +93,8 @@ struct tk_ctx {
 
   tkh::DevBuf chi, tau, psiT, slots, rec, rec_count, err_dev, jt_dev;
   tkh::DevBuf kstates;  // Krotov-pass states when they do not fit in LDS
+  // device basis order (empty: the basis itself): device row q is basis row perm[q]
+  std::vector<int32_t> perm, inv_perm;
   tkh::DevBuf path_off, path_step, path_t, path_op, ckpt, stash, gk, dJdu;
   tkh::DevBuf noise_u, noise_nu;  // pulse-noise measure
   tkh::DevBuf pmat, ones_tau;      // cross-trajectory update: Gram matrices, unit weights

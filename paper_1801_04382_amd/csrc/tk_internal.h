@@ -22,9 +22,18 @@ constexpr int kMaxBlocks = kWave * kPollPerLane;  // blocks of one Krotov launch
 constexpr int kGradCheckpoint = 64;   // steps between forward checkpoints (gradient)
 
 // error bits a kernel may raise (device int, OR-ed)
+// Static-slot layout of a kernel shape.  The shape parameter WS holds the
+// static slots of row slot 0 in its low four bits and, for shapes whose host
+// orders the basis so that row slot 0 holds the rows with the most non-zeros,
+// the fewer slots of row slots m >= 1 in the bits above (0: the same count).
+constexpr int ws_first(int ws) { return ws & 15; }
+constexpr int ws_rest(int ws) { return (ws >> 4) != 0 ? (ws >> 4) : (ws & 15); }
+constexpr int ws_at(int ws, int m) { return m == 0 ? ws_first(ws) : ws_rest(ws); }
+constexpr int ws_code(int first, int rest) { return first | rest << 4; }
+
 // predicted error (fraction of the substep) below which the jump-time Newton
 // iteration takes its last step without evaluating the norm again
-constexpr double kRootAccept = 1e-12;
+constexpr double kRootAccept = 1e-15;
 constexpr int kErrNoJumpWeight = 1;  // jump with all ||L_l psi||^2 == 0
 constexpr int kErrTaylorOrder = 2;   // step too long for kMaxTaylor terms
 constexpr int kErrSyncTimeout = 4;   // grid-wide step reduction did not complete
@@ -180,7 +189,9 @@ constexpr int kBatchHistory = 64;  // J_T values kept per instance (ring by iter
 struct Variant {
   const char *name;
   int precision;  // TK_FP64 / TK_FP32
-  int R, WS, NC, G;
+  int R, WS, NC, G;  // WS: static slots of row slot 0
+  int WSB;           // static slots of row slots m >= 1 (WSB < WS: heaviest rows first)
+  int ws_code;       // the kernels' WS parameter (ws_first / ws_rest)
   const void *k_forward;
   const void *k_backward;
   const void *k_krotov;
@@ -261,7 +272,10 @@ const void *grad_reduce_kernel();
 // Batched kernels of a precision (defined in tk_batch.hip).  The shape of an
 // instance is selected inside the kernels by BatchInstance::variant, the index
 // of (R, WS, NC) in variants() among those of the same precision.
-constexpr int kBatchShapes = 4;  // one-wave kernel shapes of the batched kernels
+constexpr int kBatchShapes = 6;  // one-wave kernel shapes of the batched kernels
+// Index of a kernel shape among the batched kernels' shapes (one-wave shapes
+// first, < kBatchShapes), or -1 when the batched kernels do not have it.
+int batch_shape_index(int precision, int R, int wsc, int NC, int G);
 struct BatchKernels {
   // one-wave shapes: per shape index
   const void *pass_fw[kBatchShapes], *pass_bw[kBatchShapes], *krotov[kBatchShapes];

@@ -326,7 +326,9 @@ Variant make_variant(const char *name) {
   v.name = name;
   v.precision = sizeof(real) == 8 ? TK_FP64 : TK_FP32;
   v.R = R;
-  v.WS = WS;
+  v.WS = ws_first(WS);
+  v.WSB = ws_rest(WS);
+  v.ws_code = WS;
   v.NC = NC;
   v.G = G;
   v.k_forward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, G, 0>);
@@ -334,7 +336,7 @@ Variant make_variant(const char *name) {
   v.k_krotov = reinterpret_cast<const void *>(&k_krotov<real, R, WS, NC, G, false>);
   v.k_krotov_gs = reinterpret_cast<const void *>(&k_krotov<real, R, WS, NC, G, true>);
   v.k_fill = reinterpret_cast<const void *>(&k_fill_slots);
-  v.k_grad = grad_kernel(v.precision, R, WS, NC, G);
+  v.k_grad = grad_kernel(v.precision, R, WS, NC, G);  // WS: the layout code
   return v;
 }
 
@@ -355,6 +357,13 @@ const Variant *variants(int *count) {
       make_variant<float, 1, 4, 2, 2>("fp32 R=1 WS=4 NC=2 G=2"),
       make_variant<float, 2, 6, 3, 2>("fp32 R=2 WS=6 NC=3 G=2"),
       make_variant<float, 3, 9, 4, 8>("fp32 R=3 WS=9 NC=4 G=8"),
+      // heaviest rows in row slot 0, fewer static slots in the others
+      make_variant<double, 2, ws_code(4, 2), 2, 1>("fp64 R=2 WS=4/2 NC=2"),
+      make_variant<double, 2, ws_code(6, 3), 3, 2>("fp64 R=2 WS=6/3 NC=3 G=2"),
+      make_variant<float, 2, ws_code(4, 2), 2, 1>("fp32 R=2 WS=4/2 NC=2"),
+      make_variant<float, 4, ws_code(6, 4), 3, 1>("fp32 R=4 WS=6/4 NC=3"),
+      make_variant<float, 2, ws_code(6, 3), 3, 2>("fp32 R=2 WS=6/3 NC=3 G=2"),
+      make_variant<float, 3, ws_code(9, 5), 4, 8>("fp32 R=3 WS=9/5 NC=4 G=8"),
   };
   *count = static_cast<int>(sizeof(table) / sizeof(table[0]));
   return table;

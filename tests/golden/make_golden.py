@@ -57,11 +57,15 @@ def _one_thread():
     return threadpool_limits(limits=1)
 
 
-def record_columns(recs, iteration):
-    """Jump records as sorted columns (iteration, direction, traj, ordinal, step, op) + t."""
-    rows = sorted((iteration, r.direction, r.traj, r.ordinal, r.step, r.op, r.t) for r in recs)
+def record_columns(recs, iteration, with_rate=False):
+    """Jump records as sorted columns (iteration, direction, traj, ordinal, step, op) + t
+    (and the relative norm decay rate at each crossing)."""
+    rows = sorted((iteration, r.direction, r.traj, r.ordinal, r.step, r.op, r.t, r.rate)
+                  for r in recs)
     ints = np.array([r[:6] for r in rows], dtype=np.int64).reshape(-1, 6)
     ts = np.array([r[6] for r in rows], dtype=np.float64)
+    if with_rate:
+        return ints, ts, np.array([r[7] for r in rows], dtype=np.float64)
     return ints, ts
 
 
@@ -71,18 +75,21 @@ def _optimise(w, n_iter, keep_guess_states=None):
     sysd = System.from_sparse(w.H0, w.H_ctrl, w.L_jump)
     res = ok.optimise(sysd, w.psi0, w.psi_tgt, w.u0, w.S, w.lam, w.T, w.M, w.seed, n_iter,
                       instance=w.instance)
-    ints, ts = [], []
-    i, t = record_columns(res.passes[0].records, 0)
+    ints, ts, rates = [], [], []
+    i, t, q = record_columns(res.passes[0].records, 0, True)
     ints.append(i)
     ts.append(t)
+    rates.append(q)
     for it in range(1, n_iter + 1):
         for recs in (res.backward_records[it - 1], res.passes[it].records):
-            i, t = record_columns(recs, it)
+            i, t, q = record_columns(recs, it, True)
             ints.append(i)
             ts.append(t)
+            rates.append(q)
     order = np.lexsort(tuple(np.concatenate(ints).T[::-1]))
     out = dict(J=np.array(res.J_T), u=np.array(res.u), rec_int=np.concatenate(ints)[order],
-               rec_t=np.concatenate(ts)[order], tau0=res.passes[0].tau)
+               rec_t=np.concatenate(ts)[order], rec_rate=np.concatenate(rates)[order],
+               tau0=res.passes[0].tau)
     if keep_guess_states is not None:
         out["sample_k"] = np.array(keep_guess_states)
         out["sample_psi"] = res.passes[0].psi_hat_T[keep_guess_states]

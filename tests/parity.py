@@ -37,14 +37,40 @@ def gpu_records(arr, iteration=None, direction=None):
     return sorted(out)
 
 
-def compare_records(gpu, ref, t_tol):
-    """Discrete fields identical; jump times within t_tol.  Returns max |dt|."""
+# relative error the library accepts per FP64 Taylor step (its order table)
+STEP_TOL_FP64 = 1e-15
+
+
+def slow_crossing_allowance(ref_rates, ref_recs, nt, step_tol=STEP_TOL_FP64):
+    """Per-record allowance added to a jump-time bar where the norm falls slowly.
+
+    The library's step propagator is a polynomial whose remainder it keeps
+    below step_tol per step; the oracle's is the exact exponential.  After n
+    steps of a pass the two states differ by up to about n step_tol
+    (relative), and a crossing where the norm falls at relative rate
+    rate = sum_l ||L_l psi||^2 / ||psi||^2 moves by that over the rate.  The
+    allowance is 4 n step_tol / rate (a factor 2 for the pulses, which carry
+    the same error from earlier passes, and 2 of margin); n counts the steps
+    from the start of the record's pass (forward: step + 1; backward:
+    nt - step)."""
+    out = []
+    for r, rate in zip(ref_recs, ref_rates):
+        n = r[4] + 1 if r[1] == 0 else nt - r[4]
+        out.append(4.0 * n * step_tol / rate if rate > 0 else float("inf"))
+    return out
+
+
+def compare_records(gpu, ref, t_tol, allowance=None):
+    """Discrete fields identical; jump times within t_tol (plus the per-record
+    allowance, if given).  Returns max |dt|."""
     assert len(gpu) == len(ref), (len(gpu), len(ref), gpu[:5], ref[:5])
     worst = 0.0
-    for g, o in zip(gpu, ref):
+    for q, (g, o) in enumerate(zip(gpu, ref)):
         assert g[:6] == o[:6], (g, o)
-        worst = max(worst, abs(g[6] - o[6]))
-    assert worst <= t_tol, worst
+        dt = abs(g[6] - o[6])
+        bar = t_tol + (allowance[q] if allowance is not None else 0.0)
+        assert dt <= bar, (g, o, dt, bar)
+        worst = max(worst, dt)
     return worst
 
 

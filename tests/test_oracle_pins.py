@@ -430,6 +430,9 @@ def test_backward_two_jumps_inside_one_step():
         if e2 < T:
             assert [(r.step, r.ordinal, r.direction) for r in recs] == [(0, 0, 1), (0, 1, 1)]
             assert abs(recs[0].t - (T - e1)) < 1e-11 and abs(recs[1].t - (T - e2)) < 1e-10
+            # the norm falls at relative rate sum_l ||L psi||^2 / ||psi||^2 = kappa n:
+            # 2 with two photons, 1 with one (kappa = 1)
+            assert abs(recs[0].rate - 2.0) < 1e-12 and abs(recs[1].rate - 1.0) < 1e-12
             checked += 1
     assert checked >= 8
 
