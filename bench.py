@@ -193,8 +193,8 @@ def cpu_baseline_window(name: str, M_sub: int, n_steps: int) -> dict:
 def bench_batched(n_inst: int, steps: int, nodes, check: int) -> dict:
     """FP32 batched form: n_inst instances of the batching workload in one
     launch; guess pass + one autotuned iteration untimed, then `steps` graph
-    iterations timed.  The first `check` instances with d <= 256 (the FP64
-    kernels stop there) are also optimised alone in FP64 (same seeds and
+    iterations timed.  The first `check` instances with d <= 256 and the
+    cheapest larger one are also optimised alone in FP64 (same seeds and
     streams) for the J_T accuracy of the FP32 form."""
     import numpy as np
     from paper_1801_04382_amd import trajkrotov as tk
@@ -210,7 +210,9 @@ def bench_batched(n_inst: int, steps: int, nodes, check: int) -> dict:
         info = b.info()
     J32 = np.concatenate([J0, J], axis=1)
     dJ, dJ_dims = [], []
-    for i in [q for q in range(n_inst) if ws[q].dim <= 256][:check]:
+    small = [q for q in range(n_inst) if ws[q].dim <= 256][:check]
+    large = sorted((q for q in range(n_inst) if ws[q].dim > 256), key=lambda q: ws[q].M * ws[q].nt)
+    for i in small + large[:1]:
         dJ_dims.append(int(ws[i].dim))
         with tk.Batch(precision="fp64") as b64:
             b64.add(ws[i])

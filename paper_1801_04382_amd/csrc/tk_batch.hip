@@ -402,14 +402,14 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArg
 
 // ---- instances of multi-wave shapes (one G-wave team per block) --------------------
 // Kernel shapes with G > 1 (indices continue those of TK_BATCH_SHAPES); the
-// d = 1296 shapes exist in FP32 only.
+// d = 1296 shape with the same static slots in every row slot exists in FP32
+// only.
 #define TK_BATCH_WIDE_SHAPES(X)  \
   X(6, 1, 4, 2, 2)               \
   X(7, 2, 6, 3, 2)               \
-  X(8, 2, ws_code(6, 3), 3, 2)
-#define TK_BATCH_WIDE_SHAPES_FP32(X) \
-  X(9, 3, 9, 4, 8)                   \
+  X(8, 2, ws_code(6, 3), 3, 2)   \
   X(10, 3, ws_code(9, 5), 4, 8)
+#define TK_BATCH_WIDE_SHAPES_FP32(X) X(9, 3, 9, 4, 8)
 
 // Term vectors of the block's team at the start of dynamic LDS, trailing
 // zero elements set.
@@ -808,6 +808,9 @@ BatchKernels batch_kernels(int precision) {
     k.wpass_fw = reinterpret_cast<const void *>(&k_batch_wide_pass<double, 0, 2>);
     k.wpass_bw = reinterpret_cast<const void *>(&k_batch_wide_pass<double, 1, 2>);
     k.wkrotov = reinterpret_cast<const void *>(&k_batch_wide_krotov<double, 2>);
+    k.wpass_fw8 = reinterpret_cast<const void *>(&k_batch_wide_pass<double, 0, 8>);
+    k.wpass_bw8 = reinterpret_cast<const void *>(&k_batch_wide_pass<double, 1, 8>);
+    k.wkrotov8 = reinterpret_cast<const void *>(&k_batch_wide_krotov<double, 8>);
   } else {
     k.wpass_fw = reinterpret_cast<const void *>(&k_batch_wide_pass<float, 0, 2>);
     k.wpass_bw = reinterpret_cast<const void *>(&k_batch_wide_pass<float, 1, 2>);

@@ -437,7 +437,11 @@ int plan_kbuf(const tk_ctx *c, const std::vector<double> &u, int margin) {
     plan_step_host(c, u, j, &n_sub, &K);
     kmax = std::max(kmax, K);
   }
-  return std::min(kmax + 1 + margin, tk::kMaxTaylor + 1);
+  int kb = std::min(kmax + 1 + margin, tk::kMaxTaylor + 1);
+  // at most what one team's LDS holds: a step that needs more terms is cut
+  // into more substeps by the kernels (FP64 at d = 1296)
+  while (kb > 3 && tk::block_lds_bytes(*c->var, 1, kb, 0) > tk::kLdsBytes) --kb;
+  return kb;
 }
 
 // Term vectors of the gradient's reverse sweep: the kept terms t_0 .. t_Kg of

@@ -364,6 +364,10 @@ const Variant *variants(int *count) {
       make_variant<float, 4, ws_code(6, 4), 3, 1>("fp32 R=4 WS=6/4 NC=3"),
       make_variant<float, 2, ws_code(6, 3), 3, 2>("fp32 R=2 WS=6/3 NC=3 G=2"),
       make_variant<float, 3, ws_code(9, 5), 4, 8>("fp32 R=3 WS=9/5 NC=4 G=8"),
+      // d = 1296 in FP64: one team's LDS holds five FP64 term vectors, so its
+      // steps take substeps short enough for four-term series (several
+      // times the work of the FP32 shape; it serves accuracy checks)
+      make_variant<double, 3, ws_code(9, 5), 4, 8>("fp64 R=3 WS=9/5 NC=4 G=8"),
   };
   *count = static_cast<int>(sizeof(table) / sizeof(table[0]));
   return table;

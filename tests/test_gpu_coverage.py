@@ -359,3 +359,26 @@ def test_reordered_basis_shape_matches_uniform_shape(tk, monkeypatch, name, prec
     t_tol = (1e-10 if precision == "fp64" else 1e-2) * w.T / w.nt
     for ra, rb in ((a[2], b[2]), (a[3], b[3]), (a[7], b[7])):
         compare_records(rb, ra, t_tol)
+
+
+# ---------------------------------------------------------------------------
+# FP64 at d = 1296 (eight-wave teams; substeps short enough for the LDS)
+# ---------------------------------------------------------------------------
+
+def test_fp64_d1296_shape_against_oracle(tk):
+    """The FP64 d = 1296 shape: one Krotov iteration of M = 1100 (states in
+    global memory) against the stored oracle values at the FP64 bars.  Its
+    series hold at most five terms, so its steps take ~20 substeps, each kept
+    to 1e-15: the slow-crossing allowance of the jump times uses 2e-14 per step."""
+    g = golden("krotov_chain4_fock2_M1100_nt80")
+    w = config_workload("chain4_fock2", M=1100, nt=80, T=10.0, lam=0.05)
+    J, u, rec, info = _krotov_run(tk, w, "fp64", 1)
+    say("fp64 d=1296: launch", info, "J gpu", J.tolist(), "oracle", g["J"].tolist(),
+        "max |du|", max_abs(u, g["u"][-1]), "records", len(rec))
+    assert info["variant"] == "fp64 R=3 WS=9/5 NC=4 G=8"
+    assert max_abs(J, g["J"]) <= 1e-10
+    assert max_abs(u, g["u"][-1]) <= 1e-10
+    ref, rates = golden_records(g, with_rate=True)
+    worst = compare_records(rec, ref, 1e-10 * w.dt,
+                            slow_crossing_allowance(rates, ref, w.nt, step_tol=2e-14))
+    say("  max |dt*|", worst)
