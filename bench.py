@@ -26,13 +26,13 @@ PEAK = {"fp64": 78.6, "fp32": 157.3}  # published MI355X vector peaks, TFLOP/s
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
 # each scaled by what the counter reads for a device copy of known size
-# (a 1 GiB copy reads FETCH_SIZE 524300 KiB and WRITE_SIZE 1048576 KiB, hence
+# (a 1 GiB copy reads FETCH_SIZE 524302 KiB and WRITE_SIZE 1048576 KiB, hence
 # factors 2.0 and 1.0).  Keyed by kernel and workload, and valid for the build
 # the counters were taken with (the library's build id, a digest of all its
 # sources and flags); any other build reports null.
 TRAFFIC = {
     ("krotov", "chain2_fock3", "fp64", 1024, 2000): {
-        "build": "abb905daa807508a", "fetch_kib": 1459000, "write_kib": 17370,
+        "build": "1fab80a5a62ac811", "fetch_kib": 1447753, "write_kib": 17370,
         "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
