@@ -650,10 +650,14 @@ __device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const Pass
 // cost of the ping-pong form: terms go in runs of four, each run reading its
 // gathers at the bound addresses moved once by the run's first vector plus
 // constant offsets of 0 .. 3 vector lengths.
-template <typename real, int R, int WS, int NC, int G, int SGN>
+// FT: when use_y1 is set, the first term's product Op in comes ready in *y1
+// (first_term_parts / first_term_finish: the same multiply-adds in the same
+// order as the gathered term), so the first term takes no LDS round trip.
+template <typename real, int R, int WS, int NC, int G, int SGN, bool FT = false>
 __device__ void taylor_keep(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                             const Terms<real, R, G> &T, const cx<real> (&in)[R],
-                            cx<real> (&out)[R], double tau, int K, const Team<G> &tm) {
+                            cx<real> (&out)[R], double tau, int K, const Team<G> &tm,
+                            const cx<real> (*y1)[R] = nullptr, bool use_y1 = false) {
   constexpr int kLen = Terms<real, R, G>::kLen;
   constexpr int kL = Team<G>::kLanes;
   cx<real> t[R], inc[R];
@@ -666,9 +670,23 @@ __device__ void taylor_keep(const LaneOp<real, R, WS, NC, G> &op, const PassArgs
   for (int n0 = 0; n0 < K; n0 += 4) {  // terms n0 + 1 .. n0 + 4 from T[n0 .. n0 + 3]
     const int shift = n0 * kLen;
     cx<real> *own = T.base + shift + tm.gl;
-    tm.sync();
-    series_term<real, R, WS, NC, G, SGN, 0>(op, static_cast<real>(tau * a.inv_n[n0 + 1]), t, inc,
-                                            shift);
+    if (FT && n0 == 0 && use_y1) {
+      const real cf = static_cast<real>(tau * a.inv_n[1]);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const cx<real> y = (*y1)[m];
+        if (SGN < 0)
+          t[m] = cx<real>{cf * y.y, -cf * y.x};
+        else
+          t[m] = cx<real>{-cf * y.y, cf * y.x};
+        inc[m].x += t[m].x;
+        inc[m].y += t[m].y;
+      }
+    } else {
+      tm.sync();
+      series_term<real, R, WS, NC, G, SGN, 0>(op, static_cast<real>(tau * a.inv_n[n0 + 1]), t,
+                                              inc, shift);
+    }
 #pragma unroll
     for (int m = 0; m < R; ++m) own[kLen + kL * m] = t[m];
     if (n0 + 2 > K) break;
@@ -762,11 +780,15 @@ __device__ __forceinline__ void apply_jump(const PassArgs &a, int l, const cx<re
 // vectors (taylor_pingpong, a little cheaper) and a step that ends in a jump
 // evaluates it again keeping the terms.  Passes whose step time is set by the
 // slowest trajectory (the sequential Krotov pass) keep the terms.
-template <typename real, int R, int WS, int NC, int G, int DIR, bool KEEP = false>
+// FT (with KEEP): *y1 is the first series term's product Op psi, formed ahead
+// (taylor_keep); it serves the substep's first series only.
+template <typename real, int R, int WS, int NC, int G, int DIR, bool KEEP = false, bool FT = false>
 __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                         const Terms<real, R, G> &T, cx<real> (&psi)[R], TrajMeta &st,
                         const Stream &rng, int j, double t0, double h, int K, double bnd, int k,
-                        const Team<G> &tm) {
+                        const Team<G> &tm, const cx<real> (*y1)[R] = nullptr,
+                        bool use_y1 = false) {
+  static_assert(!FT || KEEP, "a first term formed ahead needs the kept-term series");
   constexpr int SGN = DIR == 0 ? -1 : 1;
   double tau_rem = h;
   int Kc = K;
@@ -778,7 +800,8 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
   for (int guard = 0;; ++guard) {
     cx<real> out[R];
     if (KEEP)
-      taylor_keep<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, Kc, tm);
+      taylor_keep<real, R, WS, NC, G, SGN, FT>(op, a, T, ps, out, tau_rem, Kc, tm, y1,
+                                                       use_y1 && guard == 0);
     else
       taylor_pingpong<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, Kc, tm);
     const double n_end = norm2(out, tm);
@@ -968,17 +991,21 @@ __device__ __forceinline__ StepPlan plan_step(const PassArgs &a, const double (&
   return p;
 }
 
-// Advance across the whole step j (its substeps).
-template <typename real, int R, int WS, int NC, int G, int DIR, bool KEEP = false>
+// Advance across the whole step j (its substeps).  FT: with use_y1 set, *y1
+// is the first series term's product Op psi of the step's first substep.
+template <typename real, int R, int WS, int NC, int G, int DIR, bool KEEP = false, bool FT = false>
 __device__ __forceinline__ void advance_step(const LaneOp<real, R, WS, NC, G> &op,
                                              const PassArgs &a, const Terms<real, R, G> &T,
                                              cx<real> (&psi)[R], TrajMeta &st,
                                              const Stream &rng, int j, const StepPlan &p,
-                                             int k, const Team<G> &tm) {
+                                             int k, const Team<G> &tm,
+                                             const cx<real> (*y1)[R] = nullptr,
+                                             bool use_y1 = false) {
   for (int s = 0; s < p.n_sub; ++s) {
     const double t0 = DIR == 0 ? static_cast<double>(j) * a.dt + s * p.h
                                : static_cast<double>(j + 1) * a.dt - s * p.h;
-    advance<real, R, WS, NC, G, DIR, KEEP>(op, a, T, psi, st, rng, j, t0, p.h, p.K, p.bnd, k, tm);
+    advance<real, R, WS, NC, G, DIR, KEEP, FT>(op, a, T, psi, st, rng, j, t0, p.h, p.K, p.bnd, k,
+                                               tm, y1, use_y1 && s == 0);
   }
 }
 
@@ -1134,6 +1161,50 @@ __device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC, G> &o
       pc[c] = fma(-inv * static_cast<double>(ch[m].y), hx, pc[c]);
     }
   }
+}
+
+// The parts of the next step's first series term that do not depend on the
+// pulses, from the state in term vector 0 (which the share has just gathered
+// from): ys = the static slots' multiply-adds, in slot order; bc = the control
+// slots' gathered elements.  first_term_finish adds the control slots'
+// multiply-adds once the pulses are known: the same operations in the same
+// order as series_term's gathered term, so the result is the same to the bit.
+template <typename real, int R, int WS, int NC, int G>
+__device__ __forceinline__ void first_term_parts(const LaneOp<real, R, WS, NC, G> &op,
+                                                 cx<real> (&ys)[R],
+                                                 cx<real> (&bc)[NC > 0 ? NC : 1][R]) {
+  using Op = LaneOp<real, R, WS, NC, G>;
+  constexpr int W0 = Op::W0;
+  cx<real> b[W0][R];
+#pragma unroll
+  for (int s = 0; s < W0; ++s)
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      if (Op::live(s, m)) b[s][m] = op.sp[s][m][0];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int m = 0; m < R; ++m) bc[c][m] = op.cp[c][m][0];
+#pragma unroll
+  for (int m = 0; m < R; ++m) ys[m] = cx<real>{0, 0};
+#pragma unroll
+  for (int s = 0; s < W0; ++s)
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      if (Op::live(s, m)) cfma(ys[m], op.sval[s][m], b[s][m]);
+}
+
+template <typename real, int R, int WS, int NC, int G>
+__device__ __forceinline__ void first_term_finish(const LaneOp<real, R, WS, NC, G> &op,
+                                                  const cx<real> (&ys)[R],
+                                                  const cx<real> (&bc)[NC > 0 ? NC : 1][R],
+                                                  cx<real> (&y)[R]) {
+#pragma unroll
+  for (int m = 0; m < R; ++m) y[m] = ys[m];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int m = 0; m < R; ++m) cfma(y[m], op.cv[c][m], bc[c][m]);
 }
 
 // chi_k(t_j), own rows.  Padding rows (row >= d) read row d - 1 instead of a

@@ -178,6 +178,15 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   for (int i = 0; i < NCX; ++i) inv_lm[i] = 1.0 / (a.lam[i] * a.M);
   double u_prev[NCX];  // block 0: the previous step's new pulse, stored with the next publish
   OrderHint khint;     // the previous step's order
+  // One trajectory per team with its state in LDS: the state stays in term
+  // vector 0 from its share to its next step, so the pulse-independent parts
+  // of that step's first series term are formed while the grid exchanges the
+  // step's partials, and the term itself needs no LDS round trip.  Shapes
+  // with more rows per lane or multi-wave teams have no registers to spare
+  // for the parts (they would spill) and take the gathered term.
+  constexpr bool kFT = !GS && G == 1 && R <= 2;
+  const bool use_ft = kFT && Tw == 1;
+  cx<real> ft_ys[R], ft_bc[NCX][R];
   for (int j = 0; j < a.nt; ++j) {
     // pulse inputs of interval j, loaded now and used after the exchange
     double uo[NCX], so[NCX];
@@ -204,6 +213,8 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       // wave waits for its write on its own
       if (blockIdx.x == 0 && j > 0) a.u_new[static_cast<size_t>(i) * a.nt + j - 1] = pick(u_prev, i);
     }
+    if constexpr (kFT)
+      if (use_ft) first_term_parts(op, ft_ys, ft_bc);
     // ---- wait for every block's partial of step j; sum in block order --------
     if (wib == 0 && a.n_ctrl > 0) {
       // every lane reads kPollPerLane blocks' slots in one batch of loads (slots of
@@ -262,7 +273,11 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       load_state(t, psi);
       TrajMeta st = meta[t];
       const Stream rng = make_stream(a, k, 0);
-      advance_step<real, R, WS, NC, G, 0, true>(op, a, T, psi, st, rng, j, p, k, tm);
+      cx<real> y1[R];
+      if constexpr (kFT)
+        if (use_ft) first_term_finish(op, ft_ys, ft_bc, y1);
+      advance_step<real, R, WS, NC, G, 0, true, kFT>(op, a, T, psi, st, rng, j, p, k, tm, &y1,
+                                                      use_ft);
       tm.sync();
       store_state(t, psi);
       if (tm.leader()) meta[t] = st;
