@@ -619,7 +619,8 @@ __device__ __forceinline__ void series_term(const LaneOp<real, R, WS, NC, G> &op
 template <typename real, int R, int WS, int NC, int G, int SGN, bool SPLIT = true>
 __device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                                 const Terms<real, R, G> &T, const cx<real> (&in)[R],
-                                cx<real> (&out)[R], double tau, int K, const Team<G> &tm) {
+                                cx<real> (&out)[R], double tau, int K, const Team<G> &tm,
+                                double *d0 = nullptr) {
   constexpr int kLen = Terms<real, R, G>::kLen;
   constexpr int kL = Team<G>::kLanes;
   cx<real> *own = T.base + tm.gl;
@@ -633,6 +634,7 @@ __device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const Pass
   for (int n = 1; n <= K; n += 2) {
     tm.sync();
     series_term<real, R, WS, NC, G, SGN, 0, SPLIT>(op, static_cast<real>(tau * a.inv_n[n]), t, inc);
+    if (d0 && n == 1) *d0 = re_dot(in, t);
 #pragma unroll
     for (int m = 0; m < R; ++m) own[kLen + kL * m] = t[m];
     if (n + 1 > K) break;
@@ -650,6 +652,18 @@ __device__ void taylor_pingpong(const LaneOp<real, R, WS, NC, G> &op, const Pass
 // cost of the ping-pong form: terms go in runs of four, each run reading its
 // gathers at the bound addresses moved once by the run's first vector plus
 // constant offsets of 0 .. 3 vector lengths.
+// Re <p|q> over the lane's rows (FP64 partial of a team sum)
+template <typename real, int R>
+__device__ __forceinline__ double re_dot(const cx<real> (&p)[R], const cx<real> (&q)[R]) {
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    s = fma(static_cast<double>(p[m].x), static_cast<double>(q[m].x), s);
+    s = fma(static_cast<double>(p[m].y), static_cast<double>(q[m].y), s);
+  }
+  return s;
+}
+
 // FT: when use_y1 is set, the first term's product Op in comes ready in *y1
 // (first_term_parts / first_term_finish: the same multiply-adds in the same
 // order as the gathered term), so the first term takes no LDS round trip.
@@ -657,7 +671,8 @@ template <typename real, int R, int WS, int NC, int G, int SGN, bool FT = false>
 __device__ void taylor_keep(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                             const Terms<real, R, G> &T, const cx<real> (&in)[R],
                             cx<real> (&out)[R], double tau, int K, const Team<G> &tm,
-                            const cx<real> (*y1)[R] = nullptr, bool use_y1 = false) {
+                            double *d0 = nullptr, const cx<real> (*y1)[R] = nullptr,
+                            bool use_y1 = false) {
   constexpr int kLen = Terms<real, R, G>::kLen;
   constexpr int kL = Team<G>::kLanes;
   cx<real> t[R], inc[R];
@@ -687,6 +702,7 @@ __device__ void taylor_keep(const LaneOp<real, R, WS, NC, G> &op, const PassArgs
       series_term<real, R, WS, NC, G, SGN, 0>(op, static_cast<real>(tau * a.inv_n[n0 + 1]), t,
                                               inc, shift);
     }
+    if (d0 && n0 == 0) *d0 = re_dot(in, t);
 #pragma unroll
     for (int m = 0; m < R; ++m) own[kLen + kL * m] = t[m];
     if (n0 + 2 > K) break;
@@ -789,6 +805,9 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                         const Team<G> &tm, const cx<real> (*y1)[R] = nullptr,
                         bool use_y1 = false) {
   static_assert(!FT || KEEP, "a first term formed ahead needs the kept-term series");
+  // (one-wave teams with at most two rows per lane: the others are short of
+  // registers, and there the extra live values cost more than they save)
+  constexpr bool kSlope = G == 1 && R <= 2;
   constexpr int SGN = DIR == 0 ? -1 : 1;
   double tau_rem = h;
   int Kc = K;
@@ -799,11 +818,17 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
   constexpr double eps_real = sizeof(real) == 8 ? 0x1.0p-52 : 0x1.0p-23;
   for (int guard = 0;; ++guard) {
     cx<real> out[R];
+    // g0 = Re <t_0|t_1> over the lane's rows: summed over the team only when
+    // the substep ends below the threshold, it is half the slope of
+    // ||p(s)||^2 at s = 0 for the root search's first point (kSlope shapes;
+    // the others start from the secant).
+    double g0 = 0.0;
+    double *g0p = kSlope ? &g0 : nullptr;
     if (KEEP)
-      taylor_keep<real, R, WS, NC, G, SGN, FT>(op, a, T, ps, out, tau_rem, Kc, tm, y1,
+      taylor_keep<real, R, WS, NC, G, SGN, FT>(op, a, T, ps, out, tau_rem, Kc, tm, g0p, y1,
                                                        use_y1 && guard == 0);
     else
-      taylor_pingpong<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, Kc, tm);
+      taylor_pingpong<real, R, WS, NC, G, SGN>(op, a, T, ps, out, tau_rem, Kc, tm, g0p);
     const double n_end = norm2(out, tm);
     if (!(n_end < st.r)) {
 #pragma unroll
@@ -831,12 +856,31 @@ __device__ void advance(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
     }
     tm.sync();
     double lo = 0.0, hi = 1.0;
-    if (n_s < 0.0) n_s = norm2(ps, tm);
+    if constexpr (kSlope) {
+      if (n_s < 0.0) {
+        n_s = re_dot(ps, ps);
+        tm.sum2(n_s, g0);
+      } else {
+        g0 = tm.sum(g0);
+      }
+    } else {
+      if (n_s < 0.0) n_s = norm2(ps, tm);
+    }
     const double flo = n_s - st.r, fhi = n_end - st.r;
-    double s = flo / (flo - fhi);
+    // first point: the root in (0, 1) of the quadratic through f(0), f'(0)
+    // and f(1) (the crossing of the secant if that fails); the Newton
+    // iteration's curvature estimate starts from the slope at s = 0
+    const double fp0 = 2.0 * g0;
+    double s = -1.0;
+    if constexpr (kSlope) {
+      const double c2 = fhi - flo - fp0;
+      const double disc = fma(fp0, fp0, -4.0 * c2 * flo);
+      s = 2.0 * flo / (-fp0 + sqrt(fmax(disc, 0.0)));
+    }
+    if (!(s > lo && s < hi)) s = flo / (flo - fhi);
     if (!(s > lo && s < hi)) s = 0.5;
     cx<real> pt[R], dp[R];
-    double s_prev = -1.0, fp_prev = 0.0;
+    double s_prev = kSlope ? 0.0 : -1.0, fp_prev = fp0;
     for (int it = 0; it < 64; ++it) {
       dense_output<real, R, G>(T, Kc, static_cast<real>(s), pt, dp, tm);
       double f = 0.0, g = 0.0;  // ||p||^2 and Re <p|dp/ds>, reduced together
