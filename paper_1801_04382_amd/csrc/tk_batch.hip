@@ -43,8 +43,8 @@ namespace {
   X(1, 2, 4, 2)              \
   X(2, 4, 6, 3)              \
   X(3, 4, 8, 4)              \
-  X(4, 2, ws_code(4, 2), 2)  \
-  X(5, 4, ws_code(6, 4), 3)
+  X(4, 2, ws_code(3, 1), 2)  \
+  X(5, 4, ws_code(5, 3), 3)
 
 // ---- plain passes ------------------------------------------------------------
 template <typename real, int R, int WS, int NC, int DIR>
@@ -61,7 +61,7 @@ __device__ void batch_pass_item(const PassArgs &a, int k, uint64_t it, unsigned 
   if (lane < a.kbuf) T[lane][R * kWave] = cx<real>{0, 0};
   wave_sync();
   LaneOp<real, R, WS, NC, 1> op;
-  op.load(a.scol, a.sval, a.ccol, cval_lds, lane);
+  op.load(a.scol, a.sval, a.sdiag, a.ccol, cval_lds, lane);
   op.bind(T[0]);
   pass_trajectory<real, R, WS, NC, 1, DIR>(op, a, T, k, make_stream(a, k, DIR, it), tm);
 }
@@ -401,15 +401,15 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArg
 }
 
 // ---- instances of multi-wave shapes (one G-wave team per block) --------------------
-// Kernel shapes with G > 1 (indices continue those of TK_BATCH_SHAPES); the
-// d = 1296 shape with the same static slots in every row slot exists in FP32
-// only.
+// Kernel shapes with G > 1 (indices continue those of TK_BATCH_SHAPES).  The
+// eight-wave kernels serve the d = 1296 shape with fewer static slots past
+// row slot 0 alone: a second eight-wave shape in the same kernel would set
+// its register allocation and spill both.
 #define TK_BATCH_WIDE_SHAPES(X)  \
   X(6, 1, 4, 2, 2)               \
   X(7, 2, 6, 3, 2)               \
-  X(8, 2, ws_code(6, 3), 3, 2)   \
-  X(10, 3, ws_code(9, 5), 4, 8)
-#define TK_BATCH_WIDE_SHAPES_FP32(X) X(9, 3, 9, 4, 8)
+  X(8, 2, ws_code(5, 2), 3, 2)   \
+  X(10, 3, ws_code(8, 4), 4, 8)
 
 // Term vectors of the block's team at the start of dynamic LDS, trailing
 // zero elements set.
@@ -429,7 +429,7 @@ __device__ void wide_pass_item(const PassArgs &a, int k, uint64_t it, unsigned c
                                const Team<G> &tm) {
   const Terms<real, R, G> T = wide_terms<real, R, G>(smem, a.kbuf, tm);
   LaneOp<real, R, WS, NC, G> op;
-  op.load(a.scol, a.sval, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
+  op.load(a.scol, a.sval, a.sdiag, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
   op.bind(T[0]);
   pass_trajectory<real, R, WS, NC, G, DIR>(op, a, T, k, make_stream(a, k, DIR, it), tm);
 }
@@ -452,13 +452,6 @@ __global__ __launch_bounds__(kWave *G) void k_batch_wide_pass(BatchArgs b) {
     break;
       TK_BATCH_WIDE_SHAPES(TK_CASE)
 #undef TK_CASE
-#define TK_CASE(idx, R, WS, NC, GG)                                                     \
-  case idx:                                                                             \
-    if constexpr (GG == G && sizeof(real) == 4)                                         \
-      wide_pass_item<real, R, WS, NC, G, DIR>(a, k, it, smem_raw, tm);                  \
-    break;
-      TK_BATCH_WIDE_SHAPES_FP32(TK_CASE)
-#undef TK_CASE
       default:
         break;
     }
@@ -480,7 +473,7 @@ __device__ void wide_recompute(const BatchInstance &I, int w, int nteam, int s, 
   const int nt = ab.nt, M = ab.M, d = ab.d;
   const int j0 = s * kSegment, e = min(j0 + kSegment, nt);
   LaneOp<real, R, WS, NC, G> opb;
-  opb.load(ab.scol, ab.sval, ab.ccol, static_cast<const cx<real> *>(ab.cval), tm.gl);
+  opb.load(ab.scol, ab.sval, ab.sdiag, ab.ccol, static_cast<const cx<real> *>(ab.cval), tm.gl);
   opb.bind(T[0]);
   cx<real> *seg = static_cast<cx<real> *>(I.fw.chi);
   const cx<real> *start = static_cast<const cx<real> *>(ab.psi_start);
@@ -592,7 +585,7 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
     const int j0 = s * kSegment, j1 = min(j0 + kSegment, nt);
     wide_recompute<real, R, WS, NC, G>(I, w, nteam, s, it, T, tm);
     LaneOp<real, R, WS, NC, G> op;
-    op.load(a.scol, a.sval, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
+    op.load(a.scol, a.sval, a.sdiag, a.ccol, static_cast<const cx<real> *>(a.cval), tm.gl);
     op.bind(T[0]);
     if (s == 0) {  // start states and their shares at t_0
       for (int k = w; k < M; k += nteam) {
@@ -717,13 +710,6 @@ __global__ __launch_bounds__(kWave *G) void k_batch_wide_krotov(BatchArgs b) {
     break;
     TK_BATCH_WIDE_SHAPES(TK_CASE)
 #undef TK_CASE
-#define TK_CASE(idx, R, WS, NC, GG)                                                          \
-  case idx:                                                                                  \
-    if constexpr (GG == G && sizeof(real) == 4)                                              \
-      wide_krotov_instance<real, R, WS, NC, G>(b, I, lb, it, smem_raw, s_upd, &s_abort, tm); \
-    break;
-    TK_BATCH_WIDE_SHAPES_FP32(TK_CASE)
-#undef TK_CASE
     default:
       break;
   }
@@ -783,9 +769,6 @@ int batch_shape_index(int precision, int R, int wsc, int NC, int G) {
 #define TK_CASE(idx, r, ws, nc, g) \
   if (G == g && R == r && wsc == (ws) && NC == nc) return idx;
   TK_BATCH_WIDE_SHAPES(TK_CASE)
-  if (precision == TK_FP32) {
-    TK_BATCH_WIDE_SHAPES_FP32(TK_CASE)
-  }
 #undef TK_CASE
   return -1;
 }

@@ -333,7 +333,8 @@ struct LaneOp {
   // slot s of row slot m is used (unrolled loops fold this to a constant)
   static constexpr bool live(int s, int m) { return s < ws_at(WS, m); }
   int scol[W0][R];
-  cx<real> sval[W0][R];
+  cx<real> sval[W0][R];  // off-diagonal elements of the static part
+  cx<real> dval[R];      // its diagonal: multiplies the lane's own element, no gather
   int ccol[NCX][R];
   cx<real> cv[NCX][R];   // control matrix elements scaled by the current pulses
   const cx<real> *cval;  // unscaled control elements of this lane, [c][m][team lane]
@@ -342,13 +343,17 @@ struct LaneOp {
   const cx<real> *sp[W0][R];
   const cx<real> *cp[NCX][R];
 
-  // static slots (scol_g, sval_g) and control columns (ccol_g) from global
-  // memory; the unscaled control values stay where cval_src points (LDS or
-  // global memory); gl is the lane within the team
-  __device__ void load(const int *scol_g, const void *sval_g, const int *ccol_g,
-                       const cx<real> *cval_src, int gl) {
+  // static slots (scol_g, sval_g), the static diagonal (sdiag_g, [m][team
+  // lane]) and control columns (ccol_g) from global memory; the unscaled
+  // control values stay where cval_src points (LDS or global memory); gl is
+  // the lane within the team
+  __device__ void load(const int *scol_g, const void *sval_g, const void *sdiag_g,
+                       const int *ccol_g, const cx<real> *cval_src, int gl) {
     gl = opaque_lane(gl);
     const cx<real> *sv = static_cast<const cx<real> *>(sval_g);
+    const cx<real> *sd = static_cast<const cx<real> *>(sdiag_g);
+#pragma unroll
+    for (int m = 0; m < R; ++m) dval[m] = gld(sd, m * kL + gl);
 #pragma unroll
     for (int s = 0; s < W0; ++s)
 #pragma unroll
@@ -412,11 +417,12 @@ struct LaneOp {
   }
 
   // y = Op v for the lane's rows, v the term vector `shift` elements past the
-  // one the gathers are bound to.  All gathers first.
+  // one the gathers are bound to, own = the lane's rows of v.  All gathers
+  // first.
   // Eight-wave shapes (short of registers) gather and multiply the static
   // slots before gathering the control slots; the multiply-add order is the
   // same either way.
-  __device__ void apply_at(int shift, cx<real> (&y)[R]) const {
+  __device__ void apply_at(int shift, const cx<real> (&own)[R], cx<real> (&y)[R]) const {
     constexpr bool kHalves = G >= 4;
     cx<real> b[W0 + NC][R];
 #pragma unroll
@@ -432,7 +438,10 @@ struct LaneOp {
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+    for (int m = 0; m < R; ++m) {
+      y[m] = cx<real>{0, 0};
+      cfma(y[m], dval[m], own[m]);
+    }
 #pragma unroll
     for (int s = 0; s < W0; ++s)
 #pragma unroll
@@ -534,7 +543,7 @@ __device__ void taylor(const LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
   for (int n = 1; n <= K; ++n) {
     tm.sync();
     cx<real> y[R];
-    op.apply_at((n - 1) * Terms<real, R, G>::kLen, y);
+    op.apply_at((n - 1) * Terms<real, R, G>::kLen, t, y);
     const real c = static_cast<real>(tau * a.inv_n[n]);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -598,7 +607,10 @@ __device__ __forceinline__ void series_term(const LaneOp<real, R, WS, NC, G> &op
   constexpr int H = (SPLIT && NS * R > 16) ? (NS + 1) / 2 : NS;
   cx<real> y[R];
 #pragma unroll
-  for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+  for (int m = 0; m < R; ++m) {  // the diagonal first, from t_prev in registers
+    y[m] = cx<real>{0, 0};
+    cfma(y[m], op.dval[m], t[m]);
+  }
   gather_fma<real, R, WS, NC, G, OFF, 0, H>(op, shift, y);
   if constexpr (H < NS) gather_fma<real, R, WS, NC, G, OFF, H, NS>(op, shift, y);
 #pragma unroll
@@ -1079,7 +1091,7 @@ __device__ __forceinline__ Terms<real, R, G> block_setup(const PassArgs &a, unsi
   T.base = reinterpret_cast<cx<real> *>(smem + cval_bytes + static_cast<size_t>(team) * team_bytes);
   if (tm.gl < a.kbuf) T[tm.gl][R * kL] = cx<real>{0, 0};
   __syncthreads();
-  op.load(a.scol, a.sval, a.ccol, cval_src, tm.gl);
+  op.load(a.scol, a.sval, a.sdiag, a.ccol, cval_src, tm.gl);
   op.bind(T[0]);
   return T;
 }
@@ -1209,13 +1221,14 @@ __device__ __forceinline__ void krotov_share(const LaneOp<real, R, WS, NC, G> &o
 
 // The parts of the next step's first series term that do not depend on the
 // pulses, from the state in term vector 0 (which the share has just gathered
-// from): ys = the static slots' multiply-adds, in slot order; bc = the control
+// from; own = the lane's rows of it): ys = the diagonal's and the static
+// slots' multiply-adds, in slot order; bc = the control
 // slots' gathered elements.  first_term_finish adds the control slots'
 // multiply-adds once the pulses are known: the same operations in the same
 // order as series_term's gathered term, so the result is the same to the bit.
 template <typename real, int R, int WS, int NC, int G>
 __device__ __forceinline__ void first_term_parts(const LaneOp<real, R, WS, NC, G> &op,
-                                                 cx<real> (&ys)[R],
+                                                 const cx<real> (&own)[R], cx<real> (&ys)[R],
                                                  cx<real> (&bc)[NC > 0 ? NC : 1][R]) {
   using Op = LaneOp<real, R, WS, NC, G>;
   constexpr int W0 = Op::W0;
@@ -1230,7 +1243,10 @@ __device__ __forceinline__ void first_term_parts(const LaneOp<real, R, WS, NC, G
 #pragma unroll
     for (int m = 0; m < R; ++m) bc[c][m] = op.cp[c][m][0];
 #pragma unroll
-  for (int m = 0; m < R; ++m) ys[m] = cx<real>{0, 0};
+  for (int m = 0; m < R; ++m) {
+    ys[m] = cx<real>{0, 0};
+    cfma(ys[m], op.dval[m], own[m]);
+  }
 #pragma unroll
   for (int s = 0; s < W0; ++s)
 #pragma unroll

@@ -164,7 +164,10 @@ __device__ __forceinline__ void costate_term(const LaneOp<real, R, WS, NC, G> &o
   constexpr int H = (W0 + 1) / 2;
   cx<real> y[R];
 #pragma unroll
-  for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
+  for (int m = 0; m < R; ++m) {  // the diagonal first, from t_m in registers
+    y[m] = cx<real>{0, 0};
+    cfma(y[m], op.dval[m], t[m]);
+  }
   gather_fma<real, R, WS, NC, G, OFF, 0, H>(op, 0, y);
   if constexpr (H < W0) gather_fma<real, R, WS, NC, G, OFF, H, W0>(op, 0, y);
   if constexpr (NC > 0) {
@@ -256,7 +259,8 @@ template <typename real, int R, int WS, int NC, int G>
 __device__ __forceinline__ void load_forward(LaneOp<real, R, WS, NC, G> &op, const PassArgs &a,
                                              const cx<real> *t0,
                                              const double (&uj)[NC > 0 ? NC : 1], int gl) {
-  op.load(opaque(a.scol), opaque(static_cast<const cx<real> *>(a.sval)), opaque(a.ccol),
+  op.load(opaque(a.scol), opaque(static_cast<const cx<real> *>(a.sval)),
+          opaque(static_cast<const cx<real> *>(a.sdiag)), opaque(a.ccol),
           opaque(static_cast<const cx<real> *>(a.cval)), gl);
   op.bind(t0);
   op.set_pulses(uj, a.wc);
@@ -269,7 +273,8 @@ __device__ __forceinline__ void load_costate(LaneOp<real, R, WS, NC, G> &op, con
   double ones[NCX];
 #pragma unroll
   for (int i = 0; i < NCX; ++i) ones[i] = 1.0;
-  op.load(opaque(a.a_scol), opaque(static_cast<const cx<real> *>(a.a_sval)), opaque(a.a_ccol),
+  op.load(opaque(a.a_scol), opaque(static_cast<const cx<real> *>(a.a_sval)),
+          opaque(static_cast<const cx<real> *>(a.a_sdiag)), opaque(a.a_ccol),
           opaque(static_cast<const cx<real> *>(a.a_cval)), gl);
   op.bind(t0);
   op.set_pulses(ones, a.wc);
@@ -524,12 +529,12 @@ const void *grad_kernel(int precision, int R, int WS, int NC, int G) {  // WS: l
   TK_GRAD_CASE(float, 1, 4, 2, 2)
   TK_GRAD_CASE(float, 2, 6, 3, 2)
   TK_GRAD_CASE(float, 3, 9, 4, 8)
-  TK_GRAD_CASE(double, 2, ws_code(4, 2), 2, 1)
-  TK_GRAD_CASE(double, 2, ws_code(6, 3), 3, 2)
-  TK_GRAD_CASE(float, 2, ws_code(4, 2), 2, 1)
-  TK_GRAD_CASE(float, 4, ws_code(6, 4), 3, 1)
-  TK_GRAD_CASE(float, 2, ws_code(6, 3), 3, 2)
-  TK_GRAD_CASE(float, 3, ws_code(9, 5), 4, 8)
+  TK_GRAD_CASE(double, 2, ws_code(3, 1), 2, 1)
+  TK_GRAD_CASE(double, 2, ws_code(5, 2), 3, 2)
+  TK_GRAD_CASE(float, 2, ws_code(3, 1), 2, 1)
+  TK_GRAD_CASE(float, 4, ws_code(5, 3), 3, 1)
+  TK_GRAD_CASE(float, 2, ws_code(5, 2), 3, 2)
+  TK_GRAD_CASE(float, 3, ws_code(8, 4), 4, 8)
 #undef TK_GRAD_CASE
   return nullptr;
 }

@@ -340,6 +340,26 @@ Csr permute(const Csr &a, const std::vector<int32_t> &perm, const std::vector<in
   return out;
 }
 
+// a without its diagonal; the diagonal goes to diag (length a.n)
+Csr off_diagonal(const Csr &a, std::vector<cd> &diag) {
+  Csr out;
+  out.n = a.n;
+  out.ptr.push_back(0);
+  diag.assign(static_cast<size_t>(a.n), cd(0.0, 0.0));
+  for (int64_t r = 0; r < a.n; ++r) {
+    for (int64_t p = a.ptr[r]; p < a.ptr[r + 1]; ++p) {
+      if (a.idx[p] == r) {
+        diag[static_cast<size_t>(r)] = a.val[p];
+      } else {
+        out.idx.push_back(a.idx[p]);
+        out.val.push_back(a.val[p]);
+      }
+    }
+    out.ptr.push_back(static_cast<int64_t>(out.idx.size()));
+  }
+  return out;
+}
+
 }  // namespace
 
 namespace tkh {
@@ -514,12 +534,14 @@ tk::PassArgs base_args(tk_ctx *c, int M, uint64_t seed, uint64_t iteration, bool
   if (!backward) {
     a.scol = c->f_scol.as<int>();
     a.sval = c->f_sval.p;
+    a.sdiag = c->f_sdiag.p;
     a.ccol = c->f_ccol.as<int>();
     a.cval = c->f_cval.p;
     a.psi_start = c->psi0_bulk.p;
   } else {
     a.scol = c->b_scol.as<int>();
     a.sval = c->b_sval.p;
+    a.sdiag = c->b_sdiag.p;
     a.ccol = c->b_ccol.as<int>();
     a.cval = c->b_cval.p;
     a.psi_start = c->tgt_bulk.p;
@@ -943,6 +965,7 @@ int run_grad(tk_ctx *c, int M, const tk_jump *rec, int64_t n_rec) {
   a.tau_out = c->tau.as<double>();
   a.a_scol = c->b_scol.as<int>();
   a.a_sval = c->b_sval.p;
+  a.a_sdiag = c->b_sdiag.p;
   a.a_ccol = c->b_ccol.as<int>();
   a.a_cval = c->b_cval.p;
   a.ldcol = c->ldcol.as<int>();
@@ -1236,14 +1259,19 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   std::vector<Csr> hcd(n_ctrl);
   for (int i = 0; i < n_ctrl; ++i) hcd[i] = adjoint(hc[i]);
 
-  const int ws = std::max(A.max_row(), Ad.max_row());
-  // static non-zeros of each basis row in the forward or the costate operator,
-  // and the basis in decreasing order of them (stable): shapes with fewer
-  // static slots in row slots m >= 1 take the first 64 G rows of this order
-  // as row slot 0
+  // the static slots hold the off-diagonal elements (the diagonal multiplies
+  // the lane's own element, with no gather)
+  std::vector<cd> diag_unused;
+  const Csr Aoff0 = off_diagonal(A, diag_unused), Adoff0 = off_diagonal(Ad, diag_unused);
+  const int ws = std::max(Aoff0.max_row(), Adoff0.max_row());
+  // static off-diagonal non-zeros of each basis row in the forward or the
+  // costate operator, and the basis in decreasing order of them (stable):
+  // shapes with fewer static slots in row slots m >= 1 take the first 64 G
+  // rows of this order as row slot 0
   std::vector<int> cnt(static_cast<size_t>(d));
   for (int64_t r = 0; r < d; ++r)
-    cnt[r] = static_cast<int>(std::max(A.ptr[r + 1] - A.ptr[r], Ad.ptr[r + 1] - Ad.ptr[r]));
+    cnt[r] = static_cast<int>(
+        std::max(Aoff0.ptr[r + 1] - Aoff0.ptr[r], Adoff0.ptr[r + 1] - Adoff0.ptr[r]));
   std::vector<int32_t> order(static_cast<size_t>(d));
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
@@ -1331,10 +1359,26 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   const int nbg = c->precision == TK_FP64 ? 8 : 16;
   Ell e;
   const char *packing = "a row has more non-zeros than its slots";
-  if (!pack({&A}, best->WS, R, lanes, nbg, e, best->WSB)) return fail(c, TK_EINVAL, packing);
-  if ((rc = upload_ell(c, e, c->f_scol, c->f_sval))) return rc;
-  if (!pack({&Ad}, best->WS, R, lanes, nbg, e, best->WSB)) return fail(c, TK_EINVAL, packing);
-  if ((rc = upload_ell(c, e, c->b_scol, c->b_sval))) return rc;
+  {
+    // static parts in device order: off-diagonal slots and the diagonal
+    std::vector<cd> dg, ddg;
+    const Csr Aoff = off_diagonal(A, dg), Adoff = off_diagonal(Ad, ddg);
+    if (!pack({&Aoff}, best->WS, R, lanes, nbg, e, best->WSB)) return fail(c, TK_EINVAL, packing);
+    if ((rc = upload_ell(c, e, c->f_scol, c->f_sval))) return rc;
+    if (!pack({&Adoff}, best->WS, R, lanes, nbg, e, best->WSB)) return fail(c, TK_EINVAL, packing);
+    if ((rc = upload_ell(c, e, c->b_scol, c->b_sval))) return rc;
+    std::vector<double> v(2 * static_cast<size_t>(R) * lanes, 0.0);
+    for (int64_t q = 0; q < d; ++q) {
+      v[2 * q] = dg[q].real();
+      v[2 * q + 1] = dg[q].imag();
+    }
+    if ((rc = upload_vec(c, c->f_sdiag, v))) return rc;
+    for (int64_t q = 0; q < d; ++q) {
+      v[2 * q] = ddg[q].real();
+      v[2 * q + 1] = ddg[q].imag();
+    }
+    if ((rc = upload_vec(c, c->b_sdiag, v))) return rc;
+  }
   if (!pack_ctrl(hc, wc, best->NC, R, lanes, nbg, e)) return fail(c, TK_EINVAL, packing);
   if ((rc = upload_ell(c, e, c->f_ccol, c->f_cval))) return rc;
   if (!pack_ctrl(hcd, wc, best->NC, R, lanes, nbg, e)) return fail(c, TK_EINVAL, packing);

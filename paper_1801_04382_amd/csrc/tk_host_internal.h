@@ -82,6 +82,7 @@ struct tk_ctx {
   std::vector<tkh::Csr> L_host;  // jump operators
 
   tkh::DevBuf f_scol, f_sval, f_ccol, f_cval, b_scol, b_sval, b_ccol, b_cval, lcol, lval;
+  tkh::DevBuf f_sdiag, b_sdiag;  // diagonals of the static parts, [m][team lane]
   tkh::DevBuf ldcol, ldval;  // L_l^+ (pathwise gradient)
   int wld = 1;
   tkh::DevBuf psi0_bulk, tgt_bulk, tgt64;

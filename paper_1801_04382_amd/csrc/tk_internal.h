@@ -91,7 +91,8 @@ struct PassArgs {
   double ord_x[kMaxTaylor + 1];
   // operator used by the pass: H_eff pieces (forward) or their adjoints
   const int *scol;
-  const void *sval;
+  const void *sval;   // static part's off-diagonal elements
+  const void *sdiag;  // static part's diagonal, [m][team lane] (zero on padding rows)
   const int *ccol;
   const void *cval;
   // jump operators [l][w][m][lane]
@@ -133,6 +134,7 @@ struct PassArgs {
   // pathwise gradient with the jump record fixed
   const int *a_scol;        // adjoint operator H_eff^+: static slots
   const void *a_sval;
+  const void *a_sdiag;      // and its diagonal
   const int *a_ccol;        // adjoint control slots (H_i^+ = H_i)
   const void *a_cval;
   const int *ldcol;         // adjoint jump operators L_l^+ [l][w][m][lane]
@@ -281,7 +283,6 @@ struct BatchKernels {
   const void *pass_fw[kBatchShapes], *pass_bw[kBatchShapes], *krotov[kBatchShapes];
   const void *fill, *functional, *finish;
   // multi-wave shapes, one team per block: two-wave teams, and eight-wave teams
-  // (FP32 only; null in FP64)
   const void *wpass_fw, *wpass_bw, *wkrotov;
   const void *wpass_fw8 = nullptr, *wpass_bw8 = nullptr, *wkrotov8 = nullptr;
 };

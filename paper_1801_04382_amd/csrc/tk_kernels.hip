@@ -214,7 +214,11 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
       if (blockIdx.x == 0 && j > 0) a.u_new[static_cast<size_t>(i) * a.nt + j - 1] = pick(u_prev, i);
     }
     if constexpr (kFT)
-      if (use_ft) first_term_parts(op, ft_ys, ft_bc);
+      if (use_ft) {
+        cx<real> own[R];
+        load_lds(T[0], own, tm);
+        first_term_parts(op, own, ft_ys, ft_bc);
+      }
     // ---- wait for every block's partial of step j; sum in block order --------
     if (wib == 0 && a.n_ctrl > 0) {
       // every lane reads kPollPerLane blocks' slots in one batch of loads (slots of
@@ -373,16 +377,16 @@ const Variant *variants(int *count) {
       make_variant<float, 2, 6, 3, 2>("fp32 R=2 WS=6 NC=3 G=2"),
       make_variant<float, 3, 9, 4, 8>("fp32 R=3 WS=9 NC=4 G=8"),
       // heaviest rows in row slot 0, fewer static slots in the others
-      make_variant<double, 2, ws_code(4, 2), 2, 1>("fp64 R=2 WS=4/2 NC=2"),
-      make_variant<double, 2, ws_code(6, 3), 3, 2>("fp64 R=2 WS=6/3 NC=3 G=2"),
-      make_variant<float, 2, ws_code(4, 2), 2, 1>("fp32 R=2 WS=4/2 NC=2"),
-      make_variant<float, 4, ws_code(6, 4), 3, 1>("fp32 R=4 WS=6/4 NC=3"),
-      make_variant<float, 2, ws_code(6, 3), 3, 2>("fp32 R=2 WS=6/3 NC=3 G=2"),
-      make_variant<float, 3, ws_code(9, 5), 4, 8>("fp32 R=3 WS=9/5 NC=4 G=8"),
+      make_variant<double, 2, ws_code(3, 1), 2, 1>("fp64 R=2 WS=3/1 NC=2"),
+      make_variant<double, 2, ws_code(5, 2), 3, 2>("fp64 R=2 WS=5/2 NC=3 G=2"),
+      make_variant<float, 2, ws_code(3, 1), 2, 1>("fp32 R=2 WS=3/1 NC=2"),
+      make_variant<float, 4, ws_code(5, 3), 3, 1>("fp32 R=4 WS=5/3 NC=3"),
+      make_variant<float, 2, ws_code(5, 2), 3, 2>("fp32 R=2 WS=5/2 NC=3 G=2"),
+      make_variant<float, 3, ws_code(8, 4), 4, 8>("fp32 R=3 WS=8/4 NC=4 G=8"),
       // d = 1296 in FP64: one team's LDS holds five FP64 term vectors, so its
       // steps take substeps short enough for four-term series (several
       // times the work of the FP32 shape; it serves accuracy checks)
-      make_variant<double, 3, ws_code(9, 5), 4, 8>("fp64 R=3 WS=9/5 NC=4 G=8"),
+      make_variant<double, 3, ws_code(8, 4), 4, 8>("fp64 R=3 WS=8/4 NC=4 G=8"),
   };
   *count = static_cast<int>(sizeof(table) / sizeof(table[0]));
   return table;

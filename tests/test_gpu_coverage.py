@@ -146,7 +146,7 @@ def test_fp32_four_rows_per_lane_shape_d216(tk):
     say("fp32 d=216 M", w.M, "nt", w.nt)
     with tk.Context(precision="fp32") as ctx:
         ctx.load(w)
-        assert ctx.launch_info()["variant"] == "fp32 R=4 WS=6/4 NC=3"
+        assert ctx.launch_info()["variant"] == "fp32 R=4 WS=5/3 NC=3"
         psiT, tau, rec, n = ctx.propagate_forward(w.M, w.seed, 0)
         worst = compare_records(gpu_records(rec), golden_records(g, 0, 0), 1e-2 * dt)
         assert max_abs(psiT[g["sample_k"]], g["sample_psi"]) <= 1e-5
@@ -323,9 +323,9 @@ def test_krotov_d1296_more_trajectories_than_lds_holds(tk):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("name,precision,uniform,light", [
-    ("chain2_fock3", "fp64", "fp64 R=2 WS=4 NC=2", "fp64 R=2 WS=4/2 NC=2"),
-    ("chain3_fock2", "fp32", "fp32 R=4 WS=6 NC=3", "fp32 R=4 WS=6/4 NC=3"),
-    ("chain4_fock2", "fp32", "fp32 R=3 WS=9 NC=4 G=8", "fp32 R=3 WS=9/5 NC=4 G=8"),
+    ("chain2_fock3", "fp64", "fp64 R=2 WS=4 NC=2", "fp64 R=2 WS=3/1 NC=2"),
+    ("chain3_fock2", "fp32", "fp32 R=4 WS=6 NC=3", "fp32 R=4 WS=5/3 NC=3"),
+    ("chain4_fock2", "fp32", "fp32 R=3 WS=9 NC=4 G=8", "fp32 R=3 WS=8/4 NC=4 G=8"),
 ])
 def test_reordered_basis_shape_matches_uniform_shape(tk, monkeypatch, name, precision, uniform,
                                                      light):
@@ -375,7 +375,7 @@ def test_fp64_d1296_shape_against_oracle(tk):
     J, u, rec, info = _krotov_run(tk, w, "fp64", 1)
     say("fp64 d=1296: launch", info, "J gpu", J.tolist(), "oracle", g["J"].tolist(),
         "max |du|", max_abs(u, g["u"][-1]), "records", len(rec))
-    assert info["variant"] == "fp64 R=3 WS=9/5 NC=4 G=8"
+    assert info["variant"] == "fp64 R=3 WS=8/4 NC=4 G=8"
     assert max_abs(J, g["J"]) <= 1e-10
     assert max_abs(u, g["u"][-1]) <= 1e-10
     ref, rates = golden_records(g, with_rate=True)

@@ -108,7 +108,7 @@ def test_two_wave_shape_selected_for_d216_fp64(tk):
     g_ref = gradient_adjoint(sysd, w.psi0, w.psi_tgt, w.u0, w.T, paths)
     with tk.Context(precision="fp64") as ctx:
         ctx.load(w)
-        assert ctx.launch_info()["variant"] == "fp64 R=2 WS=6/3 NC=3 G=2"
+        assert ctx.launch_info()["variant"] == "fp64 R=2 WS=5/2 NC=3 G=2"
         psiT, tau, rec, n = ctx.propagate_forward(w.M, w.seed, 0)
         compare_records(gpu_records(rec), oracle_records(fw.records, 0), t_tol(w))
         assert max_abs(psiT, fw.psi_hat_T) <= TOL
