@@ -783,12 +783,30 @@ __device__ void apply_packed(const int *lcol, const void *lval, int wl, int l,
   const cx<real> *lv = static_cast<const cx<real> *>(lval);
 #pragma unroll
   for (int m = 0; m < R; ++m) y[m] = cx<real>{0, 0};
-  for (int w = 0; w < wl; ++w)
+  // two slots at a time: both slots' global loads, then both gathers, then
+  // the multiply-adds in slot order (one global round trip per pair)
+  for (int w0 = 0; w0 < wl; w0 += 2) {
+    const bool two = w0 + 1 < wl;  // uniform
+    int col[2][R];
+    cx<real> val[2][R], b[2][R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const int idx = ((l * wl + w) * R + m) * Team<G>::kLanes + tm.gl;
-      cfma(y[m], gld(lv, idx), v[gmem(lcol)[idx]]);
-    }
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int idx = ((l * wl + (two ? w0 + q : w0)) * R + m) * Team<G>::kLanes + tm.gl;
+        col[q][m] = gmem(lcol)[idx];
+        val[q][m] = gld(lv, idx);
+      }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int m = 0; m < R; ++m) b[q][m] = v[col[q][m]];
+#pragma unroll
+    for (int m = 0; m < R; ++m) cfma(y[m], val[0][m], b[0][m]);
+    if (two)
+#pragma unroll
+      for (int m = 0; m < R; ++m) cfma(y[m], val[1][m], b[1][m]);
+  }
 }
 
 // y = L_l p for the jump operators of the pass
