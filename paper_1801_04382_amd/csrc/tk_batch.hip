@@ -437,7 +437,7 @@ __device__ void wide_pass_item(const PassArgs &a, int k, uint64_t it, unsigned c
 template <typename real, int DIR, int G>
 __global__ __launch_bounds__(kWave *G) void k_batch_wide_pass(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double team_red[4 * G];
+  __shared__ double team_red[8 * G];
   const Team<G> tm = make_team<G>(team_red);
   const uint64_t it = *b.iteration;
   for (int q = blockIdx.x; q < b.n_witems; q += gridDim.x) {
@@ -646,7 +646,8 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
         TrajMeta st = gld(meta_g, k);
         if (j + 1 < nt) load_seg_costate<real, R, G>(a, j + 1 - j0, k, tm, ch);
         const Stream rng = make_stream(a, k, 0, it);
-        tm.sync();  // the previous trajectory's reads of the term vectors are done
+        // (the previous trajectory's reads of the term vectors ended before
+        // the team sums that close its share or its advance)
         advance_step<real, R, WS, NC, G, 0, true>(op, a, T, psi, st, rng, j, p, k, tm);
 #pragma unroll
         for (int m = 0; m < R; ++m) gst(psi_g, static_cast<size_t>(k) * kRows + tm.gl + kL * m, psi[m]);
@@ -655,7 +656,8 @@ __device__ void wide_krotov_instance(const BatchArgs &b, const BatchInstance &I,
           double pc[NCX];
 #pragma unroll
           for (int c = 0; c < NCX; ++c) pc[c] = 0.0;
-          tm.sync();
+          // the advance ended with a team sum, after every read of the term
+          // vectors, so term vector 0 is free
           store_lds(T[0], psi, tm);
           tm.sync();
           krotov_share<real, R, WS, NC, G>(op, ch, 1.0 / sqrt(st.nrm2), pc);
@@ -692,7 +694,7 @@ __global__ __launch_bounds__(kWave *G) void k_batch_wide_krotov(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double s_upd[kMaxCtrl];
   __shared__ int s_abort;
-  __shared__ double team_red[4 * G];
+  __shared__ double team_red[8 * G];
   const Team<G> tm = make_team<G>(team_red);
   if (threadIdx.x == 0) {
     s_abort = 0;

@@ -170,7 +170,7 @@ struct Team {
   int gl;            // lane within the team
   int lane;          // lane within the wave
   int g;             // wave within the team
-  double *red;       // LDS [2][2 G] (G > 1)
+  double *red;       // LDS [2][4 G] (G > 1)
   mutable int par;   // half of red the next sum writes
   __device__ __forceinline__ void sync() const {
     if (G == 1)
@@ -181,7 +181,7 @@ struct Team {
   __device__ __forceinline__ double sum(double x) const {
     x = wave_sum(x);
     if (G == 1) return x;
-    double *r = red + par * 2 * G;
+    double *r = red + par * 4 * G;
     if (lane == 0) r[g] = x;
     block_sync_lds();
     double s = 0.0;
@@ -194,7 +194,7 @@ struct Team {
   __device__ __forceinline__ void sum2(double &x, double &y) const {
     wave_sum2(x, y);
     if (G == 1) return;
-    double *r = red + par * 2 * G;
+    double *r = red + par * 4 * G;
     if (lane == 0) {
       r[g] = x;
       r[G + g] = y;
@@ -210,12 +210,32 @@ struct Team {
     x = sx;
     y = sy;
   }
-  // the first N entries of v summed over the team, two at a time
+  // the first N entries of v summed over the team: wave sums two at a time,
+  // then up to four values per exchange between the waves (each value with
+  // the bits sum() gives it)
   template <int N, int L>
   __device__ __forceinline__ void sum_n(double (&v)[L]) const {
+    wave_sum_n<N>(v);
+    if (G == 1) return;
 #pragma unroll
-    for (int c = 0; c + 1 < N; c += 2) sum2(v[c], v[c + 1]);
-    if (N % 2) v[N - 1] = sum(v[N - 1]);
+    for (int c0 = 0; c0 < N; c0 += 4) {
+      constexpr int kQ = 4;
+      double *r = red + par * 4 * G;
+      if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+          if (c0 + q < N) r[q * G + g] = v[c0 + q];
+      block_sync_lds();
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        if (c0 + q >= N) break;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < G; ++w) s += r[q * G + w];
+        v[c0 + q] = s;
+      }
+      par ^= 1;
+    }
   }
   __device__ __forceinline__ bool leader() const { return gl == 0; }
 };

@@ -303,7 +303,7 @@ template <typename real, int R, int WS, int NC, int G>
 __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_grad(
     PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double team_red[4 * G];
+  __shared__ double team_red[8 * G];
   constexpr int NCX = NC > 0 ? NC : 1;
   constexpr int kL = Team<G>::kLanes;
   constexpr int kLen = Terms<real, R, G>::kLen;

@@ -55,7 +55,7 @@ template <typename real, int R, int WS, int NC, int G, int DIR>
 __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) void k_pass(
     PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double team_red[4 * G];
+  __shared__ double team_red[8 * G];
   constexpr int kL = Team<G>::kLanes;
   const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / kL);
   const int tpb = blockDim.x / kL;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kWave *(G > kWavesPerBlock ? G : kWavesPerBlock)) v
   __shared__ double wpart[kWavesPerBlock][NCX];
   __shared__ double s_upd[NCX];
   __shared__ int s_abort;
-  __shared__ double team_red[4 * G];
+  __shared__ double team_red[8 * G];
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / kL);
