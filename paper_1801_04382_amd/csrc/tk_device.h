@@ -329,6 +329,17 @@ __device__ __forceinline__ void cfma(cx<real> &y, const cx<real> &a, const cx<re
   y.y = fma(a.y, b.x, y.y);
 }
 
+// y += a b for a control element a; RC: a is real (a.y is zero), two FMAs
+template <bool RC, typename real>
+__device__ __forceinline__ void cfma_ctrl(cx<real> &y, const cx<real> &a, const cx<real> &b) {
+  if constexpr (RC) {
+    y.x = fma(a.x, b.x, y.x);
+    y.y = fma(a.x, b.y, y.y);
+  } else {
+    cfma(y, a, b);
+  }
+}
+
 // Values the compiler cannot follow across this point.  A load whose address
 // derives from one stays where it is written: the compiler neither hoists it
 // out of an enclosing loop nor keeps its 64-bit address in registers from an
@@ -350,6 +361,7 @@ struct LaneOp {
   static constexpr int kL = kWave * G;  // lanes of the team
   static constexpr int NCX = NC > 0 ? NC : 1;
   static constexpr int W0 = ws_first(WS);  // static slots of row slot 0 (the most)
+  static constexpr bool RC = ws_real_ctrl(WS);  // real control elements
   // slot s of row slot m is used (unrolled loops fold this to a constant)
   static constexpr bool live(int s, int m) { return s < ws_at(WS, m); }
   int scol[W0][R];
@@ -477,7 +489,7 @@ struct LaneOp {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int m = 0; m < R; ++m) cfma(y[m], cv[c][m], b[W0 + c][m]);
+      for (int m = 0; m < R; ++m) cfma_ctrl<RC>(y[m], cv[c][m], b[W0 + c][m]);
   }
 
 };
@@ -606,8 +618,10 @@ __device__ __forceinline__ void gather_fma(const LaneOp<real, R, WS, NC, G> &op,
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       if (s < W0 && !Op::live(s, m)) continue;
-      cfma(y[m], s < W0 ? op.sval[s < W0 ? s : 0][m] : op.cv[s < W0 ? 0 : s - W0][m],
-           b[s - S0][m]);
+      if (s < W0)
+        cfma(y[m], op.sval[s < W0 ? s : 0][m], b[s - S0][m]);
+      else
+        cfma_ctrl<Op::RC>(y[m], op.cv[s < W0 ? 0 : s - W0][m], b[s - S0][m]);
     }
 }
 
@@ -1302,7 +1316,8 @@ __device__ __forceinline__ void first_term_finish(const LaneOp<real, R, WS, NC, 
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int m = 0; m < R; ++m) cfma(y[m], op.cv[c][m], bc[c][m]);
+    for (int m = 0; m < R; ++m)
+      cfma_ctrl<LaneOp<real, R, WS, NC, G>::RC>(y[m], op.cv[c][m], bc[c][m]);
 }
 
 // chi_k(t_j), own rows.  Padding rows (row >= d) read row d - 1 instead of a

@@ -183,7 +183,11 @@ __device__ __forceinline__ void costate_term(const LaneOp<real, R, WS, NC, G> &o
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         const cx<real> q = op.cv[c][m];
-        const cx<real> pr{q.x * b[c][m].x - q.y * b[c][m].y, q.x * b[c][m].y + q.y * b[c][m].x};
+        // (real control elements: q.y is zero)
+        const cx<real> pr = LaneOp<real, R, WS, NC, G>::RC
+                                ? cx<real>{q.x * b[c][m].x, q.x * b[c][m].y}
+                                : cx<real>{q.x * b[c][m].x - q.y * b[c][m].y,
+                                           q.x * b[c][m].y + q.y * b[c][m].x};
         y[m] = cx<real>{fma(us[c], pr.x, y[m].x), fma(us[c], pr.y, y[m].y)};
         const real im = pr.x * v[m].y - pr.y * v[m].x;  // Im(conj(pr) v)
 #pragma unroll
@@ -529,12 +533,12 @@ const void *grad_kernel(int precision, int R, int WS, int NC, int G) {  // WS: l
   TK_GRAD_CASE(float, 1, 4, 2, 2)
   TK_GRAD_CASE(float, 2, 6, 3, 2)
   TK_GRAD_CASE(float, 3, 9, 4, 8)
-  TK_GRAD_CASE(double, 2, ws_code(3, 1), 2, 1)
-  TK_GRAD_CASE(double, 2, ws_code(5, 2), 3, 2)
-  TK_GRAD_CASE(float, 2, ws_code(3, 1), 2, 1)
-  TK_GRAD_CASE(float, 4, ws_code(5, 3), 3, 1)
-  TK_GRAD_CASE(float, 2, ws_code(5, 2), 3, 2)
-  TK_GRAD_CASE(float, 3, ws_code(8, 4), 4, 8)
+  TK_GRAD_CASE(double, 2, ws_code(3, 1, true), 2, 1)
+  TK_GRAD_CASE(double, 2, ws_code(5, 2, true), 3, 2)
+  TK_GRAD_CASE(float, 2, ws_code(3, 1, true), 2, 1)
+  TK_GRAD_CASE(float, 4, ws_code(5, 3, true), 3, 1)
+  TK_GRAD_CASE(float, 2, ws_code(5, 2, true), 3, 2)
+  TK_GRAD_CASE(float, 3, ws_code(8, 4, true), 4, 8)
 #undef TK_GRAD_CASE
   return nullptr;
 }

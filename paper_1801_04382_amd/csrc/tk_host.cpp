@@ -1288,6 +1288,11 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
     wld = std::max(wld, ljd[l].max_row());
   }
   const int nc = n_ctrl * wc;
+  // shapes for real control elements (two-FMA control slots) need every H_i
+  // element real
+  bool ctrl_real = true;
+  for (int i = 0; i < n_ctrl; ++i)
+    for (const cd &v : hc[i].val) ctrl_real = ctrl_real && v.imag() == 0.0;
   // the compiled variant with the fewest rows 64 G R >= d; among those, FP64
   // shapes with 4 rows per lane come last (they spill registers), then one-wave
   // teams, then the fewest static slots per lane, then the narrowest.
@@ -1303,7 +1308,8 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
   for (int k = 0; k < nv; ++k) {
     const tk::Variant &v = vs[k];
     if (v.precision != c->precision || static_cast<int64_t>(v.R) * tk::kWave * v.G < d ||
-        v.WS < ws || v.NC < nc || (v.R > 1 && v.WSB < rest_width(int64_t{tk::kWave} * v.G)))
+        v.WS < ws || v.NC < nc || (v.R > 1 && v.WSB < rest_width(int64_t{tk::kWave} * v.G)) ||
+        (v.real_ctrl && !ctrl_real))
       continue;
     if (want && *want) {
       if (std::strcmp(want, v.name) == 0) best = &v;

@@ -22,14 +22,22 @@ constexpr int kMaxBlocks = kWave * kPollPerLane;  // blocks of one Krotov launch
 constexpr int kGradCheckpoint = 64;   // steps between forward checkpoints (gradient)
 
 // error bits a kernel may raise (device int, OR-ed)
-// Static-slot layout of a kernel shape.  The shape parameter WS holds the
-// static slots of row slot 0 in its low four bits and, for shapes whose host
-// orders the basis so that row slot 0 holds the rows with the most non-zeros,
-// the fewer slots of row slots m >= 1 in the bits above (0: the same count).
+// Static-slot layout of a kernel shape (slots for the off-diagonal elements of
+// the static part).  The shape parameter WS holds the static slots of row slot
+// 0 in its low four bits and, for shapes whose host orders the basis so that
+// row slot 0 holds the rows with the most off-diagonal non-zeros, the fewer
+// slots of row slots m >= 1 in the bits above (0: the same count).
+// Bit 8 marks shapes for real control elements: their control slots multiply
+// with two FMAs instead of four (the host picks them only when every H_i
+// element is real).
+constexpr int kRealCtrlBit = 1 << 8;
 constexpr int ws_first(int ws) { return ws & 15; }
-constexpr int ws_rest(int ws) { return (ws >> 4) != 0 ? (ws >> 4) : (ws & 15); }
+constexpr int ws_rest(int ws) { return ((ws >> 4) & 15) != 0 ? ((ws >> 4) & 15) : (ws & 15); }
 constexpr int ws_at(int ws, int m) { return m == 0 ? ws_first(ws) : ws_rest(ws); }
-constexpr int ws_code(int first, int rest) { return first | rest << 4; }
+constexpr bool ws_real_ctrl(int ws) { return (ws & kRealCtrlBit) != 0; }
+constexpr int ws_code(int first, int rest, bool real_ctrl = false) {
+  return first | rest << 4 | (real_ctrl ? kRealCtrlBit : 0);
+}
 
 // predicted error (fraction of the substep) below which the jump-time Newton
 // iteration takes its last step without evaluating the norm again
@@ -193,7 +201,8 @@ struct Variant {
   int precision;  // TK_FP64 / TK_FP32
   int R, WS, NC, G;  // WS: static slots of row slot 0
   int WSB;           // static slots of row slots m >= 1 (WSB < WS: heaviest rows first)
-  int ws_code;       // the kernels' WS parameter (ws_first / ws_rest)
+  int ws_code;       // the kernels' WS parameter (ws_first / ws_rest / ws_real_ctrl)
+  bool real_ctrl;    // control elements must be real (two-FMA control slots)
   const void *k_forward;
   const void *k_backward;
   const void *k_krotov;
