@@ -361,6 +361,43 @@ def test_reordered_basis_shape_matches_uniform_shape(tk, monkeypatch, name, prec
         compare_records(rb, ra, t_tol)
 
 
+def test_complex_controls_take_a_uniform_shape(tk):
+    """Control operators with complex elements (the cascade's H_i conjugated by
+    random diagonal phases: Hermitian, complex off-diagonal elements) never get
+    a shape for real control elements: d = 81 runs the uniform shape, and two
+    Krotov iterations match the oracle at the FP64 bars (the first update of
+    this small draw is zero, the second is not)."""
+    w = config_workload("chain2_fock3", M=4, nt=40, T=10.0, lam=0.05)
+    rng = np.random.default_rng(5)
+    ph = sp.diags(np.exp(1j * rng.uniform(0.0, 2.0 * np.pi, w.dim)))
+    Hc = [sp.csr_matrix(ph @ H @ ph.conj().T) for H in w.H_ctrl]
+    assert max(float(np.abs(H.data.imag).max()) for H in Hc) > 0.1
+    w = w.replace(H_ctrl=Hc)
+    n_iter = 2
+    ref = okrotov.optimise(oracle_system(w), w.psi0, w.psi_tgt, w.u0, w.S, w.lam, w.T, w.M,
+                           w.seed, n_iter)
+    with tk.Context(precision="fp64") as ctx:
+        ctx.load(w)
+        variant = ctx.launch_info()["variant"]
+        J, rec, n = ctx.krotov_iterate(w.M, w.seed, n_iter)
+        u = ctx.get_pulses()
+    # oracle records with the norm's decay rate at each crossing
+    runs = [(0, ref.passes[0].records)]
+    for it in range(1, n_iter + 1):
+        runs += [(it, ref.backward_records[it - 1]), (it, ref.passes[it].records)]
+    pairs = sorted((((it, r.direction, r.traj, r.ordinal, r.step, r.op, r.t), r.rate)
+                    for it, recs in runs for r in recs), key=lambda q: q[0])
+    ref_rec = [q[0] for q in pairs]
+    say("complex controls: variant", variant, "J gpu", J.tolist(), "oracle", list(ref.J_T),
+        "records", n, len(ref_rec), "max |du|", float(np.abs(ref.u[-1] - ref.u[0]).max()))
+    assert variant == "fp64 R=2 WS=4 NC=2"
+    assert max_abs(J, ref.J_T) <= 1e-10
+    assert max_abs(u, ref.u[-1]) <= 1e-10
+    assert np.abs(ref.u[-1] - ref.u[0]).max() > 1e-3
+    compare_records(gpu_records(rec), ref_rec, 1e-10 * w.T / w.nt,
+                    slow_crossing_allowance([q[1] for q in pairs], ref_rec, w.nt))
+
+
 # ---------------------------------------------------------------------------
 # FP64 at d = 1296 (eight-wave teams; substeps short enough for the LDS)
 # ---------------------------------------------------------------------------
