@@ -43,8 +43,8 @@ namespace {
   X(1, 2, 4, 2)              \
   X(2, 4, 6, 3)              \
   X(3, 4, 8, 4)              \
-  X(4, 2, ws_code(3, 1, true), 2)  \
-  X(5, 4, ws_code(5, 3, true), 3)
+  X(4, 2, ws_code(3, 1, true, 1), 2)  \
+  X(5, 4, ws_code(5, 3, true, 2), 3)
 
 // ---- plain passes ------------------------------------------------------------
 template <typename real, int R, int WS, int NC, int DIR>
@@ -408,8 +408,8 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_batch_krotov(BatchArg
 #define TK_BATCH_WIDE_SHAPES(X)  \
   X(6, 1, 4, 2, 2)               \
   X(7, 2, 6, 3, 2)               \
-  X(8, 2, ws_code(5, 2, true), 3, 2)   \
-  X(10, 3, ws_code(8, 4, true), 4, 8)
+  X(8, 2, ws_code(5, 2, true, 2), 3, 2)   \
+  X(10, 3, ws_code(8, 4, true, 4), 4, 8)
 
 // Term vectors of the block's team at the start of dynamic LDS, trailing
 // zero elements set.

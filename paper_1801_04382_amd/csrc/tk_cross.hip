@@ -401,14 +401,14 @@ const void *cross_kernel(int precision, int R, int WS, int NC, int G) {
     TK_CROSS(double, 2, 4, 2);
     TK_CROSS(double, 4, 6, 3);
     TK_CROSS(double, 4, 8, 4);
-    TK_CROSS(double, 2, ws_code(3, 1, true), 2);
+    TK_CROSS(double, 2, ws_code(3, 1, true, 1), 2);
   } else {
     TK_CROSS(float, 1, 4, 2);
     TK_CROSS(float, 2, 4, 2);
     TK_CROSS(float, 4, 6, 3);
     TK_CROSS(float, 4, 8, 4);
-    TK_CROSS(float, 2, ws_code(3, 1, true), 2);
-    TK_CROSS(float, 4, ws_code(5, 3, true), 3);
+    TK_CROSS(float, 2, ws_code(3, 1, true, 1), 2);
+    TK_CROSS(float, 4, ws_code(5, 3, true, 2), 3);
   }
 #undef TK_CROSS
   return nullptr;

@@ -203,14 +203,14 @@ const void *sparse_step_kernel(int precision, int R, int WS, int NC, int G) {
     TK_SPARSE(double, 2, 4, 2);
     TK_SPARSE(double, 4, 6, 3);
     TK_SPARSE(double, 4, 8, 4);
-    TK_SPARSE(double, 2, ws_code(3, 1, true), 2);
+    TK_SPARSE(double, 2, ws_code(3, 1, true, 1), 2);
   } else {
     TK_SPARSE(float, 1, 4, 2);
     TK_SPARSE(float, 2, 4, 2);
     TK_SPARSE(float, 4, 6, 3);
     TK_SPARSE(float, 4, 8, 4);
-    TK_SPARSE(float, 2, ws_code(3, 1, true), 2);
-    TK_SPARSE(float, 4, ws_code(5, 3, true), 3);
+    TK_SPARSE(float, 2, ws_code(3, 1, true, 1), 2);
+    TK_SPARSE(float, 4, ws_code(5, 3, true, 2), 3);
   }
 #undef TK_SPARSE
   return nullptr;

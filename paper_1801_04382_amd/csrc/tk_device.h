@@ -362,6 +362,24 @@ struct LaneOp {
   static constexpr int NCX = NC > 0 ? NC : 1;
   static constexpr int W0 = ws_first(WS);  // static slots of row slot 0 (the most)
   static constexpr bool RC = ws_real_ctrl(WS);  // real control elements
+  static constexpr bool TY = ws_typed(WS);       // typed static slots in row slot 0
+  static constexpr int WR = W0 - ws_imag(WS);    // (the real ones; the rest imaginary)
+  // y += v b for static slot s of row slot m: typed slots hold a real element
+  // (v.x) or an imaginary one (i v.y) and take two FMAs
+  __device__ __forceinline__ static void sfma(cx<real> &y, const cx<real> &v, const cx<real> &b,
+                                              int s, int m) {
+    if (TY && m == 0) {
+      if (s < WR) {
+        y.x = fma(v.x, b.x, y.x);
+        y.y = fma(v.x, b.y, y.y);
+      } else {
+        y.x = fma(-v.y, b.y, y.x);
+        y.y = fma(v.y, b.x, y.y);
+      }
+    } else {
+      cfma(y, v, b);
+    }
+  }
   // slot s of row slot m is used (unrolled loops fold this to a constant)
   static constexpr bool live(int s, int m) { return s < ws_at(WS, m); }
   int scol[W0][R];
@@ -478,7 +496,7 @@ struct LaneOp {
     for (int s = 0; s < W0; ++s)
 #pragma unroll
       for (int m = 0; m < R; ++m)
-        if (live(s, m)) cfma(y[m], sval[s][m], b[s][m]);
+        if (live(s, m)) sfma(y[m], sval[s][m], b[s][m], s, m);
     if constexpr (kHalves) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
@@ -619,7 +637,7 @@ __device__ __forceinline__ void gather_fma(const LaneOp<real, R, WS, NC, G> &op,
     for (int m = 0; m < R; ++m) {
       if (s < W0 && !Op::live(s, m)) continue;
       if (s < W0)
-        cfma(y[m], op.sval[s < W0 ? s : 0][m], b[s - S0][m]);
+        Op::sfma(y[m], op.sval[s < W0 ? s : 0][m], b[s - S0][m], s, m);
       else
         cfma_ctrl<Op::RC>(y[m], op.cv[s < W0 ? 0 : s - W0][m], b[s - S0][m]);
     }
@@ -1303,7 +1321,7 @@ __device__ __forceinline__ void first_term_parts(const LaneOp<real, R, WS, NC, G
   for (int s = 0; s < W0; ++s)
 #pragma unroll
     for (int m = 0; m < R; ++m)
-      if (Op::live(s, m)) cfma(ys[m], op.sval[s][m], b[s][m]);
+      if (Op::live(s, m)) Op::sfma(ys[m], op.sval[s][m], b[s][m], s, m);
 }
 
 template <typename real, int R, int WS, int NC, int G>

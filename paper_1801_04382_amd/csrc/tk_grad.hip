@@ -533,12 +533,12 @@ const void *grad_kernel(int precision, int R, int WS, int NC, int G) {  // WS: l
   TK_GRAD_CASE(float, 1, 4, 2, 2)
   TK_GRAD_CASE(float, 2, 6, 3, 2)
   TK_GRAD_CASE(float, 3, 9, 4, 8)
-  TK_GRAD_CASE(double, 2, ws_code(3, 1, true), 2, 1)
-  TK_GRAD_CASE(double, 2, ws_code(5, 2, true), 3, 2)
-  TK_GRAD_CASE(float, 2, ws_code(3, 1, true), 2, 1)
-  TK_GRAD_CASE(float, 4, ws_code(5, 3, true), 3, 1)
-  TK_GRAD_CASE(float, 2, ws_code(5, 2, true), 3, 2)
-  TK_GRAD_CASE(float, 3, ws_code(8, 4, true), 4, 8)
+  TK_GRAD_CASE(double, 2, ws_code(3, 1, true, 1), 2, 1)
+  TK_GRAD_CASE(double, 2, ws_code(5, 2, true, 2), 3, 2)
+  TK_GRAD_CASE(float, 2, ws_code(3, 1, true, 1), 2, 1)
+  TK_GRAD_CASE(float, 4, ws_code(5, 3, true, 2), 3, 1)
+  TK_GRAD_CASE(float, 2, ws_code(5, 2, true, 2), 3, 2)
+  TK_GRAD_CASE(float, 3, ws_code(8, 4, true, 4), 4, 8)
 #undef TK_GRAD_CASE
   return nullptr;
 }

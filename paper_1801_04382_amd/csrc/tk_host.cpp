@@ -238,10 +238,13 @@ bool hermitian(const Csr &h) {
 // c mod n_bank_groups), which keeps the gathers of one instruction from
 // colliding in the same banks.
 // Row slots m >= 1 use only the first W_rest of the W slots (shapes whose
-// basis order puts the rows with the most non-zeros in row slot 0).  Returns
-// false if a row has more non-zeros than its slots.
+// basis order puts the rows with the most non-zeros in row slot 0).  With
+// typed_real >= 0 (typed shapes), row slot 0's first typed_real slots take
+// only real elements and the others only imaginary ones.  Returns false if a
+// row has more non-zeros than its slots (of each type).
 bool pack_group(const Csr *a, int W, int W_rest, int first, int R, int lanes, int n_bank_groups,
-                int32_t dummy, std::vector<int32_t> &col, std::vector<double> &val) {
+                int32_t dummy, std::vector<int32_t> &col, std::vector<double> &val,
+                int typed_real = -1) {
   std::vector<std::vector<std::pair<int32_t, cd>>> left(static_cast<size_t>(R) * lanes);
   for (int m = 0; m < R; ++m)
     for (int lane = 0; lane < lanes; ++lane) {
@@ -259,17 +262,27 @@ bool pack_group(const Csr *a, int W, int W_rest, int first, int R, int lanes, in
         for (int lane = g0; lane < g0 + 16; ++lane) {
           auto &l = left[static_cast<size_t>(m) * lanes + lane];
           const size_t slot = (static_cast<size_t>(first + w) * R + m) * lanes + lane;
-          if (l.empty() || (m > 0 && w >= W_rest)) {
+          // the elements this slot may take (typed slots: real or imaginary ones)
+          auto fits = [&](const std::pair<int32_t, cd> &e) {
+            if (typed_real < 0 || m > 0) return true;
+            return w < typed_real ? e.second.imag() == 0.0 : e.second.real() == 0.0;
+          };
+          size_t best = l.size();
+          for (size_t q = 0; q < l.size(); ++q) {
+            if (!fits(l[q])) continue;
+            if (best == l.size()) {
+              best = q;
+              continue;
+            }
+            const int lb = load[l[best].first % n_bank_groups], lq = load[l[q].first % n_bank_groups];
+            if (lq < lb || (lq == lb && l[q].first < l[best].first)) best = q;
+          }
+          if (best == l.size() || (m > 0 && w >= W_rest)) {
             col[slot] = dummy;
             val[2 * slot] = val[2 * slot + 1] = 0.0;
             if (!dummy_used) load[dummy % n_bank_groups]++;
             dummy_used = true;
             continue;
-          }
-          size_t best = 0;
-          for (size_t q = 1; q < l.size(); ++q) {
-            const int lb = load[l[best].first % n_bank_groups], lq = load[l[q].first % n_bank_groups];
-            if (lq < lb || (lq == lb && l[q].first < l[best].first)) best = q;
           }
           col[slot] = l[best].first;
           val[2 * slot] = l[best].second.real();
@@ -286,7 +299,7 @@ bool pack_group(const Csr *a, int W, int W_rest, int first, int R, int lanes, in
 // Operators ops[g], each in W slots: layout [g][w][m][lane], `lanes` lanes
 // (64 G) per row slot m.
 bool pack(const std::vector<const Csr *> &ops, int W, int R, int lanes, int n_bank_groups,
-          Ell &out, int W_rest = -1) {
+          Ell &out, int W_rest = -1, int typed_real = -1) {
   const size_t n = ops.size() * static_cast<size_t>(W) * R * lanes;
   out.col.assign(n, 0);
   out.val.assign(2 * n, 0.0);
@@ -294,7 +307,7 @@ bool pack(const std::vector<const Csr *> &ops, int W, int R, int lanes, int n_ba
   bool ok = true;
   for (size_t g = 0; g < ops.size(); ++g)
     ok = pack_group(ops[g], W, W_rest < 0 ? W : W_rest, static_cast<int>(g) * W, R, lanes,
-                    n_bank_groups, dummy, out.col, out.val) &&
+                    n_bank_groups, dummy, out.col, out.val, typed_real) &&
          ok;
   return ok;
 }
@@ -1278,6 +1291,27 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
                    [&](int32_t x, int32_t y) { return cnt[x] > cnt[y]; });
   // the most static non-zeros of a row outside the first `lanes` rows of the order
   auto rest_width = [&](int64_t lanes) { return d > lanes ? cnt[order[lanes]] : 0; };
+  // typed shapes: the rows of row slot 0 (the first `lanes` of the order) hold
+  // at most n_re real and n_im imaginary off-diagonal elements, none complex
+  auto typed_fit = [&](int64_t lanes, int n_re, int n_im) {
+    for (int64_t q = 0; q < std::min<int64_t>(lanes, d); ++q) {
+      const int64_t r = order[static_cast<size_t>(q)];
+      for (const Csr *m : {&Aoff0, &Adoff0}) {
+        int re = 0, im = 0;
+        for (int64_t p = m->ptr[r]; p < m->ptr[r + 1]; ++p) {
+          const cd v = m->val[p];
+          if (v.imag() == 0.0)
+            ++re;
+          else if (v.real() == 0.0)
+            ++im;
+          else
+            return false;
+        }
+        if (re > n_re || im > n_im) return false;
+      }
+    }
+    return true;
+  };
   int wc = 1;
   for (int i = 0; i < n_ctrl; ++i) wc = std::max({wc, hc[i].max_row(), hcd[i].max_row()});
   int wl = 1, wld = 1;
@@ -1309,7 +1343,8 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
     const tk::Variant &v = vs[k];
     if (v.precision != c->precision || static_cast<int64_t>(v.R) * tk::kWave * v.G < d ||
         v.WS < ws || v.NC < nc || (v.R > 1 && v.WSB < rest_width(int64_t{tk::kWave} * v.G)) ||
-        (v.real_ctrl && !ctrl_real))
+        (v.real_ctrl && !ctrl_real) ||
+        (v.typed_imag >= 0 && !typed_fit(int64_t{tk::kWave} * v.G, v.WS - v.typed_imag, v.typed_imag)))
       continue;
     if (want && *want) {
       if (std::strcmp(want, v.name) == 0) best = &v;
@@ -1369,9 +1404,12 @@ int tk_set_system(tk_ctx *c, int64_t d, const tk_csr *H0, int32_t n_ctrl, const 
     // static parts in device order: off-diagonal slots and the diagonal
     std::vector<cd> dg, ddg;
     const Csr Aoff = off_diagonal(A, dg), Adoff = off_diagonal(Ad, ddg);
-    if (!pack({&Aoff}, best->WS, R, lanes, nbg, e, best->WSB)) return fail(c, TK_EINVAL, packing);
+    const int typed_real = best->typed_imag >= 0 ? best->WS - best->typed_imag : -1;
+    if (!pack({&Aoff}, best->WS, R, lanes, nbg, e, best->WSB, typed_real))
+      return fail(c, TK_EINVAL, packing);
     if ((rc = upload_ell(c, e, c->f_scol, c->f_sval))) return rc;
-    if (!pack({&Adoff}, best->WS, R, lanes, nbg, e, best->WSB)) return fail(c, TK_EINVAL, packing);
+    if (!pack({&Adoff}, best->WS, R, lanes, nbg, e, best->WSB, typed_real))
+      return fail(c, TK_EINVAL, packing);
     if ((rc = upload_ell(c, e, c->b_scol, c->b_sval))) return rc;
     std::vector<double> v(2 * static_cast<size_t>(R) * lanes, 0.0);
     for (int64_t q = 0; q < d; ++q) {

@@ -31,12 +31,20 @@ constexpr int kGradCheckpoint = 64;   // steps between forward checkpoints (grad
 // with two FMAs instead of four (the host picks them only when every H_i
 // element is real).
 constexpr int kRealCtrlBit = 1 << 8;
+// Bit 13 marks shapes whose row slot 0 static slots are typed: the first
+// ones hold real elements, the last ws_imag (bits 9..12) imaginary ones, each
+// multiplied with two FMAs (the host picks them only when the rows of row
+// slot 0 fit those counts).
+constexpr int kTypedBit = 1 << 13;
 constexpr int ws_first(int ws) { return ws & 15; }
 constexpr int ws_rest(int ws) { return ((ws >> 4) & 15) != 0 ? ((ws >> 4) & 15) : (ws & 15); }
 constexpr int ws_at(int ws, int m) { return m == 0 ? ws_first(ws) : ws_rest(ws); }
 constexpr bool ws_real_ctrl(int ws) { return (ws & kRealCtrlBit) != 0; }
-constexpr int ws_code(int first, int rest, bool real_ctrl = false) {
-  return first | rest << 4 | (real_ctrl ? kRealCtrlBit : 0);
+constexpr bool ws_typed(int ws) { return (ws & kTypedBit) != 0; }
+constexpr int ws_imag(int ws) { return (ws >> 9) & 15; }
+constexpr int ws_code(int first, int rest, bool real_ctrl = false, int typed_imag = -1) {
+  return first | rest << 4 | (real_ctrl ? kRealCtrlBit : 0) |
+         (typed_imag >= 0 ? (kTypedBit | typed_imag << 9) : 0);
 }
 
 // predicted error (fraction of the substep) below which the jump-time Newton
@@ -203,6 +211,7 @@ struct Variant {
   int WSB;           // static slots of row slots m >= 1 (WSB < WS: heaviest rows first)
   int ws_code;       // the kernels' WS parameter (ws_first / ws_rest / ws_real_ctrl)
   bool real_ctrl;    // control elements must be real (two-FMA control slots)
+  int typed_imag;    // typed row slot 0: its imaginary slots (-1: untyped)
   const void *k_forward;
   const void *k_backward;
   const void *k_krotov;

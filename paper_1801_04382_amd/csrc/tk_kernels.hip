@@ -351,6 +351,7 @@ Variant make_variant(const char *name) {
   v.WSB = ws_rest(WS);
   v.ws_code = WS;
   v.real_ctrl = ws_real_ctrl(WS);
+  v.typed_imag = ws_typed(WS) ? ws_imag(WS) : -1;
   v.NC = NC;
   v.G = G;
   v.k_forward = reinterpret_cast<const void *>(&k_pass<real, R, WS, NC, G, 0>);
@@ -380,16 +381,16 @@ const Variant *variants(int *count) {
       make_variant<float, 2, 6, 3, 2>("fp32 R=2 WS=6 NC=3 G=2"),
       make_variant<float, 3, 9, 4, 8>("fp32 R=3 WS=9 NC=4 G=8"),
       // heaviest rows in row slot 0, fewer static slots in the others
-      make_variant<double, 2, ws_code(3, 1, true), 2, 1>("fp64 R=2 WS=3/1 NC=2"),
-      make_variant<double, 2, ws_code(5, 2, true), 3, 2>("fp64 R=2 WS=5/2 NC=3 G=2"),
-      make_variant<float, 2, ws_code(3, 1, true), 2, 1>("fp32 R=2 WS=3/1 NC=2"),
-      make_variant<float, 4, ws_code(5, 3, true), 3, 1>("fp32 R=4 WS=5/3 NC=3"),
-      make_variant<float, 2, ws_code(5, 2, true), 3, 2>("fp32 R=2 WS=5/2 NC=3 G=2"),
-      make_variant<float, 3, ws_code(8, 4, true), 4, 8>("fp32 R=3 WS=8/4 NC=4 G=8"),
+      make_variant<double, 2, ws_code(3, 1, true, 1), 2, 1>("fp64 R=2 WS=3/1 NC=2"),
+      make_variant<double, 2, ws_code(5, 2, true, 2), 3, 2>("fp64 R=2 WS=5/2 NC=3 G=2"),
+      make_variant<float, 2, ws_code(3, 1, true, 1), 2, 1>("fp32 R=2 WS=3/1 NC=2"),
+      make_variant<float, 4, ws_code(5, 3, true, 2), 3, 1>("fp32 R=4 WS=5/3 NC=3"),
+      make_variant<float, 2, ws_code(5, 2, true, 2), 3, 2>("fp32 R=2 WS=5/2 NC=3 G=2"),
+      make_variant<float, 3, ws_code(8, 4, true, 4), 4, 8>("fp32 R=3 WS=8/4 NC=4 G=8"),
       // d = 1296 in FP64: one team's LDS holds five FP64 term vectors, so its
       // steps take substeps short enough for four-term series (several
       // times the work of the FP32 shape; it serves accuracy checks)
-      make_variant<double, 3, ws_code(8, 4, true), 4, 8>("fp64 R=3 WS=8/4 NC=4 G=8"),
+      make_variant<double, 3, ws_code(8, 4, true, 4), 4, 8>("fp64 R=3 WS=8/4 NC=4 G=8"),
   };
   *count = static_cast<int>(sizeof(table) / sizeof(table[0]));
   return table;
