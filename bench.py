@@ -32,7 +32,7 @@ PEAK = {"fp64": 78.6, "fp32": 157.3}  # published MI355X vector peaks, TFLOP/s
 # sources and flags); any other build reports null.
 TRAFFIC = {
     ("krotov", "chain2_fock3", "fp64", 1024, 2000): {
-        "build": "f84d42e53d2896f4", "fetch_kib": 1422628, "write_kib": 17370,
+        "build": "7a921e83ca1c4ad7", "fetch_kib": 1425443, "write_kib": 17370,
         "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
